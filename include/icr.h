@@ -1,0 +1,231 @@
+/*
+ * icr.h -- C ABI of the MI355X constraint-matrix library.
+ *
+ * Implements the hot path of the implicit contact/friction scheme of
+ * Zeng & Courtecuisse, "An efficient implicit constraint resolution scheme for
+ * interactive FE simulations" (arXiv 2306.06946):
+ *   per time step        W_H = H A^{-1} H^T         (Eq. 28, Algorithm 3)
+ *   per Newton iteration W = C W_H C^T, projected Gauss-Seidel for lambda,
+ *                        p_k = p_free + h^2 W_H C_k^T lambda_k  (Eq. 31)
+ * for the backward-Euler system A = M + h B + h^2 K (Eq. 5) of a linear
+ * tetrahedral mesh, with A factored once by a supernodal Cholesky on the GPU.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns an icr_status; no exception crosses the ABI.  On an
+ *     error, icr_last_error() holds a message until the next call on that
+ *     scene.  A scene is not thread-safe: one host thread at a time.
+ *   - "host" pointers are read during the call and copied; "device" pointers
+ *     are caller-owned GPU buffers (e.g. torch tensors) that the library never
+ *     frees.  Library-owned device memory (mesh, factor, work arenas, state)
+ *     lives until icr_destroy.
+ *   - Device work is enqueued on the scene's stream (icr_create).  Calls that
+ *     return host values (sweeps, eps, reports) synchronise that stream.
+ *   - Arrays are row-major, float64 unless stated; node ids are int32,
+ *     DOF index = 3 * node + axis.  A contact is a mesh node (nodal mapping H:
+ *     the three DOFs of that node, Eq. 6) with a frame of three rows
+ *     (normal, tangent 1, tangent 2; Eq. 26) and three force components.
+ */
+#ifndef ICR_H
+#define ICR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct icr_scene icr_scene;
+
+typedef enum {
+  ICR_OK = 0,
+  ICR_WARN_NOT_CONVERGED = 1, /* PGS hit max_sweeps with eps > tol; results valid */
+  ICR_E_ARG = -1,             /* invalid argument (message says which) */
+  ICR_E_NOT_SPD = -2,         /* Cholesky met a non-positive pivot (column in message) */
+  ICR_E_OOM = -3,             /* device allocation failed */
+  ICR_E_HIP = -4,             /* HIP runtime error (message has the HIP error string) */
+  ICR_E_STATE = -5            /* call order violated (e.g. build_WH before factor) */
+} icr_status;
+
+/* Contact status codes written by icr_solve_contacts / icr_step. */
+enum { ICR_SEPARATE = 0, ICR_STICK = 1, ICR_SLIP = 2 };
+
+/* Create a scene bound to a HIP stream (hipStream_t passed as void*; NULL =
+ * the null stream) on the current device.  *out is NULL on failure. */
+icr_status icr_create(icr_scene **out, void *stream);
+
+/* Free every library-owned buffer.  Safe on NULL. */
+void icr_destroy(icr_scene *s);
+
+/* Last error message of this scene ("" if none); valid until the next call. */
+const char *icr_last_error(const icr_scene *s);
+
+/* Rebind the scene to another stream (e.g. torch's current stream). */
+icr_status icr_set_stream(icr_scene *s, void *stream);
+
+/*
+ * Assemble the linear-elastic FE model (Sec. "Implicit time integration",
+ * Eq. 4-5): per tetrahedron K_e = V B^T D B (isotropic D from E, nu), lumped
+ * mass rho V / 4 per node, Rayleigh damping B = alpha M + beta K, and
+ * A = M + h B + h^2 K.  DOFs of nodes with fixed[i] != 0 are clamped
+ * (identity rows/columns of A, zero right-hand side).
+ *   nodes [N*3] host, rest positions (also the initial state q, v = 0)
+ *   tets  [T*4] host int32, positively oriented
+ *   E, nu [T]   host, per element
+ *   gravity[3] host; fixed [N] host uint8
+ * Errors: ICR_E_ARG on bad sizes/ids, a non-positive volume, E <= 0 or
+ * nu outside (0, 0.5).  Replaces any previous mesh (and drops the factor).
+ */
+icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int32_t *tets, int32_t T,
+                        const double *E, const double *nu, double rho, double alpha, double beta, double h,
+                        const double *gravity, const uint8_t *fixed);
+
+/*
+ * Factor A = P^T L L^T P: nested-dissection ordering and supernodal symbolic
+ * analysis on the host, numeric supernodal FP64 Cholesky on the device (the
+ * factor the multi-RHS solves of W_H run against, Eq. 28).  Synchronises.
+ * ICR_E_NOT_SPD names the first failing permuted column.
+ */
+icr_status icr_factor(icr_scene *s);
+
+typedef struct {
+  int64_t n;             /* DOFs */
+  int64_t n_supernodes;
+  int64_t n_levels;      /* height levels of the supernodal tree */
+  int64_t nnz_L;         /* stored entries of the supernodal panels (lower, incl. zeros) */
+  int64_t max_front;     /* largest front order (DOFs) */
+  double factor_flops;   /* dense flops of the numeric factor (partial Choleskys) */
+  double factor_ms;      /* device time of the numeric factor */
+  int64_t device_bytes;  /* library-owned device memory */
+} icr_factor_info;
+
+icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out);
+
+/*
+ * Mapping compliance W_H = H A^{-1} H^T (Eq. 28) for n_c nodal contacts.
+ * Computed as W_H = Z^T Z with Z = L^{-1} P H^T: a sparse-RHS supernodal
+ * forward solve (each contact's three columns live only on the path from its
+ * node's supernode to the root) followed by per-supernode SYRK updates.  The
+ * result is exactly symmetric.
+ *   node_ids [n_c] device int32, distinct, not clamped
+ *   WH       [m*m] device, m = 3 n_c, row-major; row 3c+a = contact c, axis a
+ * Errors: ICR_E_STATE before icr_factor; ICR_E_ARG if n_c < 1 or n_c exceeds
+ * the limit set by the mesh.  Ids are validated on the device; an invalid id
+ * makes the call return ICR_E_ARG (this synchronises the stream).
+ */
+icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, double *WH);
+
+/*
+ * Fast update of the compliance matrix (Eq. 28, Algorithm 3 step 2):
+ * W_ab = C_a (W_H)_ab C_b^T for all 3x3 blocks.
+ *   WH [m*m] device; C [n_c*9] device, row-major 3x3 per contact (rows
+ *   normal, t1, t2); W [m*m] device output (may not alias WH).
+ */
+icr_status icr_update_W(icr_scene *s, int32_t n_c, const double *WH, const double *C, double *W);
+
+/*
+ * Projected Gauss-Seidel on delta = d + h^2 W lambda with Signorini (Eq. 8)
+ * and the Coulomb cone |lambda_t| <= mu lambda_n (Eq. 9), sweeping contacts in
+ * index order (Eq. 19, Algorithm 1).  Per contact: separate if its gap
+ * d_n >= 0; else the stick trial lambda = -(h^2 W_aa)^{-1} d if inside the
+ * cone; else slip on the cone boundary (delta_n = 0, lambda_t opposite to the
+ * tangential gap) by j_inner passes of a shifted fixed point.  After every
+ * sweep eps = |lam_i - lam_{i-1}|_2 / |lam_i|_2; stop when eps <= tol or after
+ * max_sweeps sweeps.
+ *   W [m*m], d [m], mu [n_c] device; lambda [m] device in/out (warm start);
+ *   status [n_c] device int8 (branch of the last sweep)
+ *   sweeps_out, eps_out: host, may be NULL (then the call does not synchronise)
+ * Returns ICR_WARN_NOT_CONVERGED (when eps_out/sweeps_out are given and
+ * eps > tol).  ICR_E_ARG on n_c < 1, max_sweeps < 1, j_inner < 0, h <= 0.
+ */
+icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const double *d, const double *mu,
+                              double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
+                              int32_t j_inner, int32_t *sweeps_out, double *eps_out);
+
+/*
+ * Proximity update p = p_free + h^2 W_H f (Eq. 31 with the total force
+ * f = C_k^T lambda_k in world frame, one 3-vector per contact).
+ *   WH [m*m], p_free [m], f [m] device; p [m] device output.
+ */
+icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, const double *p_free,
+                                const double *f, double h, double *p);
+
+/* Kinematic rigid obstacle (stand-in for collision detection, Sec. "Contact
+ * generation"): a sphere (kind 1, centre c(t) = c0 + vel t, radius) or a plane
+ * (kind 0, point c(t), unit normal pointing towards the body). */
+typedef struct {
+  int32_t kind;
+  double c0[3];
+  double vel[3];
+  double normal[3];
+  double radius;
+} icr_obstacle;
+
+/* Contact candidates (surface nodes) and their friction coefficients, host
+ * arrays, copied.  Candidates must be distinct and not clamped. */
+icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu);
+
+typedef struct {
+  int32_t n_contacts;   /* contacts kept per step (closest candidates) */
+  int32_t n_newton;     /* Newton iterations (Algorithm 3) */
+  int32_t max_sweeps;   /* PGS sweeps per Newton iteration */
+  int32_t j_inner;      /* slip fixed-point passes */
+  double tol;           /* PGS stopping tolerance */
+  int32_t timing;       /* 1: record per-phase device times in the report */
+} icr_step_opts;
+
+typedef struct {
+  double t;                 /* simulation time at the end of the step */
+  double ms_total;          /* device time of the whole step (timing = 1) */
+  double ms_free;           /* free motion: right-hand side + solve (Eq. 5, 12) */
+  double ms_contacts;       /* signed distances + selection + mapping */
+  double ms_build_WH;       /* W_H = H A^-1 H^T (Eq. 28) */
+  double ms_newton;         /* all Newton iterations (directions, update_W, PGS, GEMV) */
+  double ms_update_W;       /* sum over Newton iterations */
+  double ms_pgs;            /* sum over Newton iterations */
+  double ms_correct;        /* corrective solve + integration (Eq. 20) */
+  int32_t sweeps[16];       /* PGS sweeps per Newton iteration (first 16) */
+  double eps[16];           /* final eps per Newton iteration (first 16) */
+  int32_t n_separate, n_stick, n_slip;   /* status counts after the last iteration */
+} icr_step_report;
+
+/*
+ * One time step of the fast scheme (Algorithm 1 with Algorithm 3 inside):
+ * free motion; contacts = the n_contacts candidates with the smallest signed
+ * distance at q_free (ties by node id), ordered by node id; W_H; n_newton
+ * iterations of {frames and gaps at p_{k-1}, W_k = C_k W_H C_k^T, PGS warm
+ * started from the rotated previous force, p_k = p_free + h^2 W_H C_k^T
+ * lambda_k}; corrective motion dv = dv_free + h A^-1 H^T f; v += dv;
+ * q += h v.  rep (host, may be NULL) is filled after a synchronisation.
+ */
+icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep);
+
+/* Scene state, device buffers of n = 3N doubles (read / overwrite). */
+icr_status icr_get_state(icr_scene *s, double *q, double *v, double *t_out);
+icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double t);
+
+/*
+ * Results of the last icr_step, device outputs (any may be NULL):
+ *   node_ids [n_c] int32, q_free [n], p [m] final proximity, lambda [m] in
+ *   the last frame, C [n_c*9], f [m] world force, status [n_c] int8, WH [m*m].
+ */
+icr_status icr_get_step_results(icr_scene *s, int32_t *node_ids, double *q_free, double *p, double *lambda,
+                                double *C, double *f, int8_t *status, double *WH);
+
+/*
+ * Host-side analysis only (no device needed): nested-dissection ordering and
+ * supernodal symbolic structure of the mesh graph, for inspection and tests.
+ *   perm [N] out: perm[new] = old node id.
+ *   sup  [nsup_cap*4] out: per supernode (postorder) {first permuted node,
+ *        node count, parent (-1 root), first descendant}.
+ *   rows [rows_cap] out: below-row permuted node ids, concatenated per
+ *        supernode in postorder; rows_ptr [nsup_cap+1] out.
+ *   *nsup_out, *nrows_out: sizes needed (arrays untouched if caps too small).
+ */
+icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int32_t T, int32_t *perm,
+                       int32_t *sup, int32_t nsup_cap, int32_t *rows_ptr, int32_t *rows, int32_t rows_cap,
+                       int32_t *nsup_out, int32_t *nrows_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICR_H */

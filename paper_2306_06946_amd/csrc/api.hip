@@ -1,0 +1,680 @@
+// C ABI entry points (include/icr.h): argument checks, host planning, and the
+// launch sequence of each call on the scene's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <numeric>
+
+#include "scene.hpp"
+
+using namespace icr;
+
+namespace {
+
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct StateError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct SpdError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+template <class F>
+icr_status guarded(icr_scene *s, F &&body) {
+  if (!s) return ICR_E_ARG;
+  s->err.clear();
+  try {
+    return body();
+  } catch (const ArgError &e) {
+    s->err = e.what();
+    return ICR_E_ARG;
+  } catch (const StateError &e) {
+    s->err = e.what();
+    return ICR_E_STATE;
+  } catch (const SpdError &e) {
+    s->err = e.what();
+    return ICR_E_NOT_SPD;
+  } catch (const HipError &e) {
+    s->err = e.what();
+    return (e.code == hipErrorOutOfMemory) ? ICR_E_OOM : ICR_E_HIP;
+  } catch (const std::bad_alloc &) {
+    s->err = "host allocation failed";
+    return ICR_E_OOM;
+  } catch (const std::exception &e) {
+    s->err = e.what();
+    return ICR_E_HIP;
+  }
+}
+
+#define REQUIRE(cond, msg) \
+  do {                     \
+    if (!(cond)) throw ArgError(msg); \
+  } while (0)
+
+void ensure_contact_buffers(icr_scene *s, int nc) {
+  auto &C = s->con;
+  if (nc <= C.nc_cap) return;
+  ICR_HIP(hipStreamSynchronize(s->stream));
+  C.arena.release();
+  const long m = 3L * nc;
+  C.d_nodes_c = C.arena.alloc<int>(nc);
+  C.d_mu = C.arena.alloc<double>(nc);
+  C.d_pfree = C.arena.alloc<double>(m);
+  C.d_pstart = C.arena.alloc<double>(m);
+  C.d_p = C.arena.alloc<double>(m);
+  C.d_C = C.arena.alloc<double>(9L * nc);
+  C.d_dk = C.arena.alloc<double>(m);
+  C.d_lam = C.arena.alloc<double>(m);
+  C.d_f = C.arena.alloc<double>(m);
+  C.d_WH = C.arena.alloc<double>(m * m);
+  C.d_W = C.arena.alloc<double>(m * m);
+  C.d_status = C.arena.alloc<int8_t>(nc);
+  C.d_sweeps = C.arena.alloc<int>(64);
+  C.d_eps = C.arena.alloc<double>(64);
+  C.nc_cap = nc;
+}
+
+// Host-side build of the factor descriptors from the symbolic structure.
+void prepare_factor(icr_scene *s) {
+  auto &m = s->mesh;
+  auto &F = s->fac;
+  const auto &g = m.graph;
+  analyze(m.nodes.data(), g, 48, F.sym);
+  std::string bad = check_symbolic(g, F.sym);
+  if (!bad.empty()) throw std::runtime_error("symbolic analysis: " + bad);
+  const Symbolic &sym = F.sym;
+  const int ns = sym.nsup;
+  F.sup.assign(ns, SupDev{});
+  long long fo = 0, lo = 0, xo = 0;
+  F.nnzL = 0;
+  F.flops = 0;
+  F.max_front = 0;
+  for (int s_ = 0; s_ < ns; ++s_) {
+    SupDev &d = F.sup[s_];
+    d.col0 = sym.col0[s_];
+    d.ncol = sym.ncol[s_];
+    d.nb = sym.rows_ptr[s_ + 1] - sym.rows_ptr[s_];
+    d.parent = sym.parent[s_];
+    d.rows_off = sym.rows_ptr[s_];
+    d.first_desc = sym.first_desc[s_];
+    d.child_off = sym.child_ptr[s_];
+    d.nchild = sym.child_ptr[s_ + 1] - sym.child_ptr[s_];
+    d.region_nodes = sym.col0[s_] + sym.ncol[s_] - sym.col0[sym.first_desc[s_]];
+    const long long f = 3LL * (d.ncol + d.nb), n3 = 3LL * d.ncol;
+    d.front_off = fo;
+    d.linv_off = lo;
+    d.x1_off = xo;
+    fo += f * f;
+    lo += n3 * n3;
+    xo += f;
+    F.nnzL += n3 * (n3 + 1) / 2 + (f - n3) * n3;
+    for (long long c = 0; c < n3; ++c) F.flops += (double)(f - c) * (double)(f - c);
+    F.max_front = std::max<int>(F.max_front, (int)f);
+  }
+  F.front_elems = fo;
+  F.linv_elems = lo;
+  F.x1_elems = xo;
+  // child index maps (parent local node -> child below-row index, or -1)
+  std::vector<int> invmap_off(sym.child.size()), invmap;
+  for (int p = 0; p < ns; ++p) {
+    const SupDev &P = F.sup[p];
+    const int np = P.ncol + P.nb;
+    for (int e = sym.child_ptr[p]; e < sym.child_ptr[p + 1]; ++e) {
+      const int c = sym.child[e];
+      invmap_off[e] = (int)invmap.size();
+      invmap.resize(invmap.size() + np, -1);
+      int *inv = invmap.data() + invmap_off[e];
+      for (int i = sym.rows_ptr[c]; i < sym.rows_ptr[c + 1]; ++i) {
+        int r = sym.rows[i];
+        int L;
+        if (r >= P.col0 && r < P.col0 + P.ncol)
+          L = r - P.col0;
+        else {
+          auto it = std::lower_bound(sym.rows.begin() + sym.rows_ptr[p], sym.rows.begin() + sym.rows_ptr[p + 1], r);
+          L = P.ncol + (int)(it - (sym.rows.begin() + sym.rows_ptr[p]));
+        }
+        inv[L] = i - sym.rows_ptr[c];
+      }
+    }
+  }
+  // A -> front scatter entries, grouped by level
+  std::vector<std::vector<AScatter>> per_level(sym.nlevels);
+  std::vector<int> bsr_ptr(g.ptr.begin(), g.ptr.end());
+  for (int s_ = 0; s_ < ns; ++s_) {
+    const SupDev &S = F.sup[s_];
+    for (int p = S.col0; p < S.col0 + S.ncol; ++p) {
+      const int v = sym.perm[p];
+      for (int e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
+        const int u = g.adj[e];
+        const int q = sym.iperm[u];
+        if (q < p) continue;
+        int lr;
+        if (q < S.col0 + S.ncol)
+          lr = q - S.col0;
+        else {
+          auto it = std::lower_bound(sym.rows.begin() + S.rows_off, sym.rows.begin() + S.rows_off + S.nb, q);
+          if (it == sym.rows.begin() + S.rows_off + S.nb || *it != q)
+            throw std::runtime_error("A entry outside the supernodal structure");
+          lr = S.ncol + (int)(it - (sym.rows.begin() + S.rows_off));
+        }
+        // block (row u, col v) of the BSR matrix
+        auto jt = std::lower_bound(g.adj.begin() + g.ptr[u], g.adj.begin() + g.ptr[u + 1], v);
+        int blk = (int)(jt - g.adj.begin());
+        per_level[sym.height[s_]].push_back(AScatter{s_, lr, p - S.col0, blk});
+      }
+    }
+  }
+  std::vector<AScatter> ascat;
+  F.levels.assign(sym.nlevels, LevelInfo{});
+  for (int l = 0; l < sym.nlevels; ++l) {
+    LevelInfo &L = F.levels[l];
+    L.first = sym.level_ptr[l];
+    L.count = sym.level_ptr[l + 1] - sym.level_ptr[l];
+    L.a_first = (int)ascat.size();
+    L.a_count = (int)per_level[l].size();
+    ascat.insert(ascat.end(), per_level[l].begin(), per_level[l].end());
+    for (int q = L.first; q < L.first + L.count; ++q) {
+      const SupDev &S = F.sup[sym.level_sup[q]];
+      int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
+      L.max_n3 = std::max(L.max_n3, n3);
+      L.max_f3 = std::max(L.max_f3, f);
+      L.max_b3 = std::max(L.max_b3, b3);
+      L.max_f2 = std::max<long long>(L.max_f2, (long long)f * f);
+      L.max_rows_tiles = std::max(L.max_rows_tiles, cdiv(n3, TILE));
+      L.max_below_tiles = std::max(L.max_below_tiles, cdiv(b3, TILE));
+    }
+  }
+  std::vector<int> sup_of_node(m.N);
+  for (int s_ = 0; s_ < ns; ++s_)
+    for (int p = sym.col0[s_]; p < sym.col0[s_] + sym.ncol[s_]; ++p) sup_of_node[sym.perm[p]] = s_;
+
+  s->fac_arena.release();
+  F.rhs_arena.release();
+  F.nc_cap = 0;
+  hipStream_t st = s->stream;
+  auto &A = s->fac_arena;
+  F.d_sup = A.upload(F.sup, st);
+  F.d_rows = A.upload(sym.rows, st);
+  F.d_child = A.upload(sym.child, st);
+  F.d_invmap_off = A.upload(invmap_off, st);
+  F.d_invmap = A.upload(invmap, st);
+  F.d_level_sup = A.upload(sym.level_sup, st);
+  F.d_perm = A.upload(sym.perm, st);
+  F.d_iperm = A.upload(sym.iperm, st);
+  F.d_sup_of_node = A.upload(sup_of_node, st);
+  F.d_ascat = A.upload(ascat, st);
+  F.d_front = A.alloc<double>(F.front_elems);
+  F.d_linv = A.alloc<double>(F.linv_elems);
+  F.d_x1 = A.alloc<double>(F.x1_elems);
+  F.d_y = A.alloc<double>(2L * m.n);
+  F.d_err = A.alloc<int>(1);
+  ICR_HIP(hipStreamSynchronize(st));
+}
+
+void check_obstacle(const icr_obstacle *o) {
+  REQUIRE(o != nullptr, "obstacle is NULL");
+  REQUIRE(o->kind == 0 || o->kind == 1, "obstacle kind must be 0 (plane) or 1 (sphere)");
+  if (o->kind == 1) REQUIRE(std::isfinite(o->radius) && o->radius > 0, "sphere radius must be positive");
+  if (o->kind == 0) {
+    double n2 = o->normal[0] * o->normal[0] + o->normal[1] * o->normal[1] + o->normal[2] * o->normal[2];
+    REQUIRE(std::fabs(n2 - 1.0) < 1e-12, "plane normal must be a unit vector");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+icr_status icr_create(icr_scene **out, void *stream) {
+  if (!out) return ICR_E_ARG;
+  *out = nullptr;
+  icr_scene *s = new (std::nothrow) icr_scene();
+  if (!s) return ICR_E_OOM;
+  s->stream = (hipStream_t)stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return ICR_E_HIP;
+  }
+  *out = s;
+  return ICR_OK;
+}
+
+void icr_destroy(icr_scene *s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  s->con.arena.release();
+  s->fac.rhs_arena.release();
+  s->fac_arena.release();
+  s->mesh_arena.release();
+  s->state_arena.release();
+  delete s;
+}
+
+const char *icr_last_error(const icr_scene *s) { return s ? s->err.c_str() : "null scene"; }
+
+icr_status icr_set_stream(icr_scene *s, void *stream) {
+  return guarded(s, [&] {
+    s->stream = (hipStream_t)stream;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int32_t *tets, int32_t T,
+                        const double *E, const double *nu, double rho, double alpha, double beta, double h,
+                        const double *gravity, const uint8_t *fixed) {
+  return guarded(s, [&] {
+    REQUIRE(nodes && tets && E && nu && gravity && fixed, "NULL host array");
+    REQUIRE(N > 0 && T > 0, "N and T must be positive");
+    REQUIRE(N < (1 << 24), "at most 2^24 - 1 nodes");
+    REQUIRE(std::isfinite(h) && h > 0, "h must be positive and finite");
+    REQUIRE(rho > 0 && alpha >= 0 && beta >= 0, "rho > 0, alpha >= 0, beta >= 0 required");
+    for (long i = 0; i < 4L * T; ++i) REQUIRE(tets[i] >= 0 && tets[i] < N, "tet references a node out of range");
+    for (int t = 0; t < T; ++t) {
+      REQUIRE(std::isfinite(E[t]) && E[t] > 0, "E must be positive");
+      REQUIRE(nu[t] > 0 && nu[t] < 0.5, "nu must be in (0, 0.5)");
+    }
+    ICR_HIP(hipStreamSynchronize(s->stream));
+    s->assembled = s->factored = s->has_candidates = s->stepped = false;
+    s->con.arena.release();
+    s->con.nc_cap = 0;
+    s->fac.rhs_arena.release();
+    s->fac.nc_cap = 0;
+    s->fac_arena.release();
+    s->mesh_arena.release();
+    s->state_arena.release();
+    auto &m = s->mesh;
+    m.N = N;
+    m.T = T;
+    m.n = 3 * N;
+    m.rho = rho;
+    m.alpha = alpha;
+    m.beta = beta;
+    m.h = h;
+    for (int a = 0; a < 3; ++a) m.grav[a] = gravity[a];
+    m.nodes.assign(nodes, nodes + 3L * N);
+    m.tets.assign(tets, tets + 4L * T);
+    m.fixed.assign(fixed, fixed + N);
+    m.graph = build_graph(N, tets, T);
+    const auto &g = m.graph;
+    m.nnzb = g.ptr[N];
+    std::vector<int> bsr_row(m.nnzb);
+    for (int i = 0; i < N; ++i)
+      for (int e = g.ptr[i]; e < g.ptr[i + 1]; ++e) bsr_row[e] = i;
+    // element contributions per block, ascending element order
+    std::vector<int> cnt(m.nnzb + 1, 0), nt_cnt(N + 1, 0);
+    auto block_of = [&](int u, int v) {
+      auto it = std::lower_bound(g.adj.begin() + g.ptr[u], g.adj.begin() + g.ptr[u + 1], v);
+      return (int)(it - g.adj.begin());
+    };
+    for (int t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a) {
+        nt_cnt[tets[4 * t + a] + 1]++;
+        for (int b = 0; b < 4; ++b) cnt[block_of(tets[4 * t + a], tets[4 * t + b]) + 1]++;
+      }
+    for (int i = 0; i < m.nnzb; ++i) cnt[i + 1] += cnt[i];
+    for (int i = 0; i < N; ++i) nt_cnt[i + 1] += nt_cnt[i];
+    std::vector<int> contrib(cnt[m.nnzb]), fillp(cnt.begin(), cnt.end() - 1);
+    std::vector<int> nt(nt_cnt[N]), filln(nt_cnt.begin(), nt_cnt.end() - 1);
+    for (int t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a) {
+        nt[filln[tets[4 * t + a]]++] = t;
+        for (int b = 0; b < 4; ++b) contrib[fillp[block_of(tets[4 * t + a], tets[4 * t + b])]++] = t * 16 + a * 4 + b;
+      }
+    hipStream_t st = s->stream;
+    auto &A = s->mesh_arena;
+    m.d_nodes = A.upload(m.nodes, st);
+    m.d_tets = A.upload(m.tets, st);
+    m.d_E = A.upload(std::vector<double>(E, E + T), st);
+    m.d_nu = A.upload(std::vector<double>(nu, nu + T), st);
+    m.d_fixed = A.upload(m.fixed, st);
+    m.d_bsr_ptr = A.upload(g.ptr, st);
+    m.d_bsr_col = A.upload(g.adj, st);
+    m.d_bsr_row = A.upload(bsr_row, st);
+    m.d_contrib_ptr = A.upload(cnt, st);
+    m.d_contrib = A.upload(contrib, st);
+    m.d_nt_ptr = A.upload(nt_cnt, st);
+    m.d_nt = A.upload(nt, st);
+    m.d_Ke = A.alloc<double>(144L * T);
+    m.d_vol = A.alloc<double>(T);
+    m.d_mass = A.alloc<double>(N);
+    m.d_K = A.alloc<double>(9L * m.nnzb);
+    m.d_A = A.alloc<double>(9L * m.nnzb);
+    m.d_err = A.alloc<int>(1);
+    ICR_HIP(hipMemsetAsync(m.d_err, 0x7f, sizeof(int), st));
+    launch_element_matrices(s);
+    launch_assemble_blocks(s);
+    int bad = 0;
+    ICR_HIP(hipMemcpyAsync(&bad, m.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    ICR_HIP(hipStreamSynchronize(st));
+    if (bad != 0x7f7f7f7f) throw ArgError("tetrahedron " + std::to_string(bad) + " has non-positive volume");
+    // state
+    auto &S = s->st;
+    auto &B = s->state_arena;
+    S.d_q = B.upload(m.nodes, st);
+    S.d_qrest = B.upload(m.nodes, st);
+    S.d_v = B.alloc<double>(m.n);
+    ICR_HIP(hipMemsetAsync(S.d_v, 0, sizeof(double) * m.n, st));
+    S.d_b = B.alloc<double>(m.n);
+    S.d_dvfree = B.alloc<double>(m.n);
+    S.d_qfree = B.alloc<double>(m.n);
+    S.d_sol = B.alloc<double>(m.n);
+    S.d_node_force = B.alloc<double>(m.n);
+    ICR_HIP(hipMemsetAsync(S.d_node_force, 0, sizeof(double) * m.n, st));
+    S.d_prev_nodes = B.alloc<int>(N);
+    S.prev_nc = 0;
+    S.t = 0;
+    ICR_HIP(hipStreamSynchronize(st));
+    s->assembled = true;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_factor(icr_scene *s) {
+  return guarded(s, [&] {
+    if (!s->assembled) throw StateError("icr_factor before icr_assemble");
+    s->factored = false;
+    prepare_factor(s);
+    run_numeric_factor(s);
+    int bad = 0;
+    ICR_HIP(hipMemcpy(&bad, s->fac.d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (bad != 0x7f7f7f7f)
+      throw SpdError("non-positive pivot at permuted column " + std::to_string(bad));
+    s->factored = true;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out) {
+  return guarded(s, [&] {
+    REQUIRE(out, "NULL output");
+    if (!s->factored) throw StateError("no factor");
+    out->n = s->mesh.n;
+    out->n_supernodes = s->fac.sym.nsup;
+    out->n_levels = s->fac.sym.nlevels;
+    out->nnz_L = s->fac.nnzL;
+    out->max_front = s->fac.max_front;
+    out->factor_flops = s->fac.flops;
+    out->factor_ms = s->fac.ms;
+    out->device_bytes = (int64_t)(s->mesh_arena.bytes + s->fac_arena.bytes + s->fac.rhs_arena.bytes +
+                                  s->state_arena.bytes + s->con.arena.bytes);
+    return ICR_OK;
+  });
+}
+
+icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, double *WH) {
+  return guarded(s, [&] {
+    if (!s->factored) throw StateError("icr_build_WH before icr_factor");
+    REQUIRE(n_c >= 1 && n_c <= 8192, "n_c must be in [1, 8192]");
+    REQUIRE(n_c <= s->mesh.N, "more contacts than nodes");
+    REQUIRE(node_ids && WH, "NULL device pointer");
+    ensure_rhs_capacity(s, n_c);
+    build_WH_device(s, n_c, node_ids, WH, true);
+    int bad = 0;
+    ICR_HIP(hipMemcpyAsync(&bad, s->fac.d_cerr, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    ICR_HIP(hipStreamSynchronize(s->stream));
+    if (bad == 1) throw ArgError("a contact node id is out of range or clamped");
+    if (bad) throw ArgError("duplicate contact node ids");
+    return ICR_OK;
+  });
+}
+
+icr_status icr_update_W(icr_scene *s, int32_t n_c, const double *WH, const double *C, double *W) {
+  return guarded(s, [&] {
+    REQUIRE(n_c >= 1, "n_c must be >= 1");
+    REQUIRE(WH && C && W, "NULL device pointer");
+    REQUIRE(W != WH, "W may not alias WH");
+    launch_update_W(s->stream, n_c, WH, C, W);
+    return ICR_OK;
+  });
+}
+
+icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const double *d, const double *mu,
+                              double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
+                              int32_t j_inner, int32_t *sweeps_out, double *eps_out) {
+  return guarded(s, [&] {
+    REQUIRE(n_c >= 1 && n_c <= 2688, "n_c must be in [1, 2688]");
+    REQUIRE(max_sweeps >= 1, "max_sweeps must be >= 1");
+    REQUIRE(j_inner >= 0, "j_inner must be >= 0");
+    REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
+    REQUIRE(W && d && mu && lambda && status, "NULL device pointer");
+    ensure_contact_buffers(s, std::max(n_c, 1));
+    launch_pgs(s->stream, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, s->con.d_sweeps,
+               s->con.d_eps);
+    if (sweeps_out || eps_out) {
+      int sw = 0;
+      double ep = 0;
+      ICR_HIP(hipMemcpyAsync(&sw, s->con.d_sweeps, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+      ICR_HIP(hipMemcpyAsync(&ep, s->con.d_eps, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      ICR_HIP(hipStreamSynchronize(s->stream));
+      if (sweeps_out) *sweeps_out = sw;
+      if (eps_out) *eps_out = ep;
+      if (!(ep <= tol)) return ICR_WARN_NOT_CONVERGED;
+    }
+    return ICR_OK;
+  });
+}
+
+icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, const double *p_free, const double *f,
+                                double h, double *p) {
+  return guarded(s, [&] {
+    REQUIRE(n_c >= 1, "n_c must be >= 1");
+    REQUIRE(WH && p_free && f && p, "NULL device pointer");
+    launch_proximity(s->stream, n_c, WH, p_free, f, h, p);
+    return ICR_OK;
+  });
+}
+
+icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu) {
+  return guarded(s, [&] {
+    if (!s->assembled) throw StateError("icr_set_candidates before icr_assemble");
+    REQUIRE(count >= 1 && count <= 4096, "candidate count must be in [1, 4096]");
+    REQUIRE(nodes && mu, "NULL host array");
+    std::vector<double> mu_node(s->mesh.n / 3, 0.0);
+    std::vector<uint8_t> seen(s->mesh.N, 0);
+    for (int i = 0; i < count; ++i) {
+      int v = nodes[i];
+      REQUIRE(v >= 0 && v < s->mesh.N, "candidate node out of range");
+      REQUIRE(!s->mesh.fixed[v], "candidate node is clamped");
+      REQUIRE(!seen[v]++, "duplicate candidate node");
+      REQUIRE(std::isfinite(mu[i]) && mu[i] >= 0, "friction must be >= 0");
+      mu_node[v] = mu[i];
+    }
+    auto &C = s->con;
+    C.count = count;
+    C.nodes.assign(nodes, nodes + count);
+    auto &B = s->state_arena;
+    C.d_cand = B.upload(C.nodes, s->stream);
+    C.d_mu_node = B.upload(mu_node, s->stream);
+    ICR_HIP(hipStreamSynchronize(s->stream));
+    s->has_candidates = true;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep) {
+  return guarded(s, [&] {
+    if (!s->factored) throw StateError("icr_step before icr_factor");
+    if (!s->has_candidates) throw StateError("icr_step before icr_set_candidates");
+    check_obstacle(obs);
+    REQUIRE(opt, "NULL options");
+    const int nc = opt->n_contacts;
+    REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
+    REQUIRE(nc <= 2688, "n_contacts exceeds the PGS kernel limit (2688)");
+    REQUIRE(opt->n_newton >= 1 && opt->n_newton <= 64, "n_newton must be in [1, 64]");
+    REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
+    ensure_contact_buffers(s, nc);
+    ensure_rhs_capacity(s, nc);
+    hipStream_t st = s->stream;
+    auto &C = s->con;
+    auto &S = s->st;
+    const double h = s->mesh.h, t0 = S.t, t1 = S.t + h;
+    const bool timing = opt->timing != 0;
+    hipEvent_t ev[8];
+    if (timing)
+      for (auto &e : ev) ICR_HIP(hipEventCreate(&e));
+    std::vector<hipEvent_t> nev;
+    auto mark = [&](int i) {
+      if (timing) ICR_HIP(hipEventRecord(ev[i], st));
+    };
+    mark(0);
+    // free motion (Eq. 5, 12)
+    launch_free_rhs(s, S.d_q, S.d_v, S.d_b);
+    single_rhs_solve(s, S.d_b, S.d_dvfree);
+    launch_axpy_qfree(s);
+    mark(1);
+    launch_select_contacts(s, nc, *obs, t0, t1);
+    mark(2);
+    build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
+    mark(3);
+    const int m = 3 * nc;
+    std::vector<hipEvent_t> kev;
+    if (timing) {
+      kev.resize(3 * opt->n_newton);
+      for (auto &e : kev) ICR_HIP(hipEventCreate(&e));
+    }
+    for (int k = 0; k < opt->n_newton; ++k) {
+      launch_directions(s, nc, *obs, t0, t1, k == 0);
+      if (timing) ICR_HIP(hipEventRecord(kev[3 * k], st));
+      launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);
+      if (timing) ICR_HIP(hipEventRecord(kev[3 * k + 1], st));
+      launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
+                 C.d_sweeps + k, C.d_eps + k);
+      if (timing) ICR_HIP(hipEventRecord(kev[3 * k + 2], st));
+      launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
+      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
+    }
+    (void)m;
+    mark(4);
+    // corrective motion and integration (Eq. 20)
+    launch_corrective_rhs(s, nc);
+    single_rhs_solve(s, S.d_b, S.d_sol);
+    launch_integrate(s);
+    launch_store_forces(s, nc);
+    mark(5);
+    S.t = t1;
+    s->stepped = true;
+    s->last_nc = nc;
+    if (rep) {
+      std::memset(rep, 0, sizeof(*rep));
+      rep->t = S.t;
+      int nk = std::min(opt->n_newton, 16);
+      ICR_HIP(hipMemcpyAsync(rep->sweeps, C.d_sweeps, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
+      ICR_HIP(hipMemcpyAsync(rep->eps, C.d_eps, sizeof(double) * nk, hipMemcpyDeviceToHost, st));
+      std::vector<int8_t> stat(nc);
+      ICR_HIP(hipMemcpyAsync(stat.data(), C.d_status, nc, hipMemcpyDeviceToHost, st));
+      ICR_HIP(hipStreamSynchronize(st));
+      for (int8_t v : stat) {
+        if (v == ICR_SEPARATE) rep->n_separate++;
+        if (v == ICR_STICK) rep->n_stick++;
+        if (v == ICR_SLIP) rep->n_slip++;
+      }
+      if (timing) {
+        float ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[0], ev[5]));
+        rep->ms_total = ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        rep->ms_free = ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+        rep->ms_contacts = ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        rep->ms_build_WH = ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
+        rep->ms_newton = ms;
+        ICR_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+        rep->ms_correct = ms;
+        for (int k = 0; k < opt->n_newton; ++k) {
+          ICR_HIP(hipEventElapsedTime(&ms, kev[3 * k], kev[3 * k + 1]));
+          rep->ms_update_W += ms;
+          ICR_HIP(hipEventElapsedTime(&ms, kev[3 * k + 1], kev[3 * k + 2]));
+          rep->ms_pgs += ms;
+        }
+      }
+    }
+    if (timing) {
+      if (!rep) ICR_HIP(hipStreamSynchronize(st));
+      for (auto &e : ev) (void)hipEventDestroy(e);
+      for (auto &e : kev) (void)hipEventDestroy(e);
+    }
+    return ICR_OK;
+  });
+}
+
+icr_status icr_get_state(icr_scene *s, double *q, double *v, double *t_out) {
+  return guarded(s, [&] {
+    if (!s->assembled) throw StateError("no mesh");
+    const size_t bytes = sizeof(double) * s->mesh.n;
+    if (q) ICR_HIP(hipMemcpyAsync(q, s->st.d_q, bytes, hipMemcpyDeviceToDevice, s->stream));
+    if (v) ICR_HIP(hipMemcpyAsync(v, s->st.d_v, bytes, hipMemcpyDeviceToDevice, s->stream));
+    if (t_out) *t_out = s->st.t;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double t) {
+  return guarded(s, [&] {
+    if (!s->assembled) throw StateError("no mesh");
+    REQUIRE(q && v, "NULL device pointer");
+    const size_t bytes = sizeof(double) * s->mesh.n;
+    ICR_HIP(hipMemcpyAsync(s->st.d_q, q, bytes, hipMemcpyDeviceToDevice, s->stream));
+    ICR_HIP(hipMemcpyAsync(s->st.d_v, v, bytes, hipMemcpyDeviceToDevice, s->stream));
+    s->st.t = t;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_get_step_results(icr_scene *s, int32_t *node_ids, double *q_free, double *p, double *lambda,
+                                double *C, double *f, int8_t *status, double *WH) {
+  return guarded(s, [&] {
+    if (!s->stepped) throw StateError("no step has run");
+    const int nc = s->last_nc;
+    const size_t m = 3 * (size_t)nc;
+    hipStream_t st = s->stream;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+      if (dst) ICR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    };
+    cp(node_ids, s->con.d_nodes_c, sizeof(int) * nc);
+    cp(q_free, s->st.d_qfree, sizeof(double) * s->mesh.n);
+    cp(p, s->con.d_p, sizeof(double) * m);
+    cp(lambda, s->con.d_lam, sizeof(double) * m);
+    cp(C, s->con.d_C, sizeof(double) * 9 * nc);
+    cp(f, s->con.d_f, sizeof(double) * m);
+    cp(status, s->con.d_status, nc);
+    cp(WH, s->con.d_WH, sizeof(double) * m * m);
+    return ICR_OK;
+  });
+}
+
+icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int32_t T, int32_t *perm, int32_t *sup,
+                       int32_t nsup_cap, int32_t *rows_ptr, int32_t *rows, int32_t rows_cap, int32_t *nsup_out,
+                       int32_t *nrows_out) {
+  try {
+    if (!nodes || !tets || N <= 0 || T <= 0) return ICR_E_ARG;
+    for (long i = 0; i < 4L * T; ++i)
+      if (tets[i] < 0 || tets[i] >= N) return ICR_E_ARG;
+    MeshGraph g = build_graph(N, tets, T);
+    Symbolic sym;
+    analyze(nodes, g, 48, sym);
+    if (!check_symbolic(g, sym).empty()) return ICR_E_HIP;
+    if (nsup_out) *nsup_out = sym.nsup;
+    if (nrows_out) *nrows_out = (int32_t)sym.rows.size();
+    if (perm) std::copy(sym.perm.begin(), sym.perm.end(), perm);
+    if (sup && rows_ptr && rows && sym.nsup <= nsup_cap && (int)sym.rows.size() <= rows_cap) {
+      for (int s_ = 0; s_ < sym.nsup; ++s_) {
+        sup[4 * s_] = sym.col0[s_];
+        sup[4 * s_ + 1] = sym.ncol[s_];
+        sup[4 * s_ + 2] = sym.parent[s_];
+        sup[4 * s_ + 3] = sym.first_desc[s_];
+      }
+      std::copy(sym.rows_ptr.begin(), sym.rows_ptr.end(), rows_ptr);
+      std::copy(sym.rows.begin(), sym.rows.end(), rows);
+    }
+    return ICR_OK;
+  } catch (...) {
+    return ICR_E_HIP;
+  }
+}
+
+}  // extern "C"

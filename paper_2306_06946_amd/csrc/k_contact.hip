@@ -1,0 +1,451 @@
+// Contact side of the time step: selection of the contacts at the free motion
+// (stand-in for collision detection, Sec. "Contact generation"), frames and
+// gaps (Eq. 7, 10, 26), the fast compliance update W = C W_H C^T (Eq. 28),
+// projected Gauss-Seidel (Eq. 18-19, Algorithm 1), and the proximity update
+// p_k = p_free + h^2 W_H C_k^T lambda_k (Eq. 31).
+#include <algorithm>
+
+#include "scene.hpp"
+
+namespace icr {
+
+namespace {
+
+__device__ inline unsigned long long sortable(double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ double signed_distance(const icr_obstacle &o, double t, const double p[3], double nrm[3]) {
+#pragma clang fp contract(off)
+  double c[3] = {o.c0[0] + o.vel[0] * t, o.c0[1] + o.vel[1] * t, o.c0[2] + o.vel[2] * t};
+  double r0 = p[0] - c[0], r1 = p[1] - c[1], r2 = p[2] - c[2];
+  if (o.kind == 1) {
+    double dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    nrm[0] = r0 / dist;
+    nrm[1] = r1 / dist;
+    nrm[2] = r2 / dist;
+    return dist - o.radius;
+  }
+  nrm[0] = o.normal[0];
+  nrm[1] = o.normal[1];
+  nrm[2] = o.normal[2];
+  return r0 * o.normal[0] + r1 * o.normal[1] + r2 * o.normal[2];
+}
+
+// Keep the K candidates with smallest (distance, node id) at q_free, then order
+// them by node id; gather mu, p_free = H q_free, p_start = H q, warm start.
+__global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restrict__ cand,
+                                                 const double *__restrict__ qf, const double *__restrict__ q,
+                                                 icr_obstacle obs, double t1, int K,
+                                                 const double *__restrict__ mu_node,
+                                                 const double *__restrict__ node_force, int *__restrict__ nodes_c,
+                                                 double *__restrict__ mu_c, double *__restrict__ pfree,
+                                                 double *__restrict__ pstart, double *__restrict__ finit) {
+  __shared__ unsigned long long key[4096];
+  __shared__ int nid[4096];
+  int n2 = 1;
+  while (n2 < ncand) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    if (i < ncand) {
+      int v = cand[i];
+      double p[3] = {qf[3 * v], qf[3 * v + 1], qf[3 * v + 2]}, nrm[3];
+      key[i] = sortable(signed_distance(obs, t1, p, nrm));
+      nid[i] = v;
+    } else {
+      key[i] = ~0ull;
+      nid[i] = 0x7fffffff;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        int l = i ^ j;
+        if (l > i) {
+          unsigned long long a = key[i], b = key[l];
+          int na = nid[i], nb = nid[l];
+          bool gt = (a > b) || (a == b && na > nb);
+          bool up = ((i & k) == 0);
+          if (gt == up) {
+            key[i] = b;
+            key[l] = a;
+            nid[i] = nb;
+            nid[l] = na;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // order the first K by node id
+  int k2 = 1;
+  while (k2 < K) k2 <<= 1;
+  for (int i = K + threadIdx.x; i < k2; i += blockDim.x) nid[i] = 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= k2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < k2; i += blockDim.x) {
+        int l = i ^ j;
+        if (l > i) {
+          int a = nid[i], b = nid[l];
+          bool up = ((i & k) == 0);
+          if ((a > b) == up) {
+            nid[i] = b;
+            nid[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int c = threadIdx.x; c < K; c += blockDim.x) {
+    int v = nid[c];
+    nodes_c[c] = v;
+    mu_c[c] = mu_node[v];
+    for (int a = 0; a < 3; ++a) {
+      pfree[3 * c + a] = qf[3 * v + a];
+      pstart[3 * c + a] = q[3 * v + a];
+      finit[3 * c + a] = node_force[3 * v + a];
+    }
+  }
+}
+
+// Frames C_k and gaps at p_{k-1}; d_k = delta - C_k (p - p_free); warm start
+// lambda = C_k f with f the previous world-frame force.
+__global__ void k_directions(int nc, icr_obstacle obs, double t0, double t1, const double *__restrict__ p,
+                             const double *__restrict__ pfree, const double *__restrict__ pstart,
+                             const double *__restrict__ fprev, double *__restrict__ C, double *__restrict__ dk,
+                             double *__restrict__ lam) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
+  double n[3];
+  double phi = signed_distance(obs, t1, pc, n);
+  int ax = 0;
+  double am = fabs(n[0]);
+  if (fabs(n[1]) < am) {
+    ax = 1;
+    am = fabs(n[1]);
+  }
+  if (fabs(n[2]) < am) ax = 2;
+  double en = n[ax];
+  double ta[3] = {-en * n[0], -en * n[1], -en * n[2]};
+  ta[ax] += 1.0;
+  double tn = sqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
+  ta[0] /= tn;
+  ta[1] /= tn;
+  ta[2] /= tn;
+  double tb[3] = {n[1] * ta[2] - n[2] * ta[1], n[2] * ta[0] - n[0] * ta[2], n[0] * ta[1] - n[1] * ta[0]};
+  double rel[3];
+  for (int a = 0; a < 3; ++a) {
+    double uo = (obs.c0[a] + obs.vel[a] * t1) - (obs.c0[a] + obs.vel[a] * t0);
+    rel[a] = pc[a] - pstart[3 * c + a] - uo;
+  }
+  double F[3][3] = {{n[0], n[1], n[2]}, {ta[0], ta[1], ta[2]}, {tb[0], tb[1], tb[2]}};
+  double delta[3] = {phi, ta[0] * rel[0] + ta[1] * rel[1] + ta[2] * rel[2],
+                     tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2]};
+  double dp[3] = {pc[0] - pfree[3 * c], pc[1] - pfree[3 * c + 1], pc[2] - pfree[3 * c + 2]};
+  for (int r = 0; r < 3; ++r) {
+    for (int a = 0; a < 3; ++a) C[9 * c + 3 * r + a] = F[r][a];
+    dk[3 * c + r] = delta[r] - (F[r][0] * dp[0] + F[r][1] * dp[1] + F[r][2] * dp[2]);
+    lam[3 * c + r] = F[r][0] * fprev[3 * c] + F[r][1] * fprev[3 * c + 1] + F[r][2] * fprev[3 * c + 2];
+  }
+}
+
+// W_ab = C_a (W_H)_ab C_b^T.  Block (a, b) with a < b is computed as the
+// transpose of block (b, a) from the same inputs (W_H is exactly symmetric),
+// so W is exactly symmetric.
+__global__ void k_update_W(int nc, const double *__restrict__ WH, const double *__restrict__ C,
+                           double *__restrict__ W) {
+  long blk = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= (long)nc * nc) return;
+  const int a = (int)(blk / nc), b = (int)(blk % nc);
+  const long m = 3L * nc;
+  const bool lower = a >= b;
+  double M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = WH[(3L * a + i) * m + 3L * b + j];
+      if (lower)
+        M[i][j] = v;
+      else
+        M[j][i] = v;
+    }
+  const double *X = C + 9L * (lower ? a : b);
+  const double *Y = C + 9L * (lower ? b : a);
+  double T[3][3];   // M Y^T
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[i][j] = M[i][0] * Y[3 * j] + M[i][1] * Y[3 * j + 1] + M[i][2] * Y[3 * j + 2];
+  double R[3][3];   // X T
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R[i][j] = X[3 * i] * T[0][j] + X[3 * i + 1] * T[1][j] + X[3 * i + 2] * T[2][j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) W[(3L * a + i) * m + 3L * b + j] = lower ? R[i][j] : R[j][i];
+}
+
+// ---- local solver (Signorini + Coulomb cone) --------------------------------
+
+struct Local {
+  double l[3];
+  int st;
+};
+
+__device__ Local local_solve(const double w[3][3], const double d[3], double mu, int j_inner) {
+  Local out;
+  if (d[0] >= 0.0) {
+    out.l[0] = out.l[1] = out.l[2] = 0.0;
+    out.st = ICR_SEPARATE;
+    return out;
+  }
+  // stick trial: 3x3 Cholesky solve
+  double l00 = sqrt(w[0][0]);
+  double l10 = w[1][0] / l00, l20 = w[2][0] / l00;
+  double l11 = sqrt(w[1][1] - l10 * l10);
+  double l21 = (w[2][1] - l20 * l10) / l11;
+  double l22 = sqrt(w[2][2] - l20 * l20 - l21 * l21);
+  double y0 = d[0] / l00;
+  double y1 = (d[1] - l10 * y0) / l11;
+  double y2 = (d[2] - l20 * y0 - l21 * y1) / l22;
+  double x2 = y2 / l22;
+  double x1 = (y1 - l21 * x2) / l11;
+  double x0 = (y0 - l10 * x1 - l20 * x2) / l00;
+  double ln = -x0, lt1 = -x1, lt2 = -x2;
+  if (ln > 0.0 && lt1 * lt1 + lt2 * lt2 <= (mu * ln) * (mu * ln)) {
+    out.l[0] = ln;
+    out.l[1] = lt1;
+    out.l[2] = lt2;
+    out.st = ICR_STICK;
+    return out;
+  }
+  double u0, u1;
+  double nt = sqrt(lt1 * lt1 + lt2 * lt2);
+  if (nt > 0.0) {
+    u0 = lt1 / nt;
+    u1 = lt2 / nt;
+  } else {
+    double ndt = sqrt(d[1] * d[1] + d[2] * d[2]);
+    if (ndt > 0.0) {
+      u0 = -d[1] / ndt;
+      u1 = -d[2] / ndt;
+    } else {
+      u0 = 1.0;
+      u1 = 0.0;
+    }
+  }
+  const double kap = 0.5 * (w[1][1] + w[2][2]);
+  for (int it = 0; it < j_inner; ++it) {
+    double den = w[0][0] + mu * (w[0][1] * u0 + w[0][2] * u1);
+    if (den <= 0.0) den = w[0][0];
+    double lam_n = -d[0] / den;
+    double a1 = mu * lam_n * u0, a2 = mu * lam_n * u1;
+    double r1 = d[1] + w[1][0] * lam_n + (w[1][1] - kap) * a1 + w[1][2] * a2;
+    double r2 = d[2] + w[2][0] * lam_n + w[2][1] * a1 + (w[2][2] - kap) * a2;
+    double nr = sqrt(r1 * r1 + r2 * r2);
+    if (nr > 0.0) {
+      u0 = -r1 / nr;
+      u1 = -r2 / nr;
+    }
+  }
+  double den = w[0][0] + mu * (w[0][1] * u0 + w[0][2] * u1);
+  if (den <= 0.0) den = w[0][0];
+  double lam_n = -d[0] / den;
+  out.l[0] = lam_n;
+  out.l[1] = mu * lam_n * u0;
+  out.l[2] = mu * lam_n * u1;
+  out.st = ICR_SLIP;
+  return out;
+}
+
+// Deterministic block reduction of one double (1024 threads).
+__device__ double block_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;   // valid in thread 0
+}
+
+// Single-workgroup PGS.  g = d + W~ lambda (all contacts, own term included)
+// lives in LDS; per contact a: d_a = g_a - W~_aa lambda_a, local solve, then
+// g += W~[:, a] (lambda_new - lambda_old) read from rows of the symmetric W.
+__global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__restrict__ W,
+                                                     const double *__restrict__ d, const double *__restrict__ mu,
+                                                     double h2, double *__restrict__ lam, int8_t *__restrict__ status,
+                                                     int max_sweeps, double tol, int j_inner,
+                                                     int *__restrict__ sweeps_out, double *__restrict__ eps_out) {
+  __shared__ double g[8064];
+  __shared__ double bc[4];
+  __shared__ double red[16];
+  __shared__ int stop;
+  const int m = 3 * nc;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  // g = d + h2 * W lambda0 (one wave per row, lanes across columns)
+  for (int i = wv; i < m; i += 16) {
+    double s = 0.0;
+    for (int j = ln; j < m; j += 64) s = fma(W[(long)i * m + j], lam[j], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (ln == 0) g[i] = d[i] + h2 * s;
+  }
+  if (tid == 0) stop = 0;
+  __syncthreads();
+  double dsum = 0.0;   // thread 0: sum of squared changes in this sweep
+  int sweep = 0;
+  double eps = 0.0;
+  for (sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) dsum = 0.0;
+    for (int a = 0; a < nc; ++a) {
+      if (tid == 0) {
+        double w[3][3], lo[3], dd[3];
+        for (int i = 0; i < 3; ++i) {
+          lo[i] = lam[3 * a + i];
+          for (int j = 0; j < 3; ++j) w[i][j] = h2 * W[(3L * a + i) * m + 3L * a + j];
+        }
+        for (int i = 0; i < 3; ++i) dd[i] = g[3 * a + i] - (w[i][0] * lo[0] + w[i][1] * lo[1] + w[i][2] * lo[2]);
+        Local r = local_solve(w, dd, mu[a], j_inner);
+        for (int i = 0; i < 3; ++i) {
+          double dl = r.l[i] - lo[i];
+          bc[i] = dl;
+          dsum += dl * dl;
+          lam[3 * a + i] = r.l[i];
+        }
+        status[a] = (int8_t)r.st;
+      }
+      __syncthreads();
+      const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
+      if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+        const double *r0 = W + (3L * a) * m;
+        for (int i = tid; i < m; i += 1024)
+          g[i] += h2 * (r0[i] * d0 + r0[m + i] * d1 + r0[2L * m + i] * d2);
+      }
+      __syncthreads();
+    }
+    // eps = |lam_i - lam_{i-1}| / |lam_i|
+    double part = 0.0;
+    for (int i = tid; i < m; i += 1024) part += lam[i] * lam[i];
+    __threadfence_block();
+    double nl2 = block_sum(part, red);
+    if (tid == 0) {
+      double diff = sqrt(dsum), nl = sqrt(nl2);
+      eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
+      stop = (eps <= tol) ? 1 : 0;
+    }
+    __syncthreads();
+    if (stop) {
+      ++sweep;
+      break;
+    }
+  }
+  if (tid == 0) {
+    *sweeps_out = sweep;
+    *eps_out = eps;
+  }
+}
+
+__global__ void k_world_force(int nc, const double *__restrict__ C, const double *__restrict__ lam,
+                              double *__restrict__ f) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double *R = C + 9L * c;
+  for (int a = 0; a < 3; ++a)
+    f[3 * c + a] = R[a] * lam[3 * c] + R[3 + a] * lam[3 * c + 1] + R[6 + a] * lam[3 * c + 2];
+}
+
+// p = p_free + h^2 W_H f, one wave per row.
+__global__ __launch_bounds__(256) void k_proximity(int m, const double *__restrict__ WH,
+                                                   const double *__restrict__ pfree, const double *__restrict__ f,
+                                                   double h2, double *__restrict__ p) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ln = threadIdx.x & 63;
+  if (row >= m) return;
+  const double *Wr = WH + (long)row * m;
+  double s = 0.0;
+  for (int j = ln; j < m; j += 64) s = fma(Wr[j], f[j], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (ln == 0) p[row] = pfree[row] + h2 * s;
+}
+
+__global__ void k_zero(long n, double *__restrict__ x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = 0.0;
+}
+
+__global__ void k_scatter_force(int nc, const int *__restrict__ nodes, const double *__restrict__ f,
+                                double *__restrict__ out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int v = nodes[c];
+  for (int a = 0; a < 3; ++a) out[3 * v + a] = f[3 * c + a];
+}
+
+__global__ void k_clear_nodes(int nc, const int *__restrict__ nodes, double *__restrict__ out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int v = nodes[c];
+  for (int a = 0; a < 3; ++a) out[3 * v + a] = 0.0;
+}
+
+}  // namespace
+
+void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1) {
+  (void)t0;
+  auto &C = s->con;
+  k_select<<<1, 1024, 0, s->stream>>>(C.count, C.d_cand, s->st.d_qfree, s->st.d_q, obs, t1, nc, C.d_mu_node,
+                                      s->st.d_node_force, C.d_nodes_c, C.d_mu, C.d_pfree, C.d_pstart, C.d_f);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first) {
+  auto &C = s->con;
+  const double *p = first ? C.d_pfree : C.d_p;
+  k_directions<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, obs, t0, t1, p, C.d_pfree, C.d_pstart, C.d_f, C.d_C,
+                                                     C.d_dk, C.d_lam);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_update_W(hipStream_t st, int nc, const double *WH, const double *Cm, double *W) {
+  long nb = (long)nc * nc;
+  k_update_W<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nc, WH, Cm, W);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h, double *lam,
+                int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev) {
+  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev, eps_dev);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {
+  k_world_force<<<cdiv(nc, 128), 128, 0, st>>>(nc, Cm, lam, f);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
+                      double *p) {
+  const int m = 3 * nc;
+  k_proximity<<<cdiv(m, 4), 256, 0, st>>>(m, WH, p_free, f, h * h, p);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_corrective_rhs(icr_scene *s, int nc) {
+  const long n = s->mesh.n;
+  k_zero<<<cdiv(n, 256), 256, 0, s->stream>>>(n, s->st.d_b);
+  ICR_LAUNCH_CHECK();
+  k_scatter_force<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, s->st.d_b);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_store_forces(icr_scene *s, int nc) {
+  auto &S = s->st;
+  if (S.prev_nc > 0) {
+    k_clear_nodes<<<cdiv(S.prev_nc, 128), 128, 0, s->stream>>>(S.prev_nc, S.d_prev_nodes, S.d_node_force);
+    ICR_LAUNCH_CHECK();
+  }
+  k_scatter_force<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, S.d_node_force);
+  ICR_LAUNCH_CHECK();
+  ICR_HIP(hipMemcpyAsync(S.d_prev_nodes, s->con.d_nodes_c, sizeof(int) * nc, hipMemcpyDeviceToDevice, s->stream));
+  S.prev_nc = nc;
+}
+
+}  // namespace icr

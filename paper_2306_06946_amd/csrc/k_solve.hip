@@ -1,0 +1,460 @@
+// Solves against the supernodal factor P A P^T = L L^T.
+//
+// Multi-RHS (W_H = H A^-1 H^T, Eq. 28): with Z = L^{-1} P H^T,
+// W_H = Z^T Z.  Contacts are sorted by the postorder index of the supernode
+// holding their node, so the contacts below supernode s form one contiguous
+// range [lo_s, hi_s) and its RHS front X_s has 3 (hi_s - lo_s) columns.  Per
+// height level, bottom-up:
+//   X_s  = unit columns of its own contacts + children's updates (pulled)
+//   Z_s  = L_ss^{-1} X_s[:n_s]                   (triangular dense product)
+//   X_s[n_s:] -= L_21 Z_s                        (update passed to the parent)
+//   Wp[range_s, range_s] += Z_s^T Z_s            (lower tiles; ranges of one
+//                                                 level are disjoint)
+// then W_H is read out of Wp in contact order (exactly symmetric).
+//
+// Single RHS (free motion, corrective motion): the same forward sweep with one
+// dense column, then the backward sweep top-down
+//   x_s = L_ss^{-T} (y_s - L_21^T x[below rows of s]).
+#include <algorithm>
+
+#include "scene.hpp"
+
+namespace icr {
+
+namespace {
+
+// ---- contact ordering -------------------------------------------------------
+
+// Sort the contacts by (supernode, node, index) with a bitonic network on a
+// packed 64-bit key.  Invalid ids (out of range, clamped) get the key nsup,
+// outside every supernode range, and duplicates are flagged; both make the
+// call fail on the host.
+__global__ __launch_bounds__(1024) void k_sort_contacts(int nc, int N, int nsup, const int *__restrict__ node_ids,
+                                                        const int *__restrict__ sup_of_node,
+                                                        const uint8_t *__restrict__ fixed,
+                                                        int *__restrict__ keys_sorted, int *__restrict__ order,
+                                                        int *__restrict__ pos, int *__restrict__ cerr) {
+  __shared__ unsigned long long kv[8192];
+  int n2 = 1;
+  while (n2 < nc) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    unsigned long long v = ~0ull;
+    if (i < nc) {
+      int node = node_ids[i];
+      unsigned long long key = (unsigned long long)nsup, nd = 0;
+      if (node < 0 || node >= N || fixed[node]) {
+        atomicMax(cerr, 1);
+      } else {
+        key = (unsigned long long)sup_of_node[node];
+        nd = (unsigned long long)node;
+      }
+      v = (key << 37) | (nd << 13) | (unsigned long long)i;
+    }
+    kv[i] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        int l = i ^ j;
+        if (l > i) {
+          unsigned long long a = kv[i], b = kv[l];
+          bool up = ((i & k) == 0);
+          if ((a > b) == up) {
+            kv[i] = b;
+            kv[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int p = threadIdx.x; p < nc; p += blockDim.x) {
+    unsigned long long v = kv[p];
+    int c = (int)(v & 0x1fffull);
+    order[p] = c;
+    keys_sorted[p] = (int)(v >> 37);
+    pos[c] = p;
+    if (p > 0 && (kv[p - 1] >> 13) == (v >> 13) && (int)(v >> 37) < nsup) atomicMax(cerr, 2);
+  }
+}
+
+__device__ inline int lower_bound_i(const int *a, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_ranges(int nsup, int nc, const SupDev *__restrict__ sup, const int *__restrict__ keys,
+                         int *__restrict__ lohi) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsup) return;
+  int lo = lower_bound_i(keys, nc, sup[s].first_desc);
+  int own = lower_bound_i(keys, nc, s);
+  int hi = lower_bound_i(keys, nc, s + 1);
+  if (3 * (hi - lo) > sup[s].rmax) own = hi = lo;   // only reachable with duplicate ids (flagged)
+  lohi[3 * s + 0] = lo;
+  lohi[3 * s + 1] = own;
+  lohi[3 * s + 2] = hi;
+}
+
+// ---- multi-RHS forward ------------------------------------------------------
+
+__global__ void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                               const int *__restrict__ child, const int *__restrict__ invmap_off,
+                               const int *__restrict__ invmap, const int *__restrict__ lohi,
+                               const int *__restrict__ order, const int *__restrict__ node_ids,
+                               const int *__restrict__ iperm, double *__restrict__ X) {
+  const int s = level_sup[blockIdx.y];
+  const SupDev S = sup[s];
+  const int lo = lohi[3 * s], own = lohi[3 * s + 1], hi = lohi[3 * s + 2];
+  const int r = 3 * (hi - lo);
+  if (r == 0) return;
+  const int f = 3 * (S.ncol + S.nb);
+  const long total = (long)f * r;
+  double *Xs = X + S.x_off;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % f), jc = (int)(e / f);
+    const int p = lo + jc / 3, a = jc % 3;
+    double v = 0.0;
+    if (p >= own) {
+      int node = node_ids[order[p]];
+      int lr = 3 * (iperm[node] - S.col0) + a;
+      v = (i == lr) ? 1.0 : 0.0;
+    } else {
+      for (int c = 0; c < S.nchild; ++c) {
+        const int ch = child[S.child_off + c];
+        const int clo = lohi[3 * ch], chi = lohi[3 * ch + 2];
+        if (p >= clo && p < chi) {
+          const int ii = invmap[invmap_off[S.child_off + c] + i / 3];
+          if (ii >= 0) {
+            const SupDev C = sup[ch];
+            const int fc = 3 * (C.ncol + C.nb);
+            v = X[C.x_off + (long)(3 * C.ncol + 3 * ii + i % 3) + (long)(jc - 3 * (clo - lo)) * fc];
+          }
+          break;
+        }
+      }
+    }
+    Xs[e] = v;
+  }
+}
+
+// Z_s = L_ss^{-1} X_s[:n_s]; grid (row tile, col tile, supernode)
+__global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                  const int *__restrict__ lohi, const double *__restrict__ linv,
+                                                  const double *__restrict__ X, double *__restrict__ Z) {
+  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  const int s = level_sup[blockIdx.z];
+  const SupDev S = sup[s];
+  const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
+  const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
+  const int i0 = TILE * blockIdx.x, j0 = TILE * blockIdx.y;
+  if (i0 >= n3 || j0 >= r) return;
+  const int M = min(TILE, n3 - i0), N = min(TILE, r - j0);
+  const int kend = min(n3, i0 + TILE);
+  double acc[4][4];
+  tile_zero(acc);
+  tile_gemm_acc(acc, linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, sA, sB);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double *Zs = Z + S.z_off;
+  for (int ii = 0; ii < 4; ++ii)
+    for (int jj = 0; jj < 4; ++jj) {
+      int i = ty + 16 * ii, j = tx + 16 * jj;
+      if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = acc[ii][jj];
+    }
+}
+
+// X_s[n_s:] -= L_21 Z_s
+__global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                 const int *__restrict__ lohi, const double *__restrict__ front,
+                                                 const double *__restrict__ Z, double *__restrict__ X) {
+  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  const int s = level_sup[blockIdx.z];
+  const SupDev S = sup[s];
+  const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
+  const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
+  const int i0 = TILE * blockIdx.x, j0 = TILE * blockIdx.y;
+  if (i0 >= b3 || j0 >= r) return;
+  const int M = min(TILE, b3 - i0), N = min(TILE, r - j0);
+  double acc[4][4];
+  tile_zero(acc);
+  tile_gemm_acc(acc, front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double *Xs = X + S.x_off;
+  for (int ii = 0; ii < 4; ++ii)
+    for (int jj = 0; jj < 4; ++jj) {
+      int i = ty + 16 * ii, j = tx + 16 * jj;
+      if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= acc[ii][jj];
+    }
+}
+
+// Wp[3lo + i][3lo + j] += sum_k Z(k, i) Z(k, j), lower tiles of the r x r block
+__global__ __launch_bounds__(256) void k_rhs_syrk(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                  const int *__restrict__ lohi, const double *__restrict__ Z, int m,
+                                                  double *__restrict__ Wp) {
+  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  const int s = level_sup[blockIdx.y];
+  const SupDev S = sup[s];
+  const int lo = lohi[3 * s];
+  const int r = 3 * (lohi[3 * s + 2] - lo);
+  const int nt = (r + TILE - 1) / TILE;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int I, J;
+  tri_index(blockIdx.x, I, J);
+  const int n3 = 3 * S.ncol;
+  const int i0 = TILE * I, j0 = TILE * J;
+  const int M = min(TILE, r - i0), N = min(TILE, r - j0);
+  const double *Zs = Z + S.z_off;
+  double acc[4][4];
+  tile_zero(acc);
+  tile_gemm_acc(acc, Zs + (long)i0 * n3, n3, 1, Zs + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const long base = (long)(3 * lo) * m + 3 * lo;
+  for (int ii = 0; ii < 4; ++ii)
+    for (int jj = 0; jj < 4; ++jj) {
+      int i = ty + 16 * ii, j = tx + 16 * jj;
+      if (i < M && j < N) Wp[base + (long)(i0 + i) * m + (j0 + j)] += acc[ii][jj];
+    }
+}
+
+__global__ void k_fill(long n, double v, double *__restrict__ x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+
+// W_H[3c+a][3c'+b] = Wp at the positions of c, c' (lower triangle read).
+__global__ void k_wh_unpermute(int nc, const int *__restrict__ pos, const double *__restrict__ Wp,
+                               double *__restrict__ WH) {
+  const int m = 3 * nc;
+  const long total = (long)m * m;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    int pi = 3 * pos[i / 3] + i % 3, pj = 3 * pos[j / 3] + j % 3;
+    WH[e] = (pi >= pj) ? Wp[(long)pi * m + pj] : Wp[(long)pj * m + pi];
+  }
+}
+
+// ---- single RHS -------------------------------------------------------------
+
+__global__ void k_fwd1_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                const int *__restrict__ invmap, const int *__restrict__ perm,
+                                const double *__restrict__ b, double *__restrict__ x1) {
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < f; i += gridDim.x * blockDim.x) {
+    double v = (i < n3) ? b[3 * perm[S.col0 + i / 3] + i % 3] : 0.0;
+    for (int c = 0; c < S.nchild; ++c) {
+      const int ii = invmap[invmap_off[S.child_off + c] + i / 3];
+      if (ii >= 0) {
+        const SupDev C = sup[child[S.child_off + c]];
+        v += x1[C.x1_off + 3 * C.ncol + 3 * ii + i % 3];
+      }
+    }
+    x1[S.x1_off + i] = v;
+  }
+}
+
+// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]   (rows tiled by 64)
+__global__ __launch_bounds__(256) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                   const double *__restrict__ linv, const double *__restrict__ x1,
+                                                   double *__restrict__ y) {
+  __shared__ double part[4][64];
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol;
+  const int i0 = 64 * blockIdx.x;
+  if (i0 >= n3) return;
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int i = i0 + r;
+  const int kend = min(n3, i0 + 64);
+  const double *Li = linv + S.linv_off;
+  const double *xs = x1 + S.x1_off;
+  double acc = 0.0;
+  if (i < n3)
+    for (int k = ph; k < kend; k += 4) acc = fma(Li[i + (long)k * n3], xs[k], acc);
+  part[ph][r] = acc;
+  __syncthreads();
+  if (ph == 0 && i < n3) y[3 * S.col0 + i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+}
+
+// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]
+__global__ __launch_bounds__(256) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                  const double *__restrict__ front, const double *__restrict__ y,
+                                                  double *__restrict__ x1) {
+  __shared__ double part[4][64];
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
+  const int i0 = 64 * blockIdx.x;
+  if (i0 >= b3) return;
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int i = i0 + r;
+  const double *F = front + S.front_off + n3;
+  const double *ys = y + 3 * S.col0;
+  double acc = 0.0;
+  if (i < b3)
+    for (int k = ph; k < n3; k += 4) acc = fma(F[i + (long)k * f], ys[k], acc);
+  part[ph][r] = acc;
+  __syncthreads();
+  if (ph == 0 && i < b3) x1[S.x1_off + n3 + i] -= (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+}
+
+// y_s[j] -= sum_i L21(i, j) x[below row i]  (16 columns per block, 16 lanes per column)
+__global__ __launch_bounds__(256) void k_bwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                  const int *__restrict__ rows, const double *__restrict__ front,
+                                                  const double *__restrict__ xp, double *__restrict__ y) {
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
+  const int j = 16 * blockIdx.x + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  if (16 * (int)blockIdx.x >= n3) return;
+  double acc = 0.0;
+  if (j < n3) {
+    const double *F = front + S.front_off + n3 + (long)j * f;
+    const int *rw = rows + S.rows_off;
+    for (int i = l; i < b3; i += 16) acc = fma(F[i], xp[3 * rw[i / 3] + i % 3], acc);
+  }
+  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (l == 0 && j < n3) y[3 * S.col0 + j] -= acc;
+}
+
+// xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]
+__global__ __launch_bounds__(256) void k_bwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                   const double *__restrict__ linv, const double *__restrict__ y,
+                                                   double *__restrict__ xp) {
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol;
+  const int j = 16 * blockIdx.x + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  if (16 * (int)blockIdx.x >= n3) return;
+  double acc = 0.0;
+  if (j < n3) {
+    const double *Lc = linv + S.linv_off + (long)j * n3;
+    const double *ys = y + 3 * S.col0;
+    for (int i = j + l; i < n3; i += 16) acc = fma(Lc[i], ys[i], acc);
+  }
+  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (l == 0 && j < n3) xp[3 * S.col0 + j] = acc;
+}
+
+__global__ void k_unpermute_vec(int N, const int *__restrict__ perm, const double *__restrict__ xp,
+                                double *__restrict__ x) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int v = perm[p];
+  x[3 * v] = xp[3 * p];
+  x[3 * v + 1] = xp[3 * p + 1];
+  x[3 * v + 2] = xp[3 * p + 2];
+}
+
+}  // namespace
+
+void single_rhs_solve(icr_scene *s, const double *b, double *x) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  const int nl = (int)F.levels.size();
+  double *y = F.d_y, *xp = F.d_y + s->mesh.n;
+  for (int l = 0; l < nl; ++l) {
+    const LevelInfo &L = F.levels[l];
+    if (!L.count) continue;
+    const int *ls = F.d_level_sup + L.first;
+    k_fwd1_assemble<<<dim3(cdiv(L.max_f3, 256), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
+                                                                          F.d_invmap, F.d_perm, b, F.d_x1);
+    ICR_LAUNCH_CHECK();
+    k_fwd1_diag<<<dim3(cdiv(L.max_n3, 64), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
+    ICR_LAUNCH_CHECK();
+    if (L.max_b3 > 0) {
+      k_fwd1_off<<<dim3(cdiv(L.max_b3, 64), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
+      ICR_LAUNCH_CHECK();
+    }
+  }
+  for (int l = nl - 1; l >= 0; --l) {
+    const LevelInfo &L = F.levels[l];
+    if (!L.count) continue;
+    const int *ls = F.d_level_sup + L.first;
+    if (L.max_b3 > 0) {
+      k_bwd1_off<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
+      ICR_LAUNCH_CHECK();
+    }
+    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
+    ICR_LAUNCH_CHECK();
+  }
+  k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
+  ICR_LAUNCH_CHECK();
+}
+
+void ensure_rhs_capacity(icr_scene *s, int nc) {
+  auto &F = s->fac;
+  if (nc <= F.nc_cap) return;
+  ICR_HIP(hipStreamSynchronize(s->stream));
+  F.rhs_arena.release();
+  long long xo = 0, zo = 0;
+  for (int i = 0; i < (int)F.sup.size(); ++i) {
+    SupDev &d = F.sup[i];
+    int rmax = 3 * std::min(nc, d.region_nodes);
+    d.rmax = rmax;
+    d.x_off = xo;
+    d.z_off = zo;
+    xo += (long long)3 * (d.ncol + d.nb) * rmax;
+    zo += (long long)3 * d.ncol * rmax;
+  }
+  F.d_X = F.rhs_arena.alloc<double>(xo);
+  F.d_Z = F.rhs_arena.alloc<double>(zo);
+  const long long m = 3LL * nc;
+  F.d_Wp = F.rhs_arena.alloc<double>(m * m);
+  F.d_keys = F.rhs_arena.alloc<int>(nc);
+  F.d_order = F.rhs_arena.alloc<int>(nc);
+  F.d_pos = F.rhs_arena.alloc<int>(nc);
+  F.d_lohi = F.rhs_arena.alloc<int>(3LL * F.sup.size());
+  F.d_cerr = F.rhs_arena.alloc<int>(1);
+  ICR_HIP(hipMemcpyAsync(F.d_sup, F.sup.data(), F.sup.size() * sizeof(SupDev), hipMemcpyHostToDevice, s->stream));
+  ICR_HIP(hipStreamSynchronize(s->stream));
+  F.nc_cap = nc;
+}
+
+void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  const int nsup = (int)F.sup.size();
+  const long long m = 3LL * nc;
+  if (validate) ICR_HIP(hipMemsetAsync(F.d_cerr, 0, sizeof(int), st));
+  k_sort_contacts<<<1, 1024, 0, st>>>(nc, s->mesh.N, nsup, node_ids, F.d_sup_of_node, s->mesh.d_fixed, F.d_keys,
+                                      F.d_order, F.d_pos, F.d_cerr);
+  ICR_LAUNCH_CHECK();
+  k_ranges<<<cdiv(nsup, 256), 256, 0, st>>>(nsup, nc, F.d_sup, F.d_keys, F.d_lohi);
+  ICR_LAUNCH_CHECK();
+  k_fill<<<1024, 256, 0, st>>>(m * m, 0.0, F.d_Wp);
+  ICR_LAUNCH_CHECK();
+  for (size_t l = 0; l < F.levels.size(); ++l) {
+    const LevelInfo &L = F.levels[l];
+    if (!L.count) continue;
+    const int *ls = F.d_level_sup + L.first;
+    int rmax = 0;
+    for (int q = 0; q < L.count; ++q) rmax = std::max(rmax, F.sup[F.sym.level_sup[L.first + q]].rmax);
+    if (rmax == 0) continue;
+    long long fr = (long long)L.max_f3 * rmax;
+    int gx = (int)std::min<long long>(2048, (fr + 255) / 256);
+    k_rhs_assemble<<<dim3(gx, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
+                                                      F.d_lohi, F.d_order, node_ids, F.d_iperm, F.d_X);
+    ICR_LAUNCH_CHECK();
+    const int ct = cdiv(rmax, TILE);
+    k_rhs_diag<<<dim3(L.max_rows_tiles, ct, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_linv, F.d_X, F.d_Z);
+    ICR_LAUNCH_CHECK();
+    if (L.max_below_tiles > 0) {
+      k_rhs_off<<<dim3(L.max_below_tiles, ct, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_front, F.d_Z,
+                                                                      F.d_X);
+      ICR_LAUNCH_CHECK();
+    }
+    k_rhs_syrk<<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
+    ICR_LAUNCH_CHECK();
+  }
+  k_wh_unpermute<<<2048, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH);
+  ICR_LAUNCH_CHECK();
+}
+
+}  // namespace icr

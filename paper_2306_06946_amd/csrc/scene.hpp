@@ -1,0 +1,165 @@
+// The scene object behind the opaque icr_scene handle, and the host-side
+// launchers of every kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace icr {
+
+// Device allocations owned by a scene; freed together.
+struct Arena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  template <class T>
+  T *alloc(size_t count) {
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw HipError(e, "hipMalloc(" + std::to_string(count * sizeof(T)) + " bytes)");
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T *>(p);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v, hipStream_t st) {
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) ICR_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+// Per-level host summary used to size grids.
+struct LevelInfo {
+  int first = 0, count = 0;   // into level_sup
+  int max_n3 = 0;             // max DOF columns of a supernode
+  int max_f3 = 0;             // max front order
+  int max_b3 = 0;             // max below rows (DOF)
+  long long max_f2 = 0;       // max f^2
+  int max_rows_tiles = 0;     // max ceil(n3/64)
+  int max_below_tiles = 0;    // max ceil(b3/64)
+  int a_first = 0, a_count = 0;   // A-scatter entries of the level
+  int child_rank_max = 0;
+};
+
+struct Mesh {
+  int N = 0, T = 0, n = 0, nnzb = 0;
+  double rho = 0, alpha = 0, beta = 0, h = 0, grav[3] = {0, 0, 0};
+  std::vector<double> nodes;
+  std::vector<int> tets;
+  std::vector<uint8_t> fixed;
+  MeshGraph graph;
+  // device
+  double *d_nodes = nullptr, *d_E = nullptr, *d_nu = nullptr;
+  int *d_tets = nullptr;
+  uint8_t *d_fixed = nullptr;
+  int *d_bsr_ptr = nullptr, *d_bsr_col = nullptr, *d_bsr_row = nullptr;
+  int *d_contrib_ptr = nullptr, *d_contrib = nullptr;  // per block: (tet*16 + a*4 + b)
+  int *d_nt_ptr = nullptr, *d_nt = nullptr;            // node -> tets
+  double *d_Ke = nullptr, *d_vol = nullptr, *d_mass = nullptr, *d_K = nullptr, *d_A = nullptr;
+  int *d_err = nullptr;
+};
+
+struct Factor {
+  Symbolic sym;
+  std::vector<SupDev> sup;
+  std::vector<LevelInfo> levels;
+  SupDev *d_sup = nullptr;
+  int *d_rows = nullptr, *d_child = nullptr, *d_invmap_off = nullptr, *d_invmap = nullptr;
+  int *d_level_sup = nullptr, *d_perm = nullptr, *d_iperm = nullptr, *d_sup_of_node = nullptr;
+  AScatter *d_ascat = nullptr;
+  double *d_front = nullptr, *d_linv = nullptr, *d_x1 = nullptr;
+  long long front_elems = 0, linv_elems = 0, x1_elems = 0;
+  int *d_err = nullptr;
+  double flops = 0, ms = 0;
+  long long nnzL = 0;
+  int max_front = 0;
+  // multi-RHS arenas (grown on demand)
+  int nc_cap = 0;
+  double *d_X = nullptr, *d_Z = nullptr, *d_Wp = nullptr;
+  int *d_keys = nullptr, *d_order = nullptr, *d_pos = nullptr, *d_lohi = nullptr, *d_cerr = nullptr;
+  Arena rhs_arena;
+  // single-RHS work vectors (permuted)
+  double *d_y = nullptr;
+};
+
+struct Contacts {
+  int count = 0;                 // candidates
+  std::vector<int> nodes;
+  int *d_cand = nullptr;
+  double *d_mu_node = nullptr;   // friction per node (0 if not a candidate)
+  int nc_cap = 0;
+  int *d_nodes_c = nullptr;      // selected contact nodes of the current step
+  double *d_mu = nullptr, *d_pfree = nullptr, *d_pstart = nullptr, *d_p = nullptr;
+  double *d_C = nullptr, *d_Cprev = nullptr, *d_delta = nullptr, *d_dk = nullptr;
+  double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr;
+  int8_t *d_status = nullptr;
+  int *d_sweeps = nullptr;       // per Newton iteration
+  double *d_eps = nullptr;
+  Arena arena;
+};
+
+struct State {
+  double *d_q = nullptr, *d_v = nullptr, *d_qrest = nullptr;
+  double *d_b = nullptr, *d_dvfree = nullptr, *d_qfree = nullptr, *d_sol = nullptr;
+  double *d_node_force = nullptr;   // world-frame force per node from the previous step
+  int *d_prev_nodes = nullptr;
+  int prev_nc = 0;
+  double t = 0;
+};
+
+}  // namespace icr
+
+struct icr_scene {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  bool assembled = false, factored = false, has_candidates = false, stepped = false;
+  icr::Mesh mesh;
+  icr::Factor fac;
+  icr::Contacts con;
+  icr::State st;
+  icr::Arena mesh_arena, fac_arena, state_arena;
+  int last_nc = 0;
+};
+
+namespace icr {
+
+// k_fem.hip
+void launch_element_matrices(icr_scene *s);
+void launch_assemble_blocks(icr_scene *s);
+void launch_free_rhs(icr_scene *s, const double *q, const double *v, double *b);
+void launch_axpy_qfree(icr_scene *s);
+void launch_integrate(icr_scene *s);
+
+// k_factor.hip
+void run_numeric_factor(icr_scene *s);
+
+// k_solve.hip
+void single_rhs_solve(icr_scene *s, const double *b, double *x);
+void ensure_rhs_capacity(icr_scene *s, int nc);
+void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate);
+
+// k_contact.hip
+void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1);
+void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first);
+void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
+void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
+                double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
+                double *eps_dev);
+void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
+void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
+                      double *p);
+void launch_corrective_rhs(icr_scene *s, int nc);
+void launch_store_forces(icr_scene *s, int nc);
+
+}  // namespace icr
