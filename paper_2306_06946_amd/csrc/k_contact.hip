@@ -178,8 +178,16 @@ __global__ void k_update_W(int nc, const double *__restrict__ WH, const double *
   double R[3][3];   // X T
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) R[i][j] = X[3 * i] * T[0][j] + X[3 * i + 1] * T[1][j] + X[3 * i + 2] * T[2][j];
+  // diagonal blocks: mirror the lower entries so the block is exactly symmetric
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) W[(3L * a + i) * m + 3L * b + j] = lower ? R[i][j] : R[j][i];
+    for (int j = 0; j < 3; ++j) {
+      double v;
+      if (a == b)
+        v = (i >= j) ? R[i][j] : R[j][i];
+      else
+        v = lower ? R[i][j] : R[j][i];
+      W[(3L * a + i) * m + 3L * b + j] = v;
+    }
 }
 
 // ---- local solver (Signorini + Coulomb cone) --------------------------------
