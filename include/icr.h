@@ -171,6 +171,7 @@ typedef struct {
   int32_t j_inner;      /* slip fixed-point passes */
   double tol;           /* PGS stopping tolerance */
   int32_t timing;       /* 1: record per-phase device times in the report */
+  int32_t scheme;       /* 0: fast update (Algorithm 3); 1: standard rebuild (Algorithm 2) */
 } icr_step_opts;
 
 typedef struct {
@@ -180,16 +181,20 @@ typedef struct {
   double ms_contacts;       /* signed distances + selection + mapping */
   double ms_build_WH;       /* W_H = H A^-1 H^T (Eq. 28) */
   double ms_newton;         /* all Newton iterations (directions, update_W, PGS, GEMV) */
-  double ms_update_W;       /* sum over Newton iterations */
+  double ms_update_W;       /* sum over Newton iterations (standard scheme: J A^-1 J^T rebuild) */
   double ms_pgs;            /* sum over Newton iterations */
   double ms_correct;        /* corrective solve + integration (Eq. 20) */
   int32_t sweeps[16];       /* PGS sweeps per Newton iteration (first 16) */
   double eps[16];           /* final eps per Newton iteration (first 16) */
   int32_t n_separate, n_stick, n_slip;   /* status counts after the last iteration */
+  double ms_corr;           /* sum over Newton iterations of the per-iteration correction:
+                               proximity GEMV (fast) or A^-1 J^T lambda solve + H q (standard) */
 } icr_step_report;
 
 /*
- * One time step of the fast scheme (Algorithm 1 with Algorithm 3 inside):
+ * One time step (Algorithm 1 with Algorithm 3 inside; opt->scheme = 1 runs
+ * Algorithm 2 instead: per iteration W_k = J_k A^-1 J_k^T by the multi-RHS
+ * solve with RHS J_k^T, PGS, q_k = q_free + h^2 A^-1 J_k^T lambda_k, p_k = H q_k):
  * free motion; contacts = the n_contacts candidates with the smallest signed
  * distance at q_free (ties by node id), ordered by node id; W_H; n_newton
  * iterations of {frames and gaps at p_{k-1}, W_k = C_k W_H C_k^T, PGS warm

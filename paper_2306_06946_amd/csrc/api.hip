@@ -71,6 +71,7 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_f = C.arena.alloc<double>(m);
   C.d_WH = C.arena.alloc<double>(m * m);
   C.d_W = C.arena.alloc<double>(m * m);
+  C.d_g = C.arena.alloc<double>(m);
   C.d_status = C.arena.alloc<int8_t>(nc);
   C.d_sweeps = C.arena.alloc<int>(64);
   C.d_eps = C.arena.alloc<double>(64);
@@ -435,14 +436,14 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
                               double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
                               int32_t j_inner, int32_t *sweeps_out, double *eps_out) {
   return guarded(s, [&] {
-    REQUIRE(n_c >= 1 && n_c <= 2688, "n_c must be in [1, 2688]");
+    REQUIRE(n_c >= 1 && n_c <= kPgsMaxContacts, "n_c must be in [1, 2560]");
     REQUIRE(max_sweeps >= 1, "max_sweeps must be >= 1");
     REQUIRE(j_inner >= 0, "j_inner must be >= 0");
     REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
     REQUIRE(W && d && mu && lambda && status, "NULL device pointer");
     ensure_contact_buffers(s, std::max(n_c, 1));
     launch_pgs(s->stream, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, s->con.d_sweeps,
-               s->con.d_eps);
+               s->con.d_eps, s->con.d_g);
     if (sweeps_out || eps_out) {
       int sw = 0;
       double ep = 0;
@@ -502,9 +503,11 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     REQUIRE(opt, "NULL options");
     const int nc = opt->n_contacts;
     REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
-    REQUIRE(nc <= 2688, "n_contacts exceeds the PGS kernel limit (2688)");
+    REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (2560)");
     REQUIRE(opt->n_newton >= 1 && opt->n_newton <= 64, "n_newton must be in [1, 64]");
     REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
+    REQUIRE(opt->scheme == 0 || opt->scheme == 1, "scheme must be 0 (fast) or 1 (standard)");
+    const bool standard = opt->scheme == 1;
     ensure_contact_buffers(s, nc);
     ensure_rhs_capacity(s, nc);
     hipStream_t st = s->stream;
@@ -512,57 +515,63 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     auto &S = s->st;
     const double h = s->mesh.h, t0 = S.t, t1 = S.t + h;
     const bool timing = opt->timing != 0;
-    hipEvent_t ev[8];
-    if (timing)
+    const int nk = opt->n_newton;
+    std::vector<hipEvent_t> ev, kev;
+    if (timing) {
+      ev.resize(6);
+      kev.resize(4 * nk);
       for (auto &e : ev) ICR_HIP(hipEventCreate(&e));
-    std::vector<hipEvent_t> nev;
-    auto mark = [&](int i) {
-      if (timing) ICR_HIP(hipEventRecord(ev[i], st));
+      for (auto &e : kev) ICR_HIP(hipEventCreate(&e));
+    }
+    auto mark = [&](std::vector<hipEvent_t> &v, int i) {
+      if (timing) ICR_HIP(hipEventRecord(v[i], st));
     };
-    mark(0);
+    mark(ev, 0);
     // free motion (Eq. 5, 12)
     launch_free_rhs(s, S.d_q, S.d_v, S.d_b);
     single_rhs_solve(s, S.d_b, S.d_dvfree);
     launch_axpy_qfree(s);
-    mark(1);
+    mark(ev, 1);
     launch_select_contacts(s, nc, *obs, t0, t1);
-    mark(2);
-    build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
-    mark(3);
-    const int m = 3 * nc;
-    std::vector<hipEvent_t> kev;
-    if (timing) {
-      kev.resize(3 * opt->n_newton);
-      for (auto &e : kev) ICR_HIP(hipEventCreate(&e));
-    }
-    for (int k = 0; k < opt->n_newton; ++k) {
+    mark(ev, 2);
+    if (!standard) build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
+    mark(ev, 3);
+    for (int k = 0; k < nk; ++k) {
       launch_directions(s, nc, *obs, t0, t1, k == 0);
-      if (timing) ICR_HIP(hipEventRecord(kev[3 * k], st));
-      launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);
-      if (timing) ICR_HIP(hipEventRecord(kev[3 * k + 1], st));
+      mark(kev, 4 * k);
+      if (standard)
+        build_WH_device(s, nc, C.d_nodes_c, C.d_W, false, C.d_C);   // W_k = J_k A^-1 J_k^T
+      else
+        launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);                // W_k = C_k W_H C_k^T
+      mark(kev, 4 * k + 1);
       launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
-                 C.d_sweeps + k, C.d_eps + k);
-      if (timing) ICR_HIP(hipEventRecord(kev[3 * k + 2], st));
+                 C.d_sweeps + k, C.d_eps + k, C.d_g);
+      mark(kev, 4 * k + 2);
       launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
-      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
+      if (standard) {
+        contact_force_solve(s, C.d_lam, S.d_sol);                      // A^-1 J_k^T lambda_k
+        launch_standard_proximity(s, nc);                               // p_k = H (q_free + h^2 sol)
+      } else {
+        launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+      }
+      mark(kev, 4 * k + 3);
     }
-    (void)m;
-    mark(4);
+    mark(ev, 4);
     // corrective motion and integration (Eq. 20)
-    launch_corrective_rhs(s, nc);
-    single_rhs_solve(s, S.d_b, S.d_sol);
+    if (!standard) contact_force_solve(s, C.d_f, S.d_sol);             // A^-1 H^T f (last W_H's Z)
     launch_integrate(s);
     launch_store_forces(s, nc);
-    mark(5);
+    mark(ev, 5);
     S.t = t1;
     s->stepped = true;
     s->last_nc = nc;
+    if (standard) ICR_HIP(hipMemsetAsync(C.d_WH, 0, sizeof(double) * 9L * nc * nc, st));
     if (rep) {
       std::memset(rep, 0, sizeof(*rep));
       rep->t = S.t;
-      int nk = std::min(opt->n_newton, 16);
-      ICR_HIP(hipMemcpyAsync(rep->sweeps, C.d_sweeps, sizeof(int) * nk, hipMemcpyDeviceToHost, st));
-      ICR_HIP(hipMemcpyAsync(rep->eps, C.d_eps, sizeof(double) * nk, hipMemcpyDeviceToHost, st));
+      int nr = std::min(nk, 16);
+      ICR_HIP(hipMemcpyAsync(rep->sweeps, C.d_sweeps, sizeof(int) * nr, hipMemcpyDeviceToHost, st));
+      ICR_HIP(hipMemcpyAsync(rep->eps, C.d_eps, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
       std::vector<int8_t> stat(nc);
       ICR_HIP(hipMemcpyAsync(stat.data(), C.d_status, nc, hipMemcpyDeviceToHost, st));
       ICR_HIP(hipStreamSynchronize(st));
@@ -572,24 +581,21 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
         if (v == ICR_SLIP) rep->n_slip++;
       }
       if (timing) {
-        float ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[0], ev[5]));
-        rep->ms_total = ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        rep->ms_free = ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
-        rep->ms_contacts = ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
-        rep->ms_build_WH = ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
-        rep->ms_newton = ms;
-        ICR_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
-        rep->ms_correct = ms;
-        for (int k = 0; k < opt->n_newton; ++k) {
-          ICR_HIP(hipEventElapsedTime(&ms, kev[3 * k], kev[3 * k + 1]));
-          rep->ms_update_W += ms;
-          ICR_HIP(hipEventElapsedTime(&ms, kev[3 * k + 1], kev[3 * k + 2]));
-          rep->ms_pgs += ms;
+        auto el = [&](hipEvent_t a, hipEvent_t b) {
+          float ms = 0;
+          ICR_HIP(hipEventElapsedTime(&ms, a, b));
+          return (double)ms;
+        };
+        rep->ms_total = el(ev[0], ev[5]);
+        rep->ms_free = el(ev[0], ev[1]);
+        rep->ms_contacts = el(ev[1], ev[2]);
+        rep->ms_build_WH = el(ev[2], ev[3]);
+        rep->ms_newton = el(ev[3], ev[4]);
+        rep->ms_correct = el(ev[4], ev[5]);
+        for (int k = 0; k < nk; ++k) {
+          rep->ms_update_W += el(kev[4 * k], kev[4 * k + 1]);
+          rep->ms_pgs += el(kev[4 * k + 1], kev[4 * k + 2]);
+          rep->ms_corr += el(kev[4 * k + 2], kev[4 * k + 3]);
         }
       }
     }

@@ -94,6 +94,136 @@ __device__ inline void tile_zero(double acc[4][4]) {
     for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// 64x64 FP64 tile accumulators.  Both expose for_each(f) visiting the tile-local
+// (i, j) of every value the calling thread owns.
+// ---------------------------------------------------------------------------
+
+// VALU layout: thread (tx, ty) owns (ty + 16 ii, tx + 16 jj).
+struct AccV {
+  double c[4][4];
+  __device__ void zero() { tile_zero_impl(); }
+  __device__ void tile_zero_impl() {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) c[ii][jj] = 0.0;
+  }
+  __device__ void acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M, int N, int k0,
+                      int k1, double *sA, double *sB);
+  template <class F>
+  __device__ void for_each(F &&f) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) f(ty + 16 * ii, tx + 16 * jj, c[ii][jj]);
+  }
+};
+
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+// MFMA layout (v_mfma_f64_16x16x4f64, checked on gfx950): A(i, k) comes from
+// lane i + 16 k, B(k, j) from lane j + 16 k, and D(i, j) lands in lane
+// j + 16 (i % 4), register i / 4.  Wave w owns the 32x32 quadrant
+// (32 (w >> 1), 32 (w & 1)) as 2x2 blocks of 16x16.
+struct AccM {
+  mfma_d4 c[2][2];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) c[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __device__ void acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M, int N, int k0,
+                      int k1, double *sA, double *sB);
+  template <class F>
+  __device__ void for_each(F &&f) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f(r0 + 16 * a + 4 * t + (l >> 4), c0 + 16 * b + (l & 15), c[a][b][t]);
+  }
+};
+
+// Stage one K-chunk of A (64 x KT) and B (KT x 64) into LDS as [k][i] / [k][j].
+__device__ inline void stage_chunk(const double *__restrict__ A, long ars, long acs, const double *__restrict__ B,
+                                   long brs, long bcs, int M, int N, int kb, int k1, double *sA, double *sB) {
+  const int tid = threadIdx.x;
+  const bool a_rowfast = (ars == 1);
+  const bool b_colfast = (bcs == 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int i, k;
+    if (a_rowfast) {
+      i = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      i = e >> 4;
+    }
+    int kk = kb + k;
+    double v = 0.0;
+    if (i < M && kk < k1) v = A[(long)i * ars + (long)kk * acs];
+    sA[k * TILE + i] = v;
+    int j;
+    if (b_colfast) {
+      j = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      j = e >> 4;
+    }
+    kk = kb + k;
+    v = 0.0;
+    if (j < N && kk < k1) v = B[(long)kk * brs + (long)j * bcs];
+    sB[k * TILE + j] = v;
+  }
+}
+
+__device__ inline void AccV::acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M,
+                                 int N, int k0, int k1, double *sA, double *sB) {
+  tile_gemm_acc(c, A, ars, acs, B, brs, bcs, M, N, k0, k1, sA, sB);
+}
+
+__device__ inline void AccM::acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M,
+                                 int N, int k0, int k1, double *sA, double *sB) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = l & 15, lk = l >> 4;
+  for (int kb = k0; kb < k1; kb += KT) {
+    stage_chunk(A, ars, acs, B, brs, bcs, M, N, kb, k1, sA, sB);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const int k = kk + lk;
+      double a0 = sA[k * TILE + r0 + li], a1 = sA[k * TILE + r0 + 16 + li];
+      double b0 = sB[k * TILE + c0 + li], b1 = sB[k * TILE + c0 + 16 + li];
+      c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0][0], 0, 0, 0);
+      c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[0][1], 0, 0, 0);
+      c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[1][0], 0, 0, 0);
+      c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+// The tile accumulator used by the dense kernels.
+#ifndef ICR_TILE_MFMA
+#define ICR_TILE_MFMA 1
+#endif
+#if ICR_TILE_MFMA
+typedef AccM Acc;
+#else
+typedef AccV Acc;
+#endif
+
+
 // Lower-triangle tile index x -> (I, J), I >= J, row-major over the triangle.
 __device__ inline void tri_index(int x, int &I, int &J) {
   int i = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);

@@ -276,59 +276,105 @@ __device__ double block_sum(double v, double *red) {
   return s;   // valid in thread 0
 }
 
+// g0 = d + h^2 W lambda0, one wave per row (the PGS start state).
+__global__ __launch_bounds__(256) void k_pgs_init(int m, const double *__restrict__ W, const double *__restrict__ d,
+                                                  const double *__restrict__ lam, double h2, double *__restrict__ g) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ln = threadIdx.x & 63;
+  if (row >= m) return;
+  const double *Wr = W + (long)row * m;
+  double s = 0.0;
+  for (int j = ln; j < m; j += 64) s = fma(Wr[j], lam[j], s);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (ln == 0) g[row] = d[row] + h2 * s;
+}
+
 // Single-workgroup PGS.  g = d + W~ lambda (all contacts, own term included)
-// lives in LDS; per contact a: d_a = g_a - W~_aa lambda_a, local solve, then
-// g += W~[:, a] (lambda_new - lambda_old) read from rows of the symmetric W.
+// lives in LDS; for contact a: d_a = g_a - W~_aa lambda_a, local solve, then
+// g += W~[:, a] (lambda_new - lambda_old), read from rows of the exactly
+// symmetric W.  A contact whose force is zero and whose gap g_n is >= 0 is a
+// no-op of Gauss-Seidel (it stays separated and changes nothing), so wave 0
+// scans 64 contacts at a time with a ballot and jumps to the first contact
+// that can change; the iterates are those of the sequential sweep.
+constexpr int PGS_MAX_NC = 2560;
 __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__restrict__ W,
-                                                     const double *__restrict__ d, const double *__restrict__ mu,
+                                                     const double *__restrict__ g0, const double *__restrict__ mu,
                                                      double h2, double *__restrict__ lam, int8_t *__restrict__ status,
                                                      int max_sweeps, double tol, int j_inner,
                                                      int *__restrict__ sweeps_out, double *__restrict__ eps_out) {
-  __shared__ double g[8064];
-  __shared__ double bc[4];
+  __shared__ double g[3 * PGS_MAX_NC];
+  __shared__ unsigned char nz[PGS_MAX_NC];
+  __shared__ double bc[3];
   __shared__ double red[16];
+  __shared__ int ctl;
   __shared__ int stop;
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  // g = d + h2 * W lambda0 (one wave per row, lanes across columns)
-  for (int i = wv; i < m; i += 16) {
-    double s = 0.0;
-    for (int j = ln; j < m; j += 64) s = fma(W[(long)i * m + j], lam[j], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (ln == 0) g[i] = d[i] + h2 * s;
-  }
+  for (int i = tid; i < m; i += 1024) g[i] = g0[i];
+  for (int c = tid; c < nc; c += 1024)
+    nz[c] = (lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0) ? 1 : 0;
   if (tid == 0) stop = 0;
   __syncthreads();
-  double dsum = 0.0;   // thread 0: sum of squared changes in this sweep
+  double dsum = 0.0;   // wave 0: sum of squared changes in this sweep
   int sweep = 0;
   double eps = 0.0;
   for (sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) dsum = 0.0;
-    for (int a = 0; a < nc; ++a) {
-      if (tid == 0) {
-        double w[3][3], lo[3], dd[3];
-        for (int i = 0; i < 3; ++i) {
-          lo[i] = lam[3 * a + i];
-          for (int j = 0; j < 3; ++j) w[i][j] = h2 * W[(3L * a + i) * m + 3L * a + j];
+    dsum = 0.0;
+    int a = 0;
+    while (true) {
+      if (wv == 0) {
+        int next = nc;
+        while (a < nc) {
+          const int c = a + ln;
+          const bool active = (c < nc) && (nz[c] != 0 || g[3 * c] < 0.0);
+          const unsigned long long bal = __ballot(active);
+          if (bal == 0ull) {
+            if (c < nc) status[c] = (int8_t)ICR_SEPARATE;
+            a += 64;
+            continue;
+          }
+          const int first = __ffsll((long long)bal) - 1;
+          if (ln < first && c < nc) status[c] = (int8_t)ICR_SEPARATE;
+          next = a + first;
+          break;
         }
-        for (int i = 0; i < 3; ++i) dd[i] = g[3 * a + i] - (w[i][0] * lo[0] + w[i][1] * lo[1] + w[i][2] * lo[2]);
-        Local r = local_solve(w, dd, mu[a], j_inner);
-        for (int i = 0; i < 3; ++i) {
-          double dl = r.l[i] - lo[i];
-          bc[i] = dl;
-          dsum += dl * dl;
-          lam[3 * a + i] = r.l[i];
+        if (next < nc) {
+          // every lane of wave 0 runs the local solve on the same data
+          double w[3][3], lo[3], dd[3];
+          for (int i = 0; i < 3; ++i) {
+            lo[i] = lam[3 * next + i];
+            for (int j = 0; j < 3; ++j) w[i][j] = h2 * W[(3L * next + i) * m + 3L * next + j];
+          }
+          for (int i = 0; i < 3; ++i)
+            dd[i] = g[3 * next + i] - (w[i][0] * lo[0] + w[i][1] * lo[1] + w[i][2] * lo[2]);
+          Local r = local_solve(w, dd, mu[next], j_inner);
+          double dl[3];
+          for (int i = 0; i < 3; ++i) {
+            dl[i] = r.l[i] - lo[i];
+            dsum += dl[i] * dl[i];
+          }
+          if (ln == 0) {
+            for (int i = 0; i < 3; ++i) {
+              bc[i] = dl[i];
+              lam[3 * next + i] = r.l[i];
+            }
+            status[next] = (int8_t)r.st;
+            nz[next] = (r.l[0] != 0.0 || r.l[1] != 0.0 || r.l[2] != 0.0) ? 1 : 0;
+          }
         }
-        status[a] = (int8_t)r.st;
+        if (ln == 0) ctl = next;
       }
       __syncthreads();
+      const int cur = ctl;
+      if (cur >= nc) break;
       const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
       if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
-        const double *r0 = W + (3L * a) * m;
+        const double *r0 = W + (3L * cur) * m;
         for (int i = tid; i < m; i += 1024)
           g[i] += h2 * (r0[i] * d0 + r0[m + i] * d1 + r0[2L * m + i] * d2);
       }
       __syncthreads();
+      a = cur + 1;
     }
     // eps = |lam_i - lam_{i-1}| / |lam_i|
     double part = 0.0;
@@ -387,6 +433,15 @@ __global__ void k_scatter_force(int nc, const int *__restrict__ nodes, const dou
   for (int a = 0; a < 3; ++a) out[3 * v + a] = f[3 * c + a];
 }
 
+// p = H q_k with q_k = q_free + h^2 A^-1 J^T lambda (Algorithm 2, steps 4-6).
+__global__ void k_std_proximity(int nc, const int *__restrict__ nodes, const double *__restrict__ qf,
+                                const double *__restrict__ sol, double h2, double *__restrict__ p) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int v = nodes[c];
+  for (int a = 0; a < 3; ++a) p[3 * c + a] = qf[3 * v + a] + h2 * sol[3 * v + a];
+}
+
 __global__ void k_clear_nodes(int nc, const int *__restrict__ nodes, double *__restrict__ out) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
@@ -419,8 +474,13 @@ void launch_update_W(hipStream_t st, int nc, const double *WH, const double *Cm,
 }
 
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h, double *lam,
-                int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev) {
-  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev, eps_dev);
+                int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev,
+                double *g_work) {
+  const int m = 3 * nc;
+  k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, g_work);
+  ICR_LAUNCH_CHECK();
+  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, g_work, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
+                                   eps_dev);
   ICR_LAUNCH_CHECK();
 }
 
@@ -436,11 +496,10 @@ void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_
   ICR_LAUNCH_CHECK();
 }
 
-void launch_corrective_rhs(icr_scene *s, int nc) {
-  const long n = s->mesh.n;
-  k_zero<<<cdiv(n, 256), 256, 0, s->stream>>>(n, s->st.d_b);
-  ICR_LAUNCH_CHECK();
-  k_scatter_force<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, s->st.d_b);
+void launch_standard_proximity(icr_scene *s, int nc) {
+  const double h = s->mesh.h;
+  k_std_proximity<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->st.d_qfree, s->st.d_sol, h * h,
+                                                         s->con.d_p);
   ICR_LAUNCH_CHECK();
 }
 

@@ -131,16 +131,13 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const SupDev *__restrict__ s
   const int M = min(TILE, f - i0);
   double *F = front + S.front_off;
   const double *Di = linv + S.linv_off + k + (long)k * n3;
-  double acc[4][4];
-  tile_zero(acc);
+  Acc acc;
+  acc.zero();
   // out(i, j) = sum_c P(i, c) * Dinv(j, c)
-  tile_gemm_acc(acc, F + i0 + (long)k * f, 1, f, Di, n3, 1, M, t, 0, t, sA, sB);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int ii = 0; ii < 4; ++ii)
-    for (int jj = 0; jj < 4; ++jj) {
-      int i = ty + 16 * ii, j = tx + 16 * jj;
-      if (i < M && j < t) F[(long)(i0 + i) + (long)(k + j) * f] = acc[ii][jj];
-    }
+  acc.acc(F + i0 + (long)k * f, 1, f, Di, n3, 1, M, t, 0, t, sA, sB);
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < t) F[(long)(i0 + i) + (long)(k + j) * f] = v;
+  });
 }
 
 // Trailing update of the lower triangle: F(i, j) -= sum_c P(i, c) P(j, c).
@@ -161,15 +158,12 @@ __global__ __launch_bounds__(256) void k_trailing(const SupDev *__restrict__ sup
   const int i0 = base + TILE * I, j0 = base + TILE * J;
   const int M = min(TILE, f - i0), N = min(TILE, f - j0);
   double *F = front + S.front_off;
-  double acc[4][4];
-  tile_zero(acc);
-  tile_gemm_acc(acc, F + i0 + (long)k * f, 1, f, F + j0 + (long)k * f, f, 1, M, N, 0, t, sA, sB);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int ii = 0; ii < 4; ++ii)
-    for (int jj = 0; jj < 4; ++jj) {
-      int i = ty + 16 * ii, j = tx + 16 * jj;
-      if (i < M && j < N) F[(long)(i0 + i) + (long)(j0 + j) * f] -= acc[ii][jj];
-    }
+  Acc acc;
+  acc.zero();
+  acc.acc(F + i0 + (long)k * f, 1, f, F + j0 + (long)k * f, f, 1, M, N, 0, t, sA, sB);
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < N) F[(long)(i0 + i) + (long)(j0 + j) * f] -= v;
+  });
 }
 
 // L_ss^{-1}: one workgroup per 64-column tile J, marching down tile rows:
@@ -186,24 +180,20 @@ __global__ __launch_bounds__(256) void k_linv(const SupDev *__restrict__ sup, co
   const double *F = front + S.front_off;
   double *X = linv + S.linv_off;
   const int j0 = TILE * J, N = min(TILE, n3 - j0);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   for (int I = J + 1; I < ntl; ++I) {
     const int i0 = TILE * I, M = min(TILE, n3 - i0);
-    double acc[4][4];
-    tile_zero(acc);
-    tile_gemm_acc(acc, F + i0, 1, f, X + j0 * (long)n3, 1, n3, M, N, j0, i0, sA, sB);
+    Acc acc;
+    acc.zero();
+    acc.acc(F + i0, 1, f, X + j0 * (long)n3, 1, n3, M, N, j0, i0, sA, sB);
     // stage S = acc in LDS (column-major 64x64)
-    for (int ii = 0; ii < 4; ++ii)
-      for (int jj = 0; jj < 4; ++jj) Sx[(ty + 16 * ii) + TILE * (tx + 16 * jj)] = acc[ii][jj];
+    acc.for_each([&](int i, int j, double v) { Sx[i + TILE * j] = v; });
     __syncthreads();
-    double out[4][4];
-    tile_zero(out);
-    tile_gemm_acc(out, X + i0 + (long)i0 * n3, 1, n3, Sx, 1, TILE, M, N, 0, M, sA, sB);
-    for (int ii = 0; ii < 4; ++ii)
-      for (int jj = 0; jj < 4; ++jj) {
-        int i = ty + 16 * ii, j = tx + 16 * jj;
-        if (i < M && j < N) X[(long)(i0 + i) + (long)(j0 + j) * n3] = -out[ii][jj];
-      }
+    Acc out;
+    out.zero();
+    out.acc(X + i0 + (long)i0 * n3, 1, n3, Sx, 1, TILE, M, N, 0, M, sA, sB);
+    out.for_each([&](int i, int j, double v) {
+      if (i < M && j < N) X[(long)(i0 + i) + (long)(j0 + j) * n3] = -v;
+    });
     __threadfence_block();
     __syncthreads();
   }

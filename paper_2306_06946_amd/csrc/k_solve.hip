@@ -110,7 +110,8 @@ __global__ void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__rest
                                const int *__restrict__ child, const int *__restrict__ invmap_off,
                                const int *__restrict__ invmap, const int *__restrict__ lohi,
                                const int *__restrict__ order, const int *__restrict__ node_ids,
-                               const int *__restrict__ iperm, double *__restrict__ X) {
+                               const int *__restrict__ iperm, const double *__restrict__ frames,
+                               double *__restrict__ X) {
   const int s = level_sup[blockIdx.y];
   const SupDev S = sup[s];
   const int lo = lohi[3 * s], own = lohi[3 * s + 1], hi = lohi[3 * s + 2];
@@ -124,9 +125,13 @@ __global__ void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__rest
     const int p = lo + jc / 3, a = jc % 3;
     double v = 0.0;
     if (p >= own) {
-      int node = node_ids[order[p]];
-      int lr = 3 * (iperm[node] - S.col0) + a;
-      v = (i == lr) ? 1.0 : 0.0;
+      // column of H^T (unit vector), or of J^T = H^T C^T when frames are given
+      const int c = order[p];
+      const int base = 3 * (iperm[node_ids[c]] - S.col0);
+      if (frames == nullptr)
+        v = (i == base + a) ? 1.0 : 0.0;
+      else
+        v = (i >= base && i < base + 3) ? frames[9L * c + 3 * a + (i - base)] : 0.0;
     } else {
       for (int c = 0; c < S.nchild; ++c) {
         const int ch = child[S.child_off + c];
@@ -159,16 +164,13 @@ __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup
   if (i0 >= n3 || j0 >= r) return;
   const int M = min(TILE, n3 - i0), N = min(TILE, r - j0);
   const int kend = min(n3, i0 + TILE);
-  double acc[4][4];
-  tile_zero(acc);
-  tile_gemm_acc(acc, linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, sA, sB);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  Acc acc;
+  acc.zero();
+  acc.acc(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, sA, sB);
   double *Zs = Z + S.z_off;
-  for (int ii = 0; ii < 4; ++ii)
-    for (int jj = 0; jj < 4; ++jj) {
-      int i = ty + 16 * ii, j = tx + 16 * jj;
-      if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = acc[ii][jj];
-    }
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = v;
+  });
 }
 
 // X_s[n_s:] -= L_21 Z_s
@@ -183,16 +185,13 @@ __global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup,
   const int i0 = TILE * blockIdx.x, j0 = TILE * blockIdx.y;
   if (i0 >= b3 || j0 >= r) return;
   const int M = min(TILE, b3 - i0), N = min(TILE, r - j0);
-  double acc[4][4];
-  tile_zero(acc);
-  tile_gemm_acc(acc, front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  Acc acc;
+  acc.zero();
+  acc.acc(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
   double *Xs = X + S.x_off;
-  for (int ii = 0; ii < 4; ++ii)
-    for (int jj = 0; jj < 4; ++jj) {
-      int i = ty + 16 * ii, j = tx + 16 * jj;
-      if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= acc[ii][jj];
-    }
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= v;
+  });
 }
 
 // Wp[3lo + i][3lo + j] += sum_k Z(k, i) Z(k, j), lower tiles of the r x r block
@@ -212,16 +211,13 @@ __global__ __launch_bounds__(256) void k_rhs_syrk(const SupDev *__restrict__ sup
   const int i0 = TILE * I, j0 = TILE * J;
   const int M = min(TILE, r - i0), N = min(TILE, r - j0);
   const double *Zs = Z + S.z_off;
-  double acc[4][4];
-  tile_zero(acc);
-  tile_gemm_acc(acc, Zs + (long)i0 * n3, n3, 1, Zs + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  Acc acc;
+  acc.zero();
+  acc.acc(Zs + (long)i0 * n3, n3, 1, Zs + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
   const long base = (long)(3 * lo) * m + 3 * lo;
-  for (int ii = 0; ii < 4; ++ii)
-    for (int jj = 0; jj < 4; ++jj) {
-      int i = ty + 16 * ii, j = tx + 16 * jj;
-      if (i < M && j < N) Wp[base + (long)(i0 + i) * m + (j0 + j)] += acc[ii][jj];
-    }
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < N) Wp[base + (long)(i0 + i) * m + (j0 + j)] += v;
+  });
 }
 
 __global__ void k_fill(long n, double v, double *__restrict__ x) {
@@ -354,11 +350,70 @@ __global__ void k_unpermute_vec(int N, const int *__restrict__ perm, const doubl
 
 }  // namespace
 
-void single_rhs_solve(icr_scene *s, const double *b, double *x) {
+namespace {
+
+void backward_solve(icr_scene *s, double *x) {
   auto &F = s->fac;
   hipStream_t st = s->stream;
   const int nl = (int)F.levels.size();
   double *y = F.d_y, *xp = F.d_y + s->mesh.n;
+  for (int l = nl - 1; l >= 0; --l) {
+    const LevelInfo &L = F.levels[l];
+    if (!L.count) continue;
+    const int *ls = F.d_level_sup + L.first;
+    if (L.max_b3 > 0) {
+      k_bwd1_off<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
+      ICR_LAUNCH_CHECK();
+    }
+    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
+    ICR_LAUNCH_CHECK();
+  }
+  k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
+  ICR_LAUNCH_CHECK();
+}
+
+// y[3 col0_s + i] = sum_c Z_s(i, c) f[contact at column c]: the forward half of
+// A^-1 H^T f reuses Z = L^-1 P H^T from the W_H build of the same contacts.
+// One block per (64-row tile, supernode): 64 rows x 4 column phases.
+__global__ __launch_bounds__(256) void k_zf(const SupDev *__restrict__ sup, const int *__restrict__ lohi,
+                                            const double *__restrict__ Z, const double *__restrict__ fpos,
+                                            double *__restrict__ y) {
+  __shared__ double part[4][64];
+  const int s = blockIdx.y;
+  const SupDev S = sup[s];
+  const int n3 = 3 * S.ncol;
+  const int i0 = 64 * blockIdx.x;
+  if (i0 >= n3) return;
+  const int lo = lohi[3 * s], r = 3 * (lohi[3 * s + 2] - lo);
+  const int rr = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int i = i0 + rr;
+  const double *Zs = Z + S.z_off;
+  const double *fs = fpos + 3 * lo;
+  double acc = 0.0;
+  if (i < n3) {
+#pragma unroll 4
+    for (int c = ph; c < r; c += 4) acc = fma(Zs[i + (long)c * n3], fs[c], acc);
+  }
+  part[ph][rr] = acc;
+  __syncthreads();
+  if (ph == 0 && i < n3) y[3 * S.col0 + i] = (part[0][rr] + part[1][rr]) + (part[2][rr] + part[3][rr]);
+}
+
+// fpos[3 p + a] = f[3 order[p] + a]
+__global__ void k_gather_fpos(int nc, const int *__restrict__ order, const double *__restrict__ f,
+                              double *__restrict__ fpos) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * nc) return;
+  fpos[e] = f[3 * order[e / 3] + e % 3];
+}
+
+}  // namespace
+
+void single_rhs_solve(icr_scene *s, const double *b, double *x) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  const int nl = (int)F.levels.size();
+  double *y = F.d_y;
   for (int l = 0; l < nl; ++l) {
     const LevelInfo &L = F.levels[l];
     if (!L.count) continue;
@@ -373,19 +428,20 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
       ICR_LAUNCH_CHECK();
     }
   }
-  for (int l = nl - 1; l >= 0; --l) {
-    const LevelInfo &L = F.levels[l];
-    if (!L.count) continue;
-    const int *ls = F.d_level_sup + L.first;
-    if (L.max_b3 > 0) {
-      k_bwd1_off<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
-      ICR_LAUNCH_CHECK();
-    }
-    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
-    ICR_LAUNCH_CHECK();
-  }
-  k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
+  backward_solve(s, x);
+}
+
+void contact_force_solve(icr_scene *s, const double *f, double *x) {
+  auto &F = s->fac;
+  int max_n3 = 0;
+  for (const auto &L : F.levels) max_n3 = std::max(max_n3, L.max_n3);
+  const int nsup = (int)F.sup.size();
+  const int nc = s->last_build_nc;
+  k_gather_fpos<<<cdiv(3 * nc, 256), 256, 0, s->stream>>>(nc, F.d_order, f, F.d_fpos);
   ICR_LAUNCH_CHECK();
+  k_zf<<<dim3(cdiv(max_n3, 64), nsup), 256, 0, s->stream>>>(F.d_sup, F.d_lohi, F.d_Z, F.d_fpos, F.d_y);
+  ICR_LAUNCH_CHECK();
+  backward_solve(s, x);
 }
 
 void ensure_rhs_capacity(icr_scene *s, int nc) {
@@ -411,17 +467,19 @@ void ensure_rhs_capacity(icr_scene *s, int nc) {
   F.d_order = F.rhs_arena.alloc<int>(nc);
   F.d_pos = F.rhs_arena.alloc<int>(nc);
   F.d_lohi = F.rhs_arena.alloc<int>(3LL * F.sup.size());
+  F.d_fpos = F.rhs_arena.alloc<double>(3LL * nc);
   F.d_cerr = F.rhs_arena.alloc<int>(1);
   ICR_HIP(hipMemcpyAsync(F.d_sup, F.sup.data(), F.sup.size() * sizeof(SupDev), hipMemcpyHostToDevice, s->stream));
   ICR_HIP(hipStreamSynchronize(s->stream));
   F.nc_cap = nc;
 }
 
-void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate) {
+void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate, const double *frames) {
   auto &F = s->fac;
   hipStream_t st = s->stream;
   const int nsup = (int)F.sup.size();
   const long long m = 3LL * nc;
+  s->last_build_nc = nc;
   if (validate) ICR_HIP(hipMemsetAsync(F.d_cerr, 0, sizeof(int), st));
   k_sort_contacts<<<1, 1024, 0, st>>>(nc, s->mesh.N, nsup, node_ids, F.d_sup_of_node, s->mesh.d_fixed, F.d_keys,
                                       F.d_order, F.d_pos, F.d_cerr);
@@ -440,7 +498,7 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     long long fr = (long long)L.max_f3 * rmax;
     int gx = (int)std::min<long long>(2048, (fr + 255) / 256);
     k_rhs_assemble<<<dim3(gx, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
-                                                      F.d_lohi, F.d_order, node_ids, F.d_iperm, F.d_X);
+                                                      F.d_lohi, F.d_order, node_ids, F.d_iperm, frames, F.d_X);
     ICR_LAUNCH_CHECK();
     const int ct = cdiv(rmax, TILE);
     k_rhs_diag<<<dim3(L.max_rows_tiles, ct, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_linv, F.d_X, F.d_Z);

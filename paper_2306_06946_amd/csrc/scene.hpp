@@ -85,7 +85,7 @@ struct Factor {
   int max_front = 0;
   // multi-RHS arenas (grown on demand)
   int nc_cap = 0;
-  double *d_X = nullptr, *d_Z = nullptr, *d_Wp = nullptr;
+  double *d_X = nullptr, *d_Z = nullptr, *d_Wp = nullptr, *d_fpos = nullptr;
   int *d_keys = nullptr, *d_order = nullptr, *d_pos = nullptr, *d_lohi = nullptr, *d_cerr = nullptr;
   Arena rhs_arena;
   // single-RHS work vectors (permuted)
@@ -101,7 +101,7 @@ struct Contacts {
   int *d_nodes_c = nullptr;      // selected contact nodes of the current step
   double *d_mu = nullptr, *d_pfree = nullptr, *d_pstart = nullptr, *d_p = nullptr;
   double *d_C = nullptr, *d_Cprev = nullptr, *d_delta = nullptr, *d_dk = nullptr;
-  double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr;
+  double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr, *d_g = nullptr;
   int8_t *d_status = nullptr;
   int *d_sweeps = nullptr;       // per Newton iteration
   double *d_eps = nullptr;
@@ -130,6 +130,7 @@ struct icr_scene {
   icr::State st;
   icr::Arena mesh_arena, fac_arena, state_arena;
   int last_nc = 0;
+  int last_build_nc = 0;   // contact count of the last multi-RHS forward solve (Z valid for it)
 };
 
 namespace icr {
@@ -146,20 +147,26 @@ void run_numeric_factor(icr_scene *s);
 
 // k_solve.hip
 void single_rhs_solve(icr_scene *s, const double *b, double *x);
+// x = A^-1 H^T f for the contacts of the last build_WH_device call (reuses Z).
+void contact_force_solve(icr_scene *s, const double *f, double *x);
 void ensure_rhs_capacity(icr_scene *s, int nc);
-void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate);
+// W_H = H A^-1 H^T, or J A^-1 J^T with J = C H when per-contact frames
+// [nc*9] are given (the standard rebuild of Algorithm 2).
+void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate,
+                     const double *frames = nullptr);
 
 // k_contact.hip
 void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1);
 void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
+constexpr int kPgsMaxContacts = 2560;
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
-                double *eps_dev);
+                double *eps_dev, double *g_work);
 void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
 void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
                       double *p);
-void launch_corrective_rhs(icr_scene *s, int nc);
 void launch_store_forces(icr_scene *s, int nc);
+void launch_standard_proximity(icr_scene *s, int nc);
 
 }  // namespace icr

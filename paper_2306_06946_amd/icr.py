@@ -33,7 +33,7 @@ class Obstacle(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("n_contacts", C.c_int32), ("n_newton", C.c_int32), ("max_sweeps", C.c_int32),
-                ("j_inner", C.c_int32), ("tol", C.c_double), ("timing", C.c_int32)]
+                ("j_inner", C.c_int32), ("tol", C.c_double), ("timing", C.c_int32), ("scheme", C.c_int32)]
 
 
 class StepReport(C.Structure):
@@ -41,7 +41,7 @@ class StepReport(C.Structure):
                 ("ms_contacts", C.c_double), ("ms_build_WH", C.c_double), ("ms_newton", C.c_double),
                 ("ms_update_W", C.c_double), ("ms_pgs", C.c_double), ("ms_correct", C.c_double),
                 ("sweeps", C.c_int32 * 16), ("eps", C.c_double * 16),
-                ("n_separate", C.c_int32), ("n_stick", C.c_int32), ("n_slip", C.c_int32)]
+                ("n_separate", C.c_int32), ("n_stick", C.c_int32), ("n_slip", C.c_int32), ("ms_corr", C.c_double)]
 
 
 class FactorInfo(C.Structure):
@@ -227,7 +227,7 @@ class Scene:
                                                 _dptr(p, t.float64)))
 
     def step(self, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, timing=False,
-             report=True):
+             report=True, standard=False):
         ob = Obstacle()
         ob.kind = 1 if obstacle["kind"] == "sphere" else 0
         for i in range(3):
@@ -235,7 +235,7 @@ class Scene:
             ob.vel[i] = float(obstacle["vel"][i])
             ob.normal[i] = float(obstacle["normal"][i])
         ob.radius = float(obstacle.get("radius", 0.0))
-        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0)
+        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, 1 if standard else 0)
         rep = StepReport()
         self._check(self.L.icr_step(self._h, C.byref(ob), C.byref(op), C.byref(rep) if report else None))
         if not report:

@@ -210,3 +210,81 @@ def test_step_is_deterministic(medium):
         outs.append((q.cpu(), v.cpu(), r["lam"].cpu()))
     for a, b in zip(outs[0], outs[1]):
         assert torch.equal(a, b)
+
+
+def test_precision_config_sampled_against_oracle():
+    """61k DOF / 1000 contacts, the benchmark configuration (30 fixed sweeps).
+
+    Full vectors where the oracle is cheap (q_free, contact selection), sampled
+    columns of W_H by the oracle's banded solves, and properties that hold at
+    any size for the Newton loop (exact symmetry of W_H, cone feasibility,
+    separated contacts carry no force, proximity = p_free + h^2 W_H C^T lambda).
+    """
+    sc = make_scene("precision", 0)
+    icr = _icr()
+    _say("[gpu] precision: assemble+factor")
+    s = icr.scene_from_dict(sc)
+    nc = sc["n_contacts"]
+    m = 3 * nc
+    _say("[gpu] precision: one step (30 sweeps)")
+    s.step(sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"])
+    res = s.step_results(nc, with_WH=True)
+    _say("[gpu] precision: oracle assembly + banded factor")
+    asm = O.assemble(sc)
+    fac = O.CholeskyFactor(asm["A"])
+    q0 = sc["nodes"].ravel()
+    dv, q_free, _ = O.free_motion(asm, fac, sc, q0, np.zeros_like(q0), q0)
+    got_qf = res["q_free"].cpu().numpy()
+    assert _rel(got_qf - q0, q_free - q0) <= 1e-10
+    nodes = O.select_contacts(q_free, sc, sc["h"])
+    assert np.array_equal(res["node_ids"].cpu().numpy(), nodes)
+    WH = res["WH"].cpu().numpy().reshape(m, m)
+    assert np.array_equal(WH, WH.T)
+    cols = np.array([0, 1, 2, 449, 1500, 2998, 2999])
+    _say("[gpu] precision: oracle W_H columns")
+    ref = O.build_WH(fac, nodes, asm["n"], columns=cols)
+    assert _rel(WH[:, cols], ref) <= 1e-10
+    lam = res["lam"].cpu().numpy().reshape(-1, 3)
+    st = res["status"].cpu().numpy()
+    mu = sc["cand_mu"][np.searchsorted(sc["candidates"], nodes)]
+    assert np.all(lam[:, 0] >= 0)
+    assert np.all(np.hypot(lam[:, 1], lam[:, 2]) <= mu * lam[:, 0] * (1 + 1e-12) + 1e-300)
+    assert np.all(lam[st == 0] == 0)
+    Cm = res["C"].cpu().numpy().reshape(-1, 3, 3)
+    f = np.einsum("aji,aj->ai", Cm, lam).ravel()
+    p_free = q_free.reshape(-1, 3)[nodes].ravel()
+    p = res["p"].cpu().numpy()
+    assert _rel(p - p_free, (sc["h"] ** 2) * (WH @ f)) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "medium"])
+def test_standard_scheme_matches_oracle_and_fast(cfg):
+    """Algorithm 2 on the GPU (J A^-1 J^T rebuilt by the multi-RHS solve every
+    iteration) against the oracle's Algorithm 2, and against the GPU's
+    Algorithm 3: the reformulation is exact for constant A and H."""
+    sc = make_scene(cfg, 0)
+    if cfg == "medium":
+        sc["max_sweeps"] = 100
+    icr = _icr()
+    nc = sc["n_contacts"]
+    runs = {}
+    for std in (True, False):
+        s = icr.scene_from_dict(sc)
+        _say(f"[gpu] {cfg} scheme={'standard' if std else 'fast'}")
+        rep = s.step(sc["obstacle"], nc, sc["n_newton"], sc["max_sweeps"], sc["tol"], sc["j_inner"], standard=std)
+        res = s.step_results(nc)
+        q, v, _ = s.get_state()
+        runs[std] = (rep, res["lam"].cpu().numpy(), res["status"].cpu().numpy(), res["p"].cpu().numpy(),
+                     q.cpu().numpy())
+    sim = O.Simulation(sc)
+    rec = []
+    out = sim.step(standard=True, record=rec)
+    rep, lam, st, p, q = runs[True]
+    assert rep["sweeps"] == [r["sweeps"] for r in rec]
+    assert np.array_equal(st, rec[-1]["status"])
+    assert _rel(lam, rec[-1]["lam"]) <= 1e-10
+    assert _rel(q - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+    repf, lamf, stf, pf, qf = runs[False]
+    assert np.array_equal(st, stf)
+    assert _rel(lam, lamf) <= 1e-10
+    assert _rel(q - sim.q_rest, qf - sim.q_rest) <= 1e-10
