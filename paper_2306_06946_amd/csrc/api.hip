@@ -71,7 +71,10 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_f = C.arena.alloc<double>(m);
   C.d_WH = C.arena.alloc<double>(m * m);
   C.d_W = C.arena.alloc<double>(m * m);
-  C.d_g = C.arena.alloc<double>(m);
+  C.pgs.g = C.arena.alloc<double>(m);
+  C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
+  C.pgs.Wns = C.arena.alloc<double>(pgs_wns_elems(nc));
+  C.pgs.ctl = C.arena.alloc<int>(2);
   C.d_status = C.arena.alloc<int8_t>(nc);
   C.d_sweeps = C.arena.alloc<int>(64);
   C.d_eps = C.arena.alloc<double>(64);
@@ -235,7 +238,7 @@ icr_status icr_create(icr_scene **out, void *stream) {
   icr_scene *s = new (std::nothrow) icr_scene();
   if (!s) return ICR_E_OOM;
   s->stream = (hipStream_t)stream;
-  if (hipGetDevice(&s->device) != hipSuccess) {
+  if (hipInit(0) != hipSuccess || hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return ICR_E_HIP;
   }
@@ -443,7 +446,7 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
     REQUIRE(W && d && mu && lambda && status, "NULL device pointer");
     ensure_contact_buffers(s, std::max(n_c, 1));
     launch_pgs(s->stream, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, s->con.d_sweeps,
-               s->con.d_eps, s->con.d_g);
+               s->con.d_eps, s->con.pgs);
     if (sweeps_out || eps_out) {
       int sw = 0;
       double ep = 0;
@@ -545,7 +548,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
         launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);                // W_k = C_k W_H C_k^T
       mark(kev, 4 * k + 1);
       launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
-                 C.d_sweeps + k, C.d_eps + k, C.d_g);
+                 C.d_sweeps + k, C.d_eps + k, C.pgs);
       mark(kev, 4 * k + 2);
       launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
       if (standard) {

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/icr.h"
+#include "icr.h"
 
 namespace icr {
 

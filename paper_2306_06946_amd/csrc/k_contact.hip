@@ -298,19 +298,36 @@ __global__ __launch_bounds__(256) void k_pgs_init(int m, const double *__restric
 // that can change; the iterates are those of the sequential sweep.
 constexpr int PGS_MAX_NC = 2560;
 __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__restrict__ W,
-                                                     const double *__restrict__ g0, const double *__restrict__ mu,
-                                                     double h2, double *__restrict__ lam, int8_t *__restrict__ status,
+                                                     const double *__restrict__ d, const double *__restrict__ g0,
+                                                     const double *__restrict__ mu, double h2,
+                                                     double *__restrict__ lam, int8_t *__restrict__ status,
                                                      int max_sweeps, double tol, int j_inner,
-                                                     int *__restrict__ sweeps_out, double *__restrict__ eps_out) {
+                                                     int *__restrict__ sweeps_out, double *__restrict__ eps_out,
+                                                     const int *__restrict__ ctl) {
   __shared__ double g[3 * PGS_MAX_NC];
   __shared__ unsigned char nz[PGS_MAX_NC];
   __shared__ double bc[3];
   __shared__ double red[16];
-  __shared__ int ctl;
+  __shared__ int ctl_s;
   __shared__ int stop;
+  // resume mode: continue where the active-set kernel handed over (or do nothing)
+  int first_sweep = 0;
+  if (ctl != nullptr) {
+    if (ctl[0] == 0) return;
+    first_sweep = ctl[1];
+  }
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  for (int i = tid; i < m; i += 1024) g[i] = g0[i];
+  if (g0 != nullptr) {
+    for (int i = tid; i < m; i += 1024) g[i] = g0[i];
+  } else {
+    for (int i = wv; i < m; i += 16) {
+      double sacc = 0.0;
+      for (int j = ln; j < m; j += 64) sacc = fma(W[(long)i * m + j], lam[j], sacc);
+      for (int o = 32; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 64);
+      if (ln == 0) g[i] = d[i] + h2 * sacc;
+    }
+  }
   for (int c = tid; c < nc; c += 1024)
     nz[c] = (lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0) ? 1 : 0;
   if (tid == 0) stop = 0;
@@ -318,7 +335,7 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
   double dsum = 0.0;   // wave 0: sum of squared changes in this sweep
   int sweep = 0;
   double eps = 0.0;
-  for (sweep = 0; sweep < max_sweeps; ++sweep) {
+  for (sweep = first_sweep; sweep < max_sweeps; ++sweep) {
     dsum = 0.0;
     int a = 0;
     while (true) {
@@ -362,10 +379,10 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
             nz[next] = (r.l[0] != 0.0 || r.l[1] != 0.0 || r.l[2] != 0.0) ? 1 : 0;
           }
         }
-        if (ln == 0) ctl = next;
+        if (ln == 0) ctl_s = next;
       }
       __syncthreads();
-      const int cur = ctl;
+      const int cur = ctl_s;
       if (cur >= nc) break;
       const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
       if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
@@ -392,6 +409,225 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
       break;
     }
   }
+  if (tid == 0) {
+    *sweeps_out = sweep;
+    *eps_out = eps;
+  }
+}
+
+// Active-set projected Gauss-Seidel (exact).  In a sweep only contacts with
+// a non-zero force or a negative gap can change; all others are no-ops of
+// Gauss-Seidel.  The kernel keeps the set S of contacts that may change,
+// runs the sequential sweep over S alone with the compact coupling block
+// W~_SS (gathered once per change of S and read from L2, next rows
+// prefetched), and afterwards verifies, for every contact outside S, that it
+// was indeed a no-op at its turn: its gap g_n + sum over the S contacts
+// before it of W~_{n,S} dlambda must be >= 0.  On a violation the violating
+// contacts join S and the sweep is redone from its start state, so the
+// iterates are those of the full sequential sweep.  Contacts outside S keep
+// only their normal gap g_n (all a no-op test needs); the gaps of S contacts
+// are rebuilt from scratch whenever S changes.  If S outgrows PGS_SMAX the
+// kernel hands the remaining sweeps to k_pgs_single (ctl[0] = 1).
+constexpr int PGS_SMAX = 448;
+constexpr int PGS_S3 = 3 * PGS_SMAX;
+__global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__restrict__ W,
+                                                     const double *__restrict__ d, const double *__restrict__ g0,
+                                                     const double *__restrict__ mu, double h2,
+                                                     double *__restrict__ lam, int8_t *__restrict__ status,
+                                                     int max_sweeps, double tol, int j_inner,
+                                                     int *__restrict__ sweeps_out, double *__restrict__ eps_out,
+                                                     double *__restrict__ Wss, double *__restrict__ Wns,
+                                                     int *__restrict__ ctl) {
+  __shared__ double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3];
+  __shared__ double gn[PGS_MAX_NC];
+  __shared__ int Sidx[PGS_SMAX];
+  __shared__ unsigned char inS[PGS_MAX_NC];
+  __shared__ int wcount[64];
+  __shared__ double bc[3];
+  __shared__ double red[16];
+  __shared__ int sh_nS, sh_flag, stop;
+  const int m = 3 * nc;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  for (int c = tid; c < nc; c += 1024) {
+    bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
+    inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
+  }
+  if (tid == 0) {
+    stop = 0;
+    ctl[0] = 0;
+    ctl[1] = 0;
+  }
+  __syncthreads();
+  int sweep = 0, nS = 0, ldS = 0;
+  double eps = 0.0;
+  bool need_build = true;
+  while (sweep < max_sweeps) {
+    if (need_build) {
+      // ---- ordered list of S (ballot per 64-contact window, prefix by thread 0)
+      const int nwin = (nc + 63) / 64;
+      for (int w = wv; w < nwin; w += 16) {
+        const int c = 64 * w + ln;
+        const unsigned long long bal = __ballot(c < nc && inS[c]);
+        if (ln == 0) wcount[w] = __popcll(bal);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < nwin; ++w) {
+          int t = wcount[w];
+          wcount[w] = acc;
+          acc += t;
+        }
+        sh_nS = acc;
+      }
+      __syncthreads();
+      nS = sh_nS;
+      if (nS > PGS_SMAX) {   // hand over: global lambda holds the sweep-start state
+        if (tid == 0) {
+          ctl[0] = 1;
+          ctl[1] = sweep;
+        }
+        return;
+      }
+      for (int w = wv; w < nwin; w += 16) {
+        const int c = 64 * w + ln;
+        const bool in = c < nc && inS[c];
+        const unsigned long long bal = __ballot(in);
+        if (in) Sidx[wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+      }
+      __syncthreads();
+      ldS = 3 * nS;
+      for (int r = tid; r < ldS; r += 1024) lamS[r] = lam[3 * Sidx[r / 3] + r % 3];
+      // ---- compact couplings W~_SS and the normal rows W~_{n,S}
+      const long ns2 = (long)ldS * ldS;
+      for (long e = tid; e < ns2; e += 1024) {
+        const int r = (int)(e / ldS), q = (int)(e % ldS);
+        Wss[e] = h2 * W[(3L * Sidx[r / 3] + r % 3) * m + 3L * Sidx[q / 3] + q % 3];
+      }
+      const long nn = (long)nc * ldS;
+      for (long e = tid; e < nn; e += 1024) {
+        const int c = (int)(e / ldS), q = (int)(e % ldS);
+        Wns[e] = h2 * W[(3L * c) * m + 3L * Sidx[q / 3] + q % 3];
+      }
+      __threadfence_block();
+      __syncthreads();
+      // ---- gaps from scratch (lambda is zero outside S)
+      for (int r = wv; r < ldS; r += 16) {
+        double a = 0.0;
+        for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], lamS[q], a);
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (ln == 0) gS[r] = d[3 * Sidx[r / 3] + r % 3] + a;
+      }
+      for (int c = wv; c < nc; c += 16) {
+        double a = 0.0;
+        for (int q = ln; q < ldS; q += 64) a = fma(Wns[(long)c * ldS + q], lamS[q], a);
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (ln == 0) gn[c] = d[3 * c] + a;
+      }
+      __syncthreads();
+      need_build = false;
+    }
+    // ---- sweep over S from its start state
+    for (int r = tid; r < ldS; r += 1024) lamS0[r] = lamS[r];
+    if (tid == 0) sh_flag = 0;
+    double dsum = 0.0;
+    const int r0 = tid, r1 = tid + 1024;
+    double pf0[3] = {0, 0, 0}, pf1[3] = {0, 0, 0};
+    double w[3][3];
+    if (nS > 0) {
+      for (int b = 0; b < 3; ++b) {
+        if (r0 < ldS) pf0[b] = Wss[(long)b * ldS + r0];
+        if (r1 < ldS) pf1[b] = Wss[(long)b * ldS + r1];
+      }
+      if (wv == 0)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) w[i][j] = Wss[(long)i * ldS + j];
+    }
+    __syncthreads();
+    for (int i = 0; i < nS; ++i) {
+      if (wv == 0) {
+        const int a = Sidx[i];
+        double lo[3], dd[3];
+        for (int q = 0; q < 3; ++q) lo[q] = lamS[3 * i + q];
+        for (int q = 0; q < 3; ++q) dd[q] = gS[3 * i + q] - (w[q][0] * lo[0] + w[q][1] * lo[1] + w[q][2] * lo[2]);
+        Local rs = local_solve(w, dd, mu[a], j_inner);
+        double dl[3];
+        for (int q = 0; q < 3; ++q) {
+          dl[q] = rs.l[q] - lo[q];
+          dsum += dl[q] * dl[q];
+        }
+        if (ln == 0) {
+          for (int q = 0; q < 3; ++q) {
+            bc[q] = dl[q];
+            lamS[3 * i + q] = rs.l[q];
+          }
+          status[a] = (int8_t)rs.st;
+        }
+        if (i + 1 < nS) {
+          const long base = (long)(3 * (i + 1)) * ldS + 3 * (i + 1);
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) w[p][q] = Wss[base + (long)p * ldS + q];
+        }
+      }
+      __syncthreads();
+      const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
+      if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+        if (r0 < ldS) gS[r0] += pf0[0] * d0 + pf0[1] * d1 + pf0[2] * d2;
+        if (r1 < ldS) gS[r1] += pf1[0] * d0 + pf1[1] * d1 + pf1[2] * d2;
+      }
+      if (i + 1 < nS) {
+        const long base = (long)(3 * (i + 1)) * ldS;
+        for (int b = 0; b < 3; ++b) {
+          if (r0 < ldS) pf0[b] = Wss[base + (long)b * ldS + r0];
+          if (r1 < ldS) pf1[b] = Wss[base + (long)b * ldS + r1];
+        }
+      }
+      __syncthreads();
+    }
+    // ---- verify the skipped contacts and advance their normal gaps
+    for (int c = wv; c < nc; c += 16) {
+      if (inS[c]) continue;
+      double ab = 0.0, aa = 0.0;
+      for (int q = ln; q < ldS; q += 64) {
+        const double t = Wns[(long)c * ldS + q] * (lamS[q] - lamS0[q]);
+        aa += t;
+        if (Sidx[q / 3] < c) ab += t;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        ab += __shfl_xor(ab, o, 64);
+        aa += __shfl_xor(aa, o, 64);
+      }
+      if (ln == 0) {
+        if (gn[c] + ab < 0.0) {
+          inS[c] = 1;
+          sh_flag = 1;
+        }
+        gn[c] += aa;
+        status[c] = (int8_t)ICR_SEPARATE;
+      }
+    }
+    __syncthreads();
+    if (sh_flag) {
+      // a skipped contact was not a no-op: restart the sweep with a larger S
+      for (int r = tid; r < ldS; r += 1024) lam[3 * Sidx[r / 3] + r % 3] = lamS0[r];
+      need_build = true;
+      __threadfence_block();
+      __syncthreads();
+      continue;
+    }
+    double part = 0.0;
+    for (int r = tid; r < ldS; r += 1024) part += lamS[r] * lamS[r];
+    double nl2 = block_sum(part, red);
+    if (tid == 0) {
+      double diff = sqrt(dsum), nl = sqrt(nl2);
+      eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
+      stop = (eps <= tol) ? 1 : 0;
+    }
+    __syncthreads();
+    ++sweep;
+    if (stop) break;
+  }
+  for (int r = tid; r < ldS; r += 1024) lam[3 * Sidx[r / 3] + r % 3] = lamS[r];
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
@@ -475,14 +711,21 @@ void launch_update_W(hipStream_t st, int nc, const double *WH, const double *Cm,
 
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h, double *lam,
                 int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev,
-                double *g_work) {
+                const PgsWork &wk) {
   const int m = 3 * nc;
-  k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, g_work);
+  k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
-  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, g_work, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
-                                   eps_dev);
+  k_pgs_active<<<1, 1024, 0, st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
+                                   eps_dev, wk.Wss, wk.Wns, wk.ctl);
+  ICR_LAUNCH_CHECK();
+  // continues only if the active set outgrew the compact path
+  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
+                                   eps_dev, wk.ctl);
   ICR_LAUNCH_CHECK();
 }
+
+size_t pgs_wss_elems() { return (size_t)PGS_S3 * PGS_S3; }
+size_t pgs_wns_elems(int nc) { return (size_t)nc * PGS_S3; }
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {
   k_world_force<<<cdiv(nc, 128), 128, 0, st>>>(nc, Cm, lam, f);

@@ -92,6 +92,13 @@ struct Factor {
   double *d_y = nullptr;
 };
 
+// Work buffers of the PGS kernels: start gaps g [m], compact couplings
+// (pgs_wss_elems(), pgs_wns_elems(nc) doubles) and a 2-int control block.
+struct PgsWork {
+  double *g = nullptr, *Wss = nullptr, *Wns = nullptr;
+  int *ctl = nullptr;
+};
+
 struct Contacts {
   int count = 0;                 // candidates
   std::vector<int> nodes;
@@ -101,7 +108,8 @@ struct Contacts {
   int *d_nodes_c = nullptr;      // selected contact nodes of the current step
   double *d_mu = nullptr, *d_pfree = nullptr, *d_pstart = nullptr, *d_p = nullptr;
   double *d_C = nullptr, *d_Cprev = nullptr, *d_delta = nullptr, *d_dk = nullptr;
-  double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr, *d_g = nullptr;
+  double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr;
+  PgsWork pgs;
   int8_t *d_status = nullptr;
   int *d_sweeps = nullptr;       // per Newton iteration
   double *d_eps = nullptr;
@@ -160,9 +168,11 @@ void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, doubl
 void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 2560;
+size_t pgs_wss_elems();
+size_t pgs_wns_elems(int nc);
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
-                double *eps_dev, double *g_work);
+                double *eps_dev, const PgsWork &wk);
 void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
 void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
                       double *p);
