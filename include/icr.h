@@ -172,6 +172,8 @@ typedef struct {
   double tol;           /* PGS stopping tolerance */
   int32_t timing;       /* 1: record per-phase device times in the report */
   int32_t scheme;       /* 0: fast update (Algorithm 3); 1: standard rebuild (Algorithm 2) */
+  int32_t graph;        /* 1: capture the step's launch sequence once (per options) as a HIP graph
+                           and replay it; 0: launch every kernel eagerly.  Same results. */
 } icr_step_opts;
 
 typedef struct {

@@ -57,6 +57,7 @@ icr_status guarded(icr_scene *s, F &&body) {
 void ensure_contact_buffers(icr_scene *s, int nc) {
   auto &C = s->con;
   if (nc <= C.nc_cap) return;
+  s->epoch++;
   ICR_HIP(hipStreamSynchronize(s->stream));
   C.arena.release();
   const long m = 3L * nc;
@@ -74,6 +75,7 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.pgs.g = C.arena.alloc<double>(m);
   C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
   C.pgs.Wns = C.arena.alloc<double>(pgs_wns_elems(nc));
+  C.pgs.recs = C.arena.alloc<double>(pgs_rec_elems());
   C.pgs.ctl = C.arena.alloc<int>(2);
   C.d_status = C.arena.alloc<int8_t>(nc);
   C.d_sweeps = C.arena.alloc<int>(64);
@@ -242,6 +244,8 @@ icr_status icr_create(icr_scene **out, void *stream) {
     delete s;
     return ICR_E_HIP;
   }
+  if (hipDeviceGetAttribute(&s->clock_khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess)
+    s->clock_khz = 0;
   *out = s;
   return ICR_OK;
 }
@@ -249,6 +253,8 @@ icr_status icr_create(icr_scene **out, void *stream) {
 void icr_destroy(icr_scene *s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  s->sg.reset();
+  if (s->sg.cap) (void)hipStreamDestroy(s->sg.cap);
   s->con.arena.release();
   s->fac.rhs_arena.release();
   s->fac_arena.release();
@@ -281,6 +287,8 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
       REQUIRE(nu[t] > 0 && nu[t] < 0.5, "nu must be in (0, 0.5)");
     }
     ICR_HIP(hipStreamSynchronize(s->stream));
+    s->epoch++;
+    s->sg.reset();
     s->assembled = s->factored = s->has_candidates = s->stepped = false;
     s->con.arena.release();
     s->con.nc_cap = 0;
@@ -370,6 +378,13 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     S.d_prev_nodes = B.alloc<int>(N);
     S.prev_nc = 0;
     S.t = 0;
+    S.d_ctx = B.alloc<StepCtx>(1);
+    S.d_stamps = B.alloc<unsigned long long>(6 + 4 * 64);
+    S.obs_valid = false;
+    {
+      double t0 = 0.0;
+      launch_set_ctx(s, nullptr, &t0);
+    }
     ICR_HIP(hipStreamSynchronize(st));
     s->assembled = true;
     return ICR_OK;
@@ -380,6 +395,7 @@ icr_status icr_factor(icr_scene *s) {
   return guarded(s, [&] {
     if (!s->assembled) throw StateError("icr_factor before icr_assemble");
     s->factored = false;
+    s->epoch++;
     prepare_factor(s);
     run_numeric_factor(s);
     int bad = 0;
@@ -490,6 +506,7 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
     C.count = count;
     C.nodes.assign(nodes, nodes + count);
     auto &B = s->state_arena;
+    s->epoch++;
     C.d_cand = B.upload(C.nodes, s->stream);
     C.d_mu_node = B.upload(mu_node, s->stream);
     ICR_HIP(hipStreamSynchronize(s->stream));
@@ -497,6 +514,71 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
     return ICR_OK;
   });
 }
+
+namespace {
+
+// Enqueue one whole time step on s->stream.  With opt->timing, one-thread
+// kernels stamp the device clock between phases (slots 0..5 for the step,
+// 6 + 4k + j for Newton iteration k); stamps work the same in a replayed
+// graph.  Every argument that changes from step to step lives in device
+// memory, so the sequence can be captured once and replayed.
+void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
+  hipStream_t st = s->stream;
+  auto &C = s->con;
+  auto &S = s->st;
+  const double h = s->mesh.h;
+  const int nc = opt->n_contacts, nk = opt->n_newton;
+  const bool standard = opt->scheme == 1;
+  auto mark = [&](int base, int i) {
+    if (opt->timing) launch_stamp(s, base + i);
+  };
+  const int ev = 0, kev = 6;
+  mark(ev, 0);
+  // free motion (Eq. 5, 12)
+  launch_free_rhs(s, S.d_q, S.d_v, S.d_b);
+  single_rhs_solve(s, S.d_b, S.d_dvfree);
+  launch_axpy_qfree(s);
+  mark(ev, 1);
+  launch_select_contacts(s, nc);
+  mark(ev, 2);
+  if (!standard) build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
+  mark(ev, 3);
+  for (int k = 0; k < nk; ++k) {
+    launch_directions(s, nc, k == 0);
+    mark(kev, 4 * k);
+    if (standard)
+      build_WH_device(s, nc, C.d_nodes_c, C.d_W, false, C.d_C);   // W_k = J_k A^-1 J_k^T
+    else
+      launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);                // W_k = C_k W_H C_k^T
+    mark(kev, 4 * k + 1);
+    launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
+               C.d_sweeps + k, C.d_eps + k, C.pgs);
+    mark(kev, 4 * k + 2);
+    launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
+    if (standard) {
+      contact_force_solve(s, C.d_lam, S.d_sol);                      // A^-1 J_k^T lambda_k
+      launch_standard_proximity(s, nc);                               // p_k = H (q_free + h^2 sol)
+    } else {
+      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+    }
+    mark(kev, 4 * k + 3);
+  }
+  mark(ev, 4);
+  // corrective motion and integration (Eq. 20)
+  if (!standard) contact_force_solve(s, C.d_f, S.d_sol);             // A^-1 H^T f (last W_H's Z)
+  launch_integrate(s);
+  launch_store_forces(s, nc);
+  launch_advance_time(s);
+  if (standard) launch_fill(s, C.d_WH, 9L * nc * nc, 0.0);           // no W_H in this scheme
+  mark(ev, 5);
+}
+
+bool same_opts(const icr_step_opts &a, const icr_step_opts &b) {
+  return a.n_contacts == b.n_contacts && a.n_newton == b.n_newton && a.max_sweeps == b.max_sweeps &&
+         a.j_inner == b.j_inner && a.tol == b.tol && a.timing == b.timing && a.scheme == b.scheme;
+}
+
+}  // namespace
 
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep) {
   return guarded(s, [&] {
@@ -510,65 +592,49 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     REQUIRE(opt->n_newton >= 1 && opt->n_newton <= 64, "n_newton must be in [1, 64]");
     REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
     REQUIRE(opt->scheme == 0 || opt->scheme == 1, "scheme must be 0 (fast) or 1 (standard)");
-    const bool standard = opt->scheme == 1;
+    REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");
     ensure_contact_buffers(s, nc);
     ensure_rhs_capacity(s, nc);
     hipStream_t st = s->stream;
     auto &C = s->con;
     auto &S = s->st;
-    const double h = s->mesh.h, t0 = S.t, t1 = S.t + h;
-    const bool timing = opt->timing != 0;
     const int nk = opt->n_newton;
-    std::vector<hipEvent_t> ev, kev;
-    if (timing) {
-      ev.resize(6);
-      kev.resize(4 * nk);
-      for (auto &e : ev) ICR_HIP(hipEventCreate(&e));
-      for (auto &e : kev) ICR_HIP(hipEventCreate(&e));
+    if (!S.obs_valid || std::memcmp(&S.obs_host, obs, sizeof(icr_obstacle)) != 0) {
+      launch_set_ctx(s, obs, nullptr);
+      S.obs_host = *obs;
+      S.obs_valid = true;
     }
-    auto mark = [&](std::vector<hipEvent_t> &v, int i) {
-      if (timing) ICR_HIP(hipEventRecord(v[i], st));
-    };
-    mark(ev, 0);
-    // free motion (Eq. 5, 12)
-    launch_free_rhs(s, S.d_q, S.d_v, S.d_b);
-    single_rhs_solve(s, S.d_b, S.d_dvfree);
-    launch_axpy_qfree(s);
-    mark(ev, 1);
-    launch_select_contacts(s, nc, *obs, t0, t1);
-    mark(ev, 2);
-    if (!standard) build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
-    mark(ev, 3);
-    for (int k = 0; k < nk; ++k) {
-      launch_directions(s, nc, *obs, t0, t1, k == 0);
-      mark(kev, 4 * k);
-      if (standard)
-        build_WH_device(s, nc, C.d_nodes_c, C.d_W, false, C.d_C);   // W_k = J_k A^-1 J_k^T
-      else
-        launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);                // W_k = C_k W_H C_k^T
-      mark(kev, 4 * k + 1);
-      launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
-                 C.d_sweeps + k, C.d_eps + k, C.pgs);
-      mark(kev, 4 * k + 2);
-      launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
-      if (standard) {
-        contact_force_solve(s, C.d_lam, S.d_sol);                      // A^-1 J_k^T lambda_k
-        launch_standard_proximity(s, nc);                               // p_k = H (q_free + h^2 sol)
-      } else {
-        launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+    if (opt->graph) {
+      auto &G = s->sg;
+      if (!G.valid || G.epoch != s->epoch || !same_opts(G.key, *opt)) {
+        G.reset();
+        if (!G.cap) ICR_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        s->stream = G.cap;
+        try {
+          ICR_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+          enqueue_step(s, opt);
+          ICR_HIP(hipStreamEndCapture(G.cap, &G.graph));
+        } catch (...) {
+          hipGraph_t junk = nullptr;
+          (void)hipStreamEndCapture(G.cap, &junk);
+          if (junk) (void)hipGraphDestroy(junk);
+          s->stream = st;
+          G.reset();
+          throw;
+        }
+        s->stream = st;
+        ICR_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        G.key = *opt;
+        G.epoch = s->epoch;
+        G.valid = true;
       }
-      mark(kev, 4 * k + 3);
+      ICR_HIP(hipGraphLaunch(G.exec, st));
+    } else {
+      enqueue_step(s, opt);
     }
-    mark(ev, 4);
-    // corrective motion and integration (Eq. 20)
-    if (!standard) contact_force_solve(s, C.d_f, S.d_sol);             // A^-1 H^T f (last W_H's Z)
-    launch_integrate(s);
-    launch_store_forces(s, nc);
-    mark(ev, 5);
-    S.t = t1;
+    S.t = S.t + s->mesh.h;
     s->stepped = true;
     s->last_nc = nc;
-    if (standard) ICR_HIP(hipMemsetAsync(C.d_WH, 0, sizeof(double) * 9L * nc * nc, st));
     if (rep) {
       std::memset(rep, 0, sizeof(*rep));
       rep->t = S.t;
@@ -583,29 +649,23 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
         if (v == ICR_STICK) rep->n_stick++;
         if (v == ICR_SLIP) rep->n_slip++;
       }
-      if (timing) {
-        auto el = [&](hipEvent_t a, hipEvent_t b) {
-          float ms = 0;
-          ICR_HIP(hipEventElapsedTime(&ms, a, b));
-          return (double)ms;
-        };
-        rep->ms_total = el(ev[0], ev[5]);
-        rep->ms_free = el(ev[0], ev[1]);
-        rep->ms_contacts = el(ev[1], ev[2]);
-        rep->ms_build_WH = el(ev[2], ev[3]);
-        rep->ms_newton = el(ev[3], ev[4]);
-        rep->ms_correct = el(ev[4], ev[5]);
+      if (opt->timing) {
+        std::vector<unsigned long long> ts(6 + 4 * nk);
+        ICR_HIP(hipMemcpy(ts.data(), S.d_stamps, sizeof(unsigned long long) * ts.size(), hipMemcpyDeviceToHost));
+        const double per_ms = s->clock_khz > 0 ? (double)s->clock_khz : 1e5;
+        auto el = [&](int a, int b) { return (double)(long long)(ts[b] - ts[a]) / per_ms; };
+        rep->ms_total = el(0, 5);
+        rep->ms_free = el(0, 1);
+        rep->ms_contacts = el(1, 2);
+        rep->ms_build_WH = el(2, 3);
+        rep->ms_newton = el(3, 4);
+        rep->ms_correct = el(4, 5);
         for (int k = 0; k < nk; ++k) {
-          rep->ms_update_W += el(kev[4 * k], kev[4 * k + 1]);
-          rep->ms_pgs += el(kev[4 * k + 1], kev[4 * k + 2]);
-          rep->ms_corr += el(kev[4 * k + 2], kev[4 * k + 3]);
+          rep->ms_update_W += el(6 + 4 * k, 6 + 4 * k + 1);
+          rep->ms_pgs += el(6 + 4 * k + 1, 6 + 4 * k + 2);
+          rep->ms_corr += el(6 + 4 * k + 2, 6 + 4 * k + 3);
         }
       }
-    }
-    if (timing) {
-      if (!rep) ICR_HIP(hipStreamSynchronize(st));
-      for (auto &e : ev) (void)hipEventDestroy(e);
-      for (auto &e : kev) (void)hipEventDestroy(e);
     }
     return ICR_OK;
   });
@@ -630,6 +690,7 @@ icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double 
     ICR_HIP(hipMemcpyAsync(s->st.d_q, q, bytes, hipMemcpyDeviceToDevice, s->stream));
     ICR_HIP(hipMemcpyAsync(s->st.d_v, v, bytes, hipMemcpyDeviceToDevice, s->stream));
     s->st.t = t;
+    launch_set_ctx(s, nullptr, &t);
     return ICR_OK;
   });
 }

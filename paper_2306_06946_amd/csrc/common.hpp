@@ -191,14 +191,80 @@ __device__ inline void AccV::acc(const double *A, long ars, long acs, const doub
   tile_gemm_acc(c, A, ars, acs, B, brs, bcs, M, N, k0, k1, sA, sB);
 }
 
+// Register-prefetched staging: the next K-chunk is fetched from global memory
+// into registers while the MFMAs of the current chunk run from LDS.
+__device__ inline void load_chunk_regs(const double *__restrict__ A, long ars, long acs, const double *__restrict__ B,
+                                       long brs, long bcs, int M, int N, int kb, int k1, double ra[4],
+                                       double rb[4]) {
+  const int tid = threadIdx.x;
+  const bool a_rowfast = (ars == 1);
+  const bool b_colfast = (bcs == 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int i, k;
+    if (a_rowfast) {
+      i = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      i = e >> 4;
+    }
+    int kk = kb + k;
+    ra[q] = (i < M && kk < k1) ? A[(long)i * ars + (long)kk * acs] : 0.0;
+    int j;
+    if (b_colfast) {
+      j = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      j = e >> 4;
+    }
+    kk = kb + k;
+    rb[q] = (j < N && kk < k1) ? B[(long)kk * brs + (long)j * bcs] : 0.0;
+  }
+}
+
+__device__ inline void store_chunk_lds(bool a_rowfast, bool b_colfast, const double ra[4], const double rb[4],
+                                       double *sA, double *sB) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int i, k;
+    if (a_rowfast) {
+      i = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      i = e >> 4;
+    }
+    sA[k * TILE + i] = ra[q];
+    int j;
+    if (b_colfast) {
+      j = e & 63;
+      k = e >> 6;
+    } else {
+      k = e & 15;
+      j = e >> 4;
+    }
+    sB[k * TILE + j] = rb[q];
+  }
+}
+
 __device__ inline void AccM::acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M,
                                  int N, int k0, int k1, double *sA, double *sB) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
   const int li = l & 15, lk = l >> 4;
+  const bool a_rowfast = (ars == 1), b_colfast = (bcs == 1);
+  if (k0 >= k1) return;
+  double ra[4], rb[4];
+  load_chunk_regs(A, ars, acs, B, brs, bcs, M, N, k0, k1, ra, rb);
   for (int kb = k0; kb < k1; kb += KT) {
-    stage_chunk(A, ars, acs, B, brs, bcs, M, N, kb, k1, sA, sB);
+    store_chunk_lds(a_rowfast, b_colfast, ra, rb, sA, sB);
     __syncthreads();
+    if (kb + KT < k1) load_chunk_regs(A, ars, acs, B, brs, bcs, M, N, kb + KT, k1, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int k = kk + lk;

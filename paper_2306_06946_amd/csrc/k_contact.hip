@@ -37,13 +37,15 @@ __device__ double signed_distance(const icr_obstacle &o, double t, const double 
 // them by node id; gather mu, p_free = H q_free, p_start = H q, warm start.
 __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restrict__ cand,
                                                  const double *__restrict__ qf, const double *__restrict__ q,
-                                                 icr_obstacle obs, double t1, int K,
+                                                 const StepCtx *__restrict__ ctx, int K,
                                                  const double *__restrict__ mu_node,
                                                  const double *__restrict__ node_force, int *__restrict__ nodes_c,
                                                  double *__restrict__ mu_c, double *__restrict__ pfree,
                                                  double *__restrict__ pstart, double *__restrict__ finit) {
   __shared__ unsigned long long key[4096];
   __shared__ int nid[4096];
+  const icr_obstacle obs = ctx->obs;
+  const double t1 = ctx->t0 + ctx->h;
   int n2 = 1;
   while (n2 < ncand) n2 <<= 1;
   for (int i = threadIdx.x; i < n2; i += blockDim.x) {
@@ -111,12 +113,14 @@ __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restric
 
 // Frames C_k and gaps at p_{k-1}; d_k = delta - C_k (p - p_free); warm start
 // lambda = C_k f with f the previous world-frame force.
-__global__ void k_directions(int nc, icr_obstacle obs, double t0, double t1, const double *__restrict__ p,
+__global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const double *__restrict__ p,
                              const double *__restrict__ pfree, const double *__restrict__ pstart,
                              const double *__restrict__ fprev, double *__restrict__ C, double *__restrict__ dk,
                              double *__restrict__ lam) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  const icr_obstacle obs = ctx->obs;
+  const double t0 = ctx->t0, t1 = ctx->t0 + ctx->h;
   double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
   double n[3];
   double phi = signed_distance(obs, t1, pc, n);
@@ -256,6 +260,111 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
   double den = w[0][0] + mu * (w[0][1] * u0 + w[0][2] * u1);
   if (den <= 0.0) den = w[0][0];
   double lam_n = -d[0] / den;
+  out.l[0] = lam_n;
+  out.l[1] = mu * lam_n * u0;
+  out.l[2] = mu * lam_n * u1;
+  out.st = ICR_SLIP;
+  return out;
+}
+
+// Per-contact record of the active-set PGS, computed once per active set:
+// the symmetric 3x3 block of h^2 W_aa, its Cholesky factor, the reciprocals
+// of the factor's diagonal and the slip shift kappa = (w11 + w22) / 2.
+constexpr int PGS_REC = 16;
+__device__ inline void make_record(const double w[3][3], double *rec) {
+  double l00 = sqrt(w[0][0]);
+  double l10 = w[1][0] / l00, l20 = w[2][0] / l00;
+  double l11 = sqrt(w[1][1] - l10 * l10);
+  double l21 = (w[2][1] - l20 * l10) / l11;
+  double l22 = sqrt(w[2][2] - l20 * l20 - l21 * l21);
+  rec[0] = w[0][0];
+  rec[1] = w[0][1];
+  rec[2] = w[0][2];
+  rec[3] = w[1][1];
+  rec[4] = w[1][2];
+  rec[5] = w[2][2];
+  rec[6] = l10;
+  rec[7] = l20;
+  rec[8] = l21;
+  rec[9] = 1.0 / l00;
+  rec[10] = 1.0 / l11;
+  rec[11] = 1.0 / l22;
+  rec[12] = 0.5 * (w[1][1] + w[2][2]);
+  rec[13] = rec[14] = rec[15] = 0.0;
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (full double precision for the well-scaled positive values used here).
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ inline double frsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Same branches and fixed point as local_solve, with the factor of the
+// diagonal block precomputed and divisions replaced by refined reciprocals.
+__device__ Local local_solve_rec(const double *rc, const double d[3], double mu, int j_inner) {
+  Local out;
+  if (d[0] >= 0.0) {
+    out.l[0] = out.l[1] = out.l[2] = 0.0;
+    out.st = ICR_SEPARATE;
+    return out;
+  }
+  const double w00 = rc[0], w01 = rc[1], w02 = rc[2], w11 = rc[3], w12 = rc[4], w22 = rc[5];
+  const double l10 = rc[6], l20 = rc[7], l21 = rc[8], r00 = rc[9], r11 = rc[10], r22 = rc[11], kap = rc[12];
+  double y0 = d[0] * r00;
+  double y1 = (d[1] - l10 * y0) * r11;
+  double y2 = (d[2] - l20 * y0 - l21 * y1) * r22;
+  double x2 = y2 * r22;
+  double x1 = (y1 - l21 * x2) * r11;
+  double x0 = (y0 - l10 * x1 - l20 * x2) * r00;
+  double ln = -x0, lt1 = -x1, lt2 = -x2;
+  if (ln > 0.0 && lt1 * lt1 + lt2 * lt2 <= (mu * ln) * (mu * ln)) {
+    out.l[0] = ln;
+    out.l[1] = lt1;
+    out.l[2] = lt2;
+    out.st = ICR_STICK;
+    return out;
+  }
+  double u0, u1;
+  double nt2 = lt1 * lt1 + lt2 * lt2;
+  if (nt2 > 0.0) {
+    double inv = frsqrt(nt2);
+    u0 = lt1 * inv;
+    u1 = lt2 * inv;
+  } else {
+    double nd2 = d[1] * d[1] + d[2] * d[2];
+    if (nd2 > 0.0) {
+      double inv = frsqrt(nd2);
+      u0 = -d[1] * inv;
+      u1 = -d[2] * inv;
+    } else {
+      u0 = 1.0;
+      u1 = 0.0;
+    }
+  }
+  for (int it = 0; it < j_inner; ++it) {
+    double den = w00 + mu * (w01 * u0 + w02 * u1);
+    if (den <= 0.0) den = w00;
+    double lam_n = -d[0] * frcp(den);
+    double a1 = mu * lam_n * u0, a2 = mu * lam_n * u1;
+    double r1 = d[1] + w01 * lam_n + (w11 - kap) * a1 + w12 * a2;
+    double r2 = d[2] + w02 * lam_n + w12 * a1 + (w22 - kap) * a2;
+    double s2 = r1 * r1 + r2 * r2;
+    if (s2 > 0.0) {
+      double inv = frsqrt(s2);
+      u0 = -r1 * inv;
+      u1 = -r2 * inv;
+    }
+  }
+  double den = w00 + mu * (w01 * u0 + w02 * u1);
+  if (den <= 0.0) den = w00;
+  double lam_n = -d[0] * frcp(den);
   out.l[0] = lam_n;
   out.l[1] = mu * lam_n * u0;
   out.l[2] = mu * lam_n * u1;
@@ -437,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
                                                      int max_sweeps, double tol, int j_inner,
                                                      int *__restrict__ sweeps_out, double *__restrict__ eps_out,
                                                      double *__restrict__ Wss, double *__restrict__ Wns,
-                                                     int *__restrict__ ctl) {
+                                                     double *__restrict__ recs, int *__restrict__ ctl) {
   __shared__ double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3];
   __shared__ double gn[PGS_MAX_NC];
   __shared__ int Sidx[PGS_SMAX];
@@ -511,6 +620,13 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       }
       __threadfence_block();
       __syncthreads();
+      for (int i = tid; i < nS; i += 1024) {
+        double wb[3][3];
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q) wb[p][q] = Wss[(long)(3 * i + p) * ldS + 3 * i + q];
+        make_record(wb, recs + (long)PGS_REC * i);
+      }
+      __threadfence_block();
       // ---- gaps from scratch (lambda is zero outside S)
       for (int r = wv; r < ldS; r += 16) {
         double a = 0.0;
@@ -533,15 +649,14 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     double dsum = 0.0;
     const int r0 = tid, r1 = tid + 1024;
     double pf0[3] = {0, 0, 0}, pf1[3] = {0, 0, 0};
-    double w[3][3];
+    double rc[13];
     if (nS > 0) {
       for (int b = 0; b < 3; ++b) {
         if (r0 < ldS) pf0[b] = Wss[(long)b * ldS + r0];
         if (r1 < ldS) pf1[b] = Wss[(long)b * ldS + r1];
       }
       if (wv == 0)
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) w[i][j] = Wss[(long)i * ldS + j];
+        for (int q = 0; q < 13; ++q) rc[q] = recs[q];
     }
     __syncthreads();
     for (int i = 0; i < nS; ++i) {
@@ -549,8 +664,10 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
         const int a = Sidx[i];
         double lo[3], dd[3];
         for (int q = 0; q < 3; ++q) lo[q] = lamS[3 * i + q];
-        for (int q = 0; q < 3; ++q) dd[q] = gS[3 * i + q] - (w[q][0] * lo[0] + w[q][1] * lo[1] + w[q][2] * lo[2]);
-        Local rs = local_solve(w, dd, mu[a], j_inner);
+        dd[0] = gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
+        dd[1] = gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
+        dd[2] = gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
+        Local rs = local_solve_rec(rc, dd, mu[a], j_inner);
         double dl[3];
         for (int q = 0; q < 3; ++q) {
           dl[q] = rs.l[q] - lo[q];
@@ -563,11 +680,8 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
           }
           status[a] = (int8_t)rs.st;
         }
-        if (i + 1 < nS) {
-          const long base = (long)(3 * (i + 1)) * ldS + 3 * (i + 1);
-          for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 3; ++q) w[p][q] = Wss[base + (long)p * ldS + q];
-        }
+        if (i + 1 < nS)
+          for (int q = 0; q < 13; ++q) rc[q] = recs[(long)PGS_REC * (i + 1) + q];
       }
       __syncthreads();
       const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
@@ -678,6 +792,21 @@ __global__ void k_std_proximity(int nc, const int *__restrict__ nodes, const dou
   for (int a = 0; a < 3; ++a) p[3 * c + a] = qf[3 * v + a] + h2 * sol[3 * v + a];
 }
 
+__global__ void k_set_ctx(StepCtx *ctx, icr_obstacle obs, int set_obs, double t0, int set_t, double h) {
+  if (set_obs) ctx->obs = obs;
+  if (set_t) ctx->t0 = t0;
+  ctx->h = h;
+}
+
+__global__ void k_advance_time(StepCtx *ctx) { ctx->t0 = ctx->t0 + ctx->h; }
+
+__global__ void k_stamp(unsigned long long *ts, int slot) { ts[slot] = wall_clock64(); }
+
+__global__ void k_copy_int(int n, const int *__restrict__ a, int *__restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
 __global__ void k_clear_nodes(int nc, const int *__restrict__ nodes, double *__restrict__ out) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
@@ -687,18 +816,17 @@ __global__ void k_clear_nodes(int nc, const int *__restrict__ nodes, double *__r
 
 }  // namespace
 
-void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1) {
-  (void)t0;
+void launch_select_contacts(icr_scene *s, int nc) {
   auto &C = s->con;
-  k_select<<<1, 1024, 0, s->stream>>>(C.count, C.d_cand, s->st.d_qfree, s->st.d_q, obs, t1, nc, C.d_mu_node,
+  k_select<<<1, 1024, 0, s->stream>>>(C.count, C.d_cand, s->st.d_qfree, s->st.d_q, s->st.d_ctx, nc, C.d_mu_node,
                                       s->st.d_node_force, C.d_nodes_c, C.d_mu, C.d_pfree, C.d_pstart, C.d_f);
   ICR_LAUNCH_CHECK();
 }
 
-void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first) {
+void launch_directions(icr_scene *s, int nc, bool first) {
   auto &C = s->con;
   const double *p = first ? C.d_pfree : C.d_p;
-  k_directions<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, obs, t0, t1, p, C.d_pfree, C.d_pstart, C.d_f, C.d_C,
+  k_directions<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->st.d_ctx, p, C.d_pfree, C.d_pstart, C.d_f, C.d_C,
                                                      C.d_dk, C.d_lam);
   ICR_LAUNCH_CHECK();
 }
@@ -716,7 +844,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
   k_pgs_active<<<1, 1024, 0, st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
-                                   eps_dev, wk.Wss, wk.Wns, wk.ctl);
+                                   eps_dev, wk.Wss, wk.Wns, wk.recs, wk.ctl);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
   k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
@@ -725,6 +853,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
 }
 
 size_t pgs_wss_elems() { return (size_t)PGS_S3 * PGS_S3; }
+size_t pgs_rec_elems() { return (size_t)PGS_REC * PGS_SMAX; }
 size_t pgs_wns_elems(int nc) { return (size_t)nc * PGS_S3; }
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {
@@ -736,6 +865,23 @@ void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_
                       double *p) {
   const int m = 3 * nc;
   k_proximity<<<cdiv(m, 4), 256, 0, st>>>(m, WH, p_free, f, h * h, p);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_set_ctx(icr_scene *s, const icr_obstacle *obs, const double *t0) {
+  icr_obstacle o{};
+  if (obs) o = *obs;
+  k_set_ctx<<<1, 1, 0, s->stream>>>(s->st.d_ctx, o, obs ? 1 : 0, t0 ? *t0 : 0.0, t0 ? 1 : 0, s->mesh.h);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_stamp(icr_scene *s, int slot) {
+  k_stamp<<<1, 1, 0, s->stream>>>(s->st.d_stamps, slot);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_advance_time(icr_scene *s) {
+  k_advance_time<<<1, 1, 0, s->stream>>>(s->st.d_ctx);
   ICR_LAUNCH_CHECK();
 }
 
@@ -754,7 +900,8 @@ void launch_store_forces(icr_scene *s, int nc) {
   }
   k_scatter_force<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, S.d_node_force);
   ICR_LAUNCH_CHECK();
-  ICR_HIP(hipMemcpyAsync(S.d_prev_nodes, s->con.d_nodes_c, sizeof(int) * nc, hipMemcpyDeviceToDevice, s->stream));
+  k_copy_int<<<cdiv(nc, 256), 256, 0, s->stream>>>(nc, s->con.d_nodes_c, S.d_prev_nodes);
+  ICR_LAUNCH_CHECK();
   S.prev_nc = nc;
 }
 

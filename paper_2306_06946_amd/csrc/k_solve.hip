@@ -257,85 +257,89 @@ __global__ void k_fwd1_assemble(const SupDev *__restrict__ sup, const int *__res
   }
 }
 
-// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]   (rows tiled by 64)
+// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]: 16 rows x 16 k-phases per block
 __global__ __launch_bounds__(256) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                    const double *__restrict__ linv, const double *__restrict__ x1,
                                                    double *__restrict__ y) {
-  __shared__ double part[4][64];
+  __shared__ double part[16][17];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
-  const int i0 = 64 * blockIdx.x;
+  const int i0 = 16 * blockIdx.x;
   if (i0 >= n3) return;
-  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int r = threadIdx.x & 15, ph = threadIdx.x >> 4;
   const int i = i0 + r;
-  const int kend = min(n3, i0 + 64);
+  const int kend = min(n3, i0 + 16);
   const double *Li = linv + S.linv_off;
   const double *xs = x1 + S.x1_off;
   double acc = 0.0;
   if (i < n3)
-    for (int k = ph; k < kend; k += 4) acc = fma(Li[i + (long)k * n3], xs[k], acc);
+    for (int k = ph; k < kend; k += 16) acc = fma(Li[i + (long)k * n3], xs[k], acc);
   part[ph][r] = acc;
   __syncthreads();
-  if (ph == 0 && i < n3) y[3 * S.col0 + i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+  if (ph == 0 && i < n3) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += part[q][r];
+    y[3 * S.col0 + i] = t;
+  }
 }
 
-// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]
+// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]: 16 rows x 16 k-phases per block
 __global__ __launch_bounds__(256) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                   const double *__restrict__ front, const double *__restrict__ y,
                                                   double *__restrict__ x1) {
-  __shared__ double part[4][64];
+  __shared__ double part[16][17];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int i0 = 64 * blockIdx.x;
+  const int i0 = 16 * blockIdx.x;
   if (i0 >= b3) return;
-  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int r = threadIdx.x & 15, ph = threadIdx.x >> 4;
   const int i = i0 + r;
   const double *F = front + S.front_off + n3;
   const double *ys = y + 3 * S.col0;
   double acc = 0.0;
   if (i < b3)
-    for (int k = ph; k < n3; k += 4) acc = fma(F[i + (long)k * f], ys[k], acc);
+    for (int k = ph; k < n3; k += 16) acc = fma(F[i + (long)k * f], ys[k], acc);
   part[ph][r] = acc;
   __syncthreads();
-  if (ph == 0 && i < b3) x1[S.x1_off + n3 + i] -= (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+  if (ph == 0 && i < b3) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += part[q][r];
+    x1[S.x1_off + n3 + i] -= t;
+  }
 }
 
-// y_s[j] -= sum_i L21(i, j) x[below row i]  (16 columns per block, 16 lanes per column)
+// y_s[j] -= sum_i L21(i, j) x[below row i]: one wave per column, 4 columns per block
 __global__ __launch_bounds__(256) void k_bwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                   const int *__restrict__ rows, const double *__restrict__ front,
                                                   const double *__restrict__ xp, double *__restrict__ y) {
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int j = 16 * blockIdx.x + (threadIdx.x >> 4);
-  const int l = threadIdx.x & 15;
-  if (16 * (int)blockIdx.x >= n3) return;
+  const int j = 4 * blockIdx.x + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (j >= n3) return;
+  const double *F = front + S.front_off + n3 + (long)j * f;
+  const int *rw = rows + S.rows_off;
   double acc = 0.0;
-  if (j < n3) {
-    const double *F = front + S.front_off + n3 + (long)j * f;
-    const int *rw = rows + S.rows_off;
-    for (int i = l; i < b3; i += 16) acc = fma(F[i], xp[3 * rw[i / 3] + i % 3], acc);
-  }
-  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (l == 0 && j < n3) y[3 * S.col0 + j] -= acc;
+  for (int i = l; i < b3; i += 64) acc = fma(F[i], xp[3 * rw[i / 3] + i % 3], acc);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (l == 0) y[3 * S.col0 + j] -= acc;
 }
 
-// xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]
+// xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]: one wave per column
 __global__ __launch_bounds__(256) void k_bwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                    const double *__restrict__ linv, const double *__restrict__ y,
                                                    double *__restrict__ xp) {
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
-  const int j = 16 * blockIdx.x + (threadIdx.x >> 4);
-  const int l = threadIdx.x & 15;
-  if (16 * (int)blockIdx.x >= n3) return;
+  const int j = 4 * blockIdx.x + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (j >= n3) return;
+  const double *Lc = linv + S.linv_off + (long)j * n3;
+  const double *ys = y + 3 * S.col0;
   double acc = 0.0;
-  if (j < n3) {
-    const double *Lc = linv + S.linv_off + (long)j * n3;
-    const double *ys = y + 3 * S.col0;
-    for (int i = j + l; i < n3; i += 16) acc = fma(Lc[i], ys[i], acc);
-  }
-  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (l == 0 && j < n3) xp[3 * S.col0 + j] = acc;
+  for (int i = j + l; i < n3; i += 64) acc = fma(Lc[i], ys[i], acc);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (l == 0) xp[3 * S.col0 + j] = acc;
 }
 
 __global__ void k_unpermute_vec(int N, const int *__restrict__ perm, const double *__restrict__ xp,
@@ -362,10 +366,10 @@ void backward_solve(icr_scene *s, double *x) {
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
     if (L.max_b3 > 0) {
-      k_bwd1_off<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
+      k_bwd1_off<<<dim3(cdiv(L.max_n3, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
       ICR_LAUNCH_CHECK();
     }
-    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
+    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
     ICR_LAUNCH_CHECK();
   }
   k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
@@ -421,10 +425,10 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
     k_fwd1_assemble<<<dim3(cdiv(L.max_f3, 256), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
                                                                           F.d_invmap, F.d_perm, b, F.d_x1);
     ICR_LAUNCH_CHECK();
-    k_fwd1_diag<<<dim3(cdiv(L.max_n3, 64), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
+    k_fwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
     ICR_LAUNCH_CHECK();
     if (L.max_b3 > 0) {
-      k_fwd1_off<<<dim3(cdiv(L.max_b3, 64), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
+      k_fwd1_off<<<dim3(cdiv(L.max_b3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
       ICR_LAUNCH_CHECK();
     }
   }
@@ -444,9 +448,15 @@ void contact_force_solve(icr_scene *s, const double *f, double *x) {
   backward_solve(s, x);
 }
 
+void launch_fill(icr_scene *s, double *x, long n, double v) {
+  k_fill<<<(unsigned)std::min<long>(1024, (n + 255) / 256), 256, 0, s->stream>>>(n, v, x);
+  ICR_LAUNCH_CHECK();
+}
+
 void ensure_rhs_capacity(icr_scene *s, int nc) {
   auto &F = s->fac;
   if (nc <= F.nc_cap) return;
+  s->epoch++;
   ICR_HIP(hipStreamSynchronize(s->stream));
   F.rhs_arena.release();
   long long xo = 0, zo = 0;

@@ -95,7 +95,7 @@ struct Factor {
 // Work buffers of the PGS kernels: start gaps g [m], compact couplings
 // (pgs_wss_elems(), pgs_wns_elems(nc) doubles) and a 2-int control block.
 struct PgsWork {
-  double *g = nullptr, *Wss = nullptr, *Wns = nullptr;
+  double *g = nullptr, *Wss = nullptr, *Wns = nullptr, *recs = nullptr;
   int *ctl = nullptr;
 };
 
@@ -116,7 +116,19 @@ struct Contacts {
   Arena arena;
 };
 
+// Per-step parameters kept in device memory, so a captured step graph can be
+// replayed: the obstacle and the time at the start of the step.
+struct StepCtx {
+  icr_obstacle obs;
+  double t0;
+  double h;
+};
+
 struct State {
+  StepCtx *d_ctx = nullptr;
+  unsigned long long *d_stamps = nullptr;   // device-clock phase stamps of the last timed step
+  icr_obstacle obs_host{};      // last obstacle written to d_ctx
+  bool obs_valid = false;
   double *d_q = nullptr, *d_v = nullptr, *d_qrest = nullptr;
   double *d_b = nullptr, *d_dvfree = nullptr, *d_qfree = nullptr, *d_sol = nullptr;
   double *d_node_force = nullptr;   // world-frame force per node from the previous step
@@ -126,6 +138,23 @@ struct State {
 };
 
 }  // namespace icr
+
+// A captured icr_step launch sequence and the options it was captured for.
+struct StepGraph {
+  bool valid = false;
+  icr_step_opts key{};
+  long epoch = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    valid = false;
+  }
+};
 
 struct icr_scene {
   hipStream_t stream = nullptr;
@@ -139,6 +168,9 @@ struct icr_scene {
   icr::Arena mesh_arena, fac_arena, state_arena;
   int last_nc = 0;
   int last_build_nc = 0;   // contact count of the last multi-RHS forward solve (Z valid for it)
+  long epoch = 0;          // bumped whenever device buffers are (re)allocated
+  int clock_khz = 0;       // device wall-clock rate used by the phase stamps
+  StepGraph sg;
 };
 
 namespace icr {
@@ -158,17 +190,22 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x);
 // x = A^-1 H^T f for the contacts of the last build_WH_device call (reuses Z).
 void contact_force_solve(icr_scene *s, const double *f, double *x);
 void ensure_rhs_capacity(icr_scene *s, int nc);
+void launch_fill(icr_scene *s, double *x, long n, double v);
 // W_H = H A^-1 H^T, or J A^-1 J^T with J = C H when per-contact frames
 // [nc*9] are given (the standard rebuild of Algorithm 2).
 void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate,
                      const double *frames = nullptr);
 
 // k_contact.hip
-void launch_select_contacts(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1);
-void launch_directions(icr_scene *s, int nc, const icr_obstacle &obs, double t0, double t1, bool first);
+void launch_select_contacts(icr_scene *s, int nc);
+void launch_directions(icr_scene *s, int nc, bool first);
+void launch_set_ctx(icr_scene *s, const icr_obstacle *obs, const double *t0);
+void launch_advance_time(icr_scene *s);
+void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 2560;
 size_t pgs_wss_elems();
+size_t pgs_rec_elems();
 size_t pgs_wns_elems(int nc);
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,

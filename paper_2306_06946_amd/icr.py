@@ -33,7 +33,8 @@ class Obstacle(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("n_contacts", C.c_int32), ("n_newton", C.c_int32), ("max_sweeps", C.c_int32),
-                ("j_inner", C.c_int32), ("tol", C.c_double), ("timing", C.c_int32), ("scheme", C.c_int32)]
+                ("j_inner", C.c_int32), ("tol", C.c_double), ("timing", C.c_int32), ("scheme", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class StepReport(C.Structure):
@@ -227,7 +228,7 @@ class Scene:
                                                 _dptr(p, t.float64)))
 
     def step(self, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, timing=False,
-             report=True, standard=False):
+             report=True, standard=False, graph=True):
         ob = Obstacle()
         ob.kind = 1 if obstacle["kind"] == "sphere" else 0
         for i in range(3):
@@ -235,7 +236,8 @@ class Scene:
             ob.vel[i] = float(obstacle["vel"][i])
             ob.normal[i] = float(obstacle["normal"][i])
         ob.radius = float(obstacle.get("radius", 0.0))
-        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, 1 if standard else 0)
+        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, 1 if standard else 0,
+                      1 if graph else 0)
         rep = StepReport()
         self._check(self.L.icr_step(self._h, C.byref(ob), C.byref(op), C.byref(rep) if report else None))
         if not report:
