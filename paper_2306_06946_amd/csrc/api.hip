@@ -74,9 +74,8 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_W = C.arena.alloc<double>(m * m);
   C.pgs.g = C.arena.alloc<double>(m);
   C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
-  C.pgs.Wns = C.arena.alloc<double>(pgs_wns_elems(nc));
-  C.pgs.recs = C.arena.alloc<double>(pgs_rec_elems());
   C.pgs.ctl = C.arena.alloc<int>(2);
+  pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);
   C.d_sweeps = C.arena.alloc<int>(64);
   C.d_eps = C.arena.alloc<double>(64);

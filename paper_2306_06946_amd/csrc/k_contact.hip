@@ -526,71 +526,82 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
 
 // Active-set projected Gauss-Seidel (exact).  In a sweep only contacts with
 // a non-zero force or a negative gap can change; all others are no-ops of
-// Gauss-Seidel.  The kernel keeps the set S of contacts that may change,
-// runs the sequential sweep over S alone with the compact coupling block
-// W~_SS (gathered once per change of S and read from L2, next rows
-// prefetched), and afterwards verifies, for every contact outside S, that it
-// was indeed a no-op at its turn: its gap g_n + sum over the S contacts
-// before it of W~_{n,S} dlambda must be >= 0.  On a violation the violating
-// contacts join S and the sweep is redone from its start state, so the
-// iterates are those of the full sequential sweep.  Contacts outside S keep
-// only their normal gap g_n (all a no-op test needs); the gaps of S contacts
-// are rebuilt from scratch whenever S changes.  If S outgrows PGS_SMAX the
-// kernel hands the remaining sweeps to k_pgs_single (ctl[0] = 1).
-constexpr int PGS_SMAX = 448;
+// Gauss-Seidel.  The kernel keeps the set S of contacts that may change and
+// runs the sequential sweep over S alone, with the compact coupling block
+// W~_SS (gathered once per set, rows for the next contact prefetched into
+// registers) and per-contact records (3x3 block, its factor, mu) in LDS.  It
+// then verifies that every contact outside S was a no-op at its turn, i.e.
+// that its normal gap
+//   g_n(c) = g_n^set(c) + W~_{n(c),S} (lambda^turn - lambda^set) >= 0,
+// with lambda^turn the force of S contacts before c in this sweep and after c
+// from the previous sweep.  Cauchy-Schwarz on the PSD matrix W~ bounds the
+// correction by sqrt(W~_cc) * sum_q sqrt(W~_qq) |lambda^turn_q - lambda^set_q|,
+// which settles almost every contact; the others are evaluated exactly.  On a
+// violation the violating contacts join S and the sweep restarts from its
+// start state, so the iterates are those of the full sequential sweep.  If S
+// outgrows PGS_SMAX the remaining sweeps go to k_pgs_single (ctl[0] = 1).
+constexpr int PGS_SMAX = 512;
 constexpr int PGS_S3 = 3 * PGS_SMAX;
+constexpr int PGS_RW = 14;   // record width in LDS
+struct PgsLds {
+  double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
+  double rec[PGS_SMAX * PGS_RW];
+  double gnSet[PGS_MAX_NC], swn[PGS_MAX_NC];
+  double bc[3];
+  double red[16];
+  int Sidx[PGS_SMAX];
+  int wcount[64];
+  int ulist[PGS_MAX_NC];
+  unsigned char inS[PGS_MAX_NC];
+  int nS, flag, stop, nu;
+};
+
 __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__restrict__ W,
                                                      const double *__restrict__ d, const double *__restrict__ g0,
                                                      const double *__restrict__ mu, double h2,
                                                      double *__restrict__ lam, int8_t *__restrict__ status,
                                                      int max_sweeps, double tol, int j_inner,
                                                      int *__restrict__ sweeps_out, double *__restrict__ eps_out,
-                                                     double *__restrict__ Wss, double *__restrict__ Wns,
-                                                     double *__restrict__ recs, int *__restrict__ ctl) {
-  __shared__ double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3];
-  __shared__ double gn[PGS_MAX_NC];
-  __shared__ int Sidx[PGS_SMAX];
-  __shared__ unsigned char inS[PGS_MAX_NC];
-  __shared__ int wcount[64];
-  __shared__ double bc[3];
-  __shared__ double red[16];
-  __shared__ int sh_nS, sh_flag, stop;
+                                                     double *__restrict__ Wss, int *__restrict__ ctl) {
+  extern __shared__ double lds_raw[];
+  PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   for (int c = tid; c < nc; c += 1024) {
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
-    inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
+    L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
+    L.swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
   }
   if (tid == 0) {
-    stop = 0;
+    L.stop = 0;
     ctl[0] = 0;
     ctl[1] = 0;
   }
   __syncthreads();
   int sweep = 0, nS = 0, ldS = 0;
   double eps = 0.0;
-  bool need_build = true;
+  bool need_build = true, first_build = true;
   while (sweep < max_sweeps) {
     if (need_build) {
       // ---- ordered list of S (ballot per 64-contact window, prefix by thread 0)
       const int nwin = (nc + 63) / 64;
       for (int w = wv; w < nwin; w += 16) {
         const int c = 64 * w + ln;
-        const unsigned long long bal = __ballot(c < nc && inS[c]);
-        if (ln == 0) wcount[w] = __popcll(bal);
+        const unsigned long long bal = __ballot(c < nc && L.inS[c]);
+        if (ln == 0) L.wcount[w] = __popcll(bal);
       }
       __syncthreads();
       if (tid == 0) {
         int acc = 0;
         for (int w = 0; w < nwin; ++w) {
-          int t = wcount[w];
-          wcount[w] = acc;
+          int t = L.wcount[w];
+          L.wcount[w] = acc;
           acc += t;
         }
-        sh_nS = acc;
+        L.nS = acc;
       }
       __syncthreads();
-      nS = sh_nS;
+      nS = L.nS;
       if (nS > PGS_SMAX) {   // hand over: global lambda holds the sweep-start state
         if (tid == 0) {
           ctl[0] = 1;
@@ -600,23 +611,21 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       }
       for (int w = wv; w < nwin; w += 16) {
         const int c = 64 * w + ln;
-        const bool in = c < nc && inS[c];
+        const bool in = c < nc && L.inS[c];
         const unsigned long long bal = __ballot(in);
-        if (in) Sidx[wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+        if (in) L.Sidx[L.wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
       }
       __syncthreads();
       ldS = 3 * nS;
-      for (int r = tid; r < ldS; r += 1024) lamS[r] = lam[3 * Sidx[r / 3] + r % 3];
-      // ---- compact couplings W~_SS and the normal rows W~_{n,S}
+      for (int r = tid; r < ldS; r += 1024) {
+        L.lamS[r] = lam[3 * L.Sidx[r / 3] + r % 3];
+        L.lamSet[r] = L.lamS[r];
+      }
+      // ---- compact couplings W~_SS
       const long ns2 = (long)ldS * ldS;
       for (long e = tid; e < ns2; e += 1024) {
         const int r = (int)(e / ldS), q = (int)(e % ldS);
-        Wss[e] = h2 * W[(3L * Sidx[r / 3] + r % 3) * m + 3L * Sidx[q / 3] + q % 3];
-      }
-      const long nn = (long)nc * ldS;
-      for (long e = tid; e < nn; e += 1024) {
-        const int c = (int)(e / ldS), q = (int)(e % ldS);
-        Wns[e] = h2 * W[(3L * c) * m + 3L * Sidx[q / 3] + q % 3];
+        Wss[e] = h2 * W[(3L * L.Sidx[r / 3] + r % 3) * m + 3L * L.Sidx[q / 3] + q % 3];
       }
       __threadfence_block();
       __syncthreads();
@@ -624,50 +633,62 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
         double wb[3][3];
         for (int p = 0; p < 3; ++p)
           for (int q = 0; q < 3; ++q) wb[p][q] = Wss[(long)(3 * i + p) * ldS + 3 * i + q];
-        make_record(wb, recs + (long)PGS_REC * i);
+        double *rc = L.rec + PGS_RW * i;
+        double tmp[16];
+        make_record(wb, tmp);
+        for (int q = 0; q < 13; ++q) rc[q] = tmp[q];
+        rc[13] = mu[L.Sidx[i]];
       }
-      __threadfence_block();
-      // ---- gaps from scratch (lambda is zero outside S)
-      for (int r = wv; r < ldS; r += 16) {
-        double a = 0.0;
-        for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], lamS[q], a);
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-        if (ln == 0) gS[r] = d[3 * Sidx[r / 3] + r % 3] + a;
-      }
-      for (int c = wv; c < nc; c += 16) {
-        double a = 0.0;
-        for (int q = ln; q < ldS; q += 64) a = fma(Wns[(long)c * ldS + q], lamS[q], a);
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-        if (ln == 0) gn[c] = d[3 * c] + a;
+      // ---- gaps at the set's start state (lambda is zero outside S)
+      if (first_build) {
+        // g0 = d + W~ lambda0 was formed by k_pgs_init for every row
+        for (int r = tid; r < ldS; r += 1024) L.gS[r] = g0[3 * L.Sidx[r / 3] + r % 3];
+        for (int c = tid; c < nc; c += 1024) L.gnSet[c] = g0[3 * c];
+      } else {
+        for (int r = wv; r < ldS; r += 16) {
+          double a = 0.0;
+          for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], L.lamS[q], a);
+          for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+          if (ln == 0) L.gS[r] = d[3 * L.Sidx[r / 3] + r % 3] + a;
+        }
+        for (int c = wv; c < nc; c += 16) {
+          if (L.inS[c]) continue;
+          double a = 0.0;
+          for (int q = ln; q < ldS; q += 64)
+            a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], L.lamS[q], a);
+          for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+          if (ln == 0) L.gnSet[c] = d[3 * c] + a;
+        }
       }
       __syncthreads();
       need_build = false;
+      first_build = false;
     }
     // ---- sweep over S from its start state
-    for (int r = tid; r < ldS; r += 1024) lamS0[r] = lamS[r];
-    if (tid == 0) sh_flag = 0;
+    for (int r = tid; r < ldS; r += 1024) L.lamS0[r] = L.lamS[r];
+    if (tid == 0) {
+      L.flag = 0;
+      L.nu = 0;
+    }
     double dsum = 0.0;
     const int r0 = tid, r1 = tid + 1024;
     double pf0[3] = {0, 0, 0}, pf1[3] = {0, 0, 0};
-    double rc[13];
     if (nS > 0) {
       for (int b = 0; b < 3; ++b) {
         if (r0 < ldS) pf0[b] = Wss[(long)b * ldS + r0];
         if (r1 < ldS) pf1[b] = Wss[(long)b * ldS + r1];
       }
-      if (wv == 0)
-        for (int q = 0; q < 13; ++q) rc[q] = recs[q];
     }
     __syncthreads();
     for (int i = 0; i < nS; ++i) {
       if (wv == 0) {
-        const int a = Sidx[i];
+        const double *rc = L.rec + PGS_RW * i;
         double lo[3], dd[3];
-        for (int q = 0; q < 3; ++q) lo[q] = lamS[3 * i + q];
-        dd[0] = gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
-        dd[1] = gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
-        dd[2] = gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
-        Local rs = local_solve_rec(rc, dd, mu[a], j_inner);
+        for (int q = 0; q < 3; ++q) lo[q] = L.lamS[3 * i + q];
+        dd[0] = L.gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
+        dd[1] = L.gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
+        dd[2] = L.gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
+        Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
         double dl[3];
         for (int q = 0; q < 3; ++q) {
           dl[q] = rs.l[q] - lo[q];
@@ -675,19 +696,17 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
         }
         if (ln == 0) {
           for (int q = 0; q < 3; ++q) {
-            bc[q] = dl[q];
-            lamS[3 * i + q] = rs.l[q];
+            L.bc[q] = dl[q];
+            L.lamS[3 * i + q] = rs.l[q];
           }
-          status[a] = (int8_t)rs.st;
+          status[L.Sidx[i]] = (int8_t)rs.st;
         }
-        if (i + 1 < nS)
-          for (int q = 0; q < 13; ++q) rc[q] = recs[(long)PGS_REC * (i + 1) + q];
       }
       __syncthreads();
-      const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
+      const double d0 = L.bc[0], d1 = L.bc[1], d2 = L.bc[2];
       if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
-        if (r0 < ldS) gS[r0] += pf0[0] * d0 + pf0[1] * d1 + pf0[2] * d2;
-        if (r1 < ldS) gS[r1] += pf1[0] * d0 + pf1[1] * d1 + pf1[2] * d2;
+        if (r0 < ldS) L.gS[r0] += pf0[0] * d0 + pf0[1] * d1 + pf0[2] * d2;
+        if (r1 < ldS) L.gS[r1] += pf1[0] * d0 + pf1[1] * d1 + pf1[2] * d2;
       }
       if (i + 1 < nS) {
         const long base = (long)(3 * (i + 1)) * ldS;
@@ -698,50 +717,62 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       }
       __syncthreads();
     }
-    // ---- verify the skipped contacts and advance their normal gaps
-    for (int c = wv; c < nc; c += 16) {
-      if (inS[c]) continue;
-      double ab = 0.0, aa = 0.0;
+    // ---- verify the skipped contacts
+    // bound factor B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
+    double bpart = 0.0;
+    for (int r = tid; r < ldS; r += 1024) {
+      const double *rc = L.rec + PGS_RW * (r / 3);
+      const double wqq = (r % 3 == 0) ? rc[0] : ((r % 3 == 1) ? rc[3] : rc[5]);
+      const double dv = fmax(fabs(L.lamS[r] - L.lamSet[r]), fabs(L.lamS0[r] - L.lamSet[r]));
+      bpart += sqrt(wqq) * dv;
+    }
+    const double Bsum = block_sum(bpart, L.red);
+    if (tid == 0) L.red[0] = Bsum;
+    __syncthreads();
+    const double B = L.red[0] * (1.0 + 1e-12);
+    for (int c = tid; c < nc; c += 1024) {
+      if (L.inS[c]) continue;
+      const double g = L.gnSet[c], rb = L.swn[c] * B;
+      if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
+      status[c] = (int8_t)ICR_SEPARATE;
+    }
+    __syncthreads();
+    const int nu = L.nu;
+    for (int u = wv; u < nu; u += 16) {   // exact gap at the turn of the unsettled contacts
+      const int c = L.ulist[u];
+      double a = 0.0;
       for (int q = ln; q < ldS; q += 64) {
-        const double t = Wns[(long)c * ldS + q] * (lamS[q] - lamS0[q]);
-        aa += t;
-        if (Sidx[q / 3] < c) ab += t;
+        const double lt = (L.Sidx[q / 3] < c) ? L.lamS[q] : L.lamS0[q];
+        a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        ab += __shfl_xor(ab, o, 64);
-        aa += __shfl_xor(aa, o, 64);
-      }
-      if (ln == 0) {
-        if (gn[c] + ab < 0.0) {
-          inS[c] = 1;
-          sh_flag = 1;
-        }
-        gn[c] += aa;
-        status[c] = (int8_t)ICR_SEPARATE;
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (ln == 0 && L.gnSet[c] + a < 0.0) {
+        L.inS[c] = 1;
+        L.flag = 1;
       }
     }
     __syncthreads();
-    if (sh_flag) {
+    if (L.flag) {
       // a skipped contact was not a no-op: restart the sweep with a larger S
-      for (int r = tid; r < ldS; r += 1024) lam[3 * Sidx[r / 3] + r % 3] = lamS0[r];
+      for (int r = tid; r < ldS; r += 1024) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS0[r];
       need_build = true;
       __threadfence_block();
       __syncthreads();
       continue;
     }
     double part = 0.0;
-    for (int r = tid; r < ldS; r += 1024) part += lamS[r] * lamS[r];
-    double nl2 = block_sum(part, red);
+    for (int r = tid; r < ldS; r += 1024) part += L.lamS[r] * L.lamS[r];
+    double nl2 = block_sum(part, L.red);
     if (tid == 0) {
       double diff = sqrt(dsum), nl = sqrt(nl2);
       eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
-      stop = (eps <= tol) ? 1 : 0;
+      L.stop = (eps <= tol) ? 1 : 0;
     }
     __syncthreads();
     ++sweep;
-    if (stop) break;
+    if (L.stop) break;
   }
-  for (int r = tid; r < ldS; r += 1024) lam[3 * Sidx[r / 3] + r % 3] = lamS[r];
+  for (int r = tid; r < ldS; r += 1024) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS[r];
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
@@ -843,8 +874,8 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   const int m = 3 * nc;
   k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
-  k_pgs_active<<<1, 1024, 0, st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
-                                   eps_dev, wk.Wss, wk.Wns, wk.recs, wk.ctl);
+  k_pgs_active<<<1, 1024, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
+                                                sweeps_dev, eps_dev, wk.Wss, wk.ctl);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
   k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
@@ -853,8 +884,14 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
 }
 
 size_t pgs_wss_elems() { return (size_t)PGS_S3 * PGS_S3; }
-size_t pgs_rec_elems() { return (size_t)PGS_REC * PGS_SMAX; }
-size_t pgs_wns_elems(int nc) { return (size_t)nc * PGS_S3; }
+
+void pgs_prepare() {
+  static bool done = false;
+  if (done) return;
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PgsLds)));
+  done = true;
+}
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {
   k_world_force<<<cdiv(nc, 128), 128, 0, st>>>(nc, Cm, lam, f);

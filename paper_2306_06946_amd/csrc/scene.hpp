@@ -92,10 +92,10 @@ struct Factor {
   double *d_y = nullptr;
 };
 
-// Work buffers of the PGS kernels: start gaps g [m], compact couplings
-// (pgs_wss_elems(), pgs_wns_elems(nc) doubles) and a 2-int control block.
+// Work buffers of the PGS kernels: start gaps g [m], the compact coupling
+// block (pgs_wss_elems() doubles) and a 2-int control block.
 struct PgsWork {
-  double *g = nullptr, *Wss = nullptr, *Wns = nullptr, *recs = nullptr;
+  double *g = nullptr, *Wss = nullptr;
   int *ctl = nullptr;
 };
 
@@ -205,8 +205,7 @@ void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 2560;
 size_t pgs_wss_elems();
-size_t pgs_rec_elems();
-size_t pgs_wns_elems(int nc);
+void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
                 double *eps_dev, const PgsWork &wk);
