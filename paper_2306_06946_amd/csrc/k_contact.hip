@@ -307,7 +307,8 @@ __device__ inline double frsqrt(double x) {
 }
 
 // Same branches and fixed point as local_solve, with the factor of the
-// diagonal block precomputed and divisions replaced by refined reciprocals.
+// diagonal block precomputed, divisions replaced by refined reciprocals and
+// the slip pass written on the direction alone (same iterates up to rounding).
 __device__ Local local_solve_rec(const double *rc, const double d[3], double mu, int j_inner) {
   Local out;
   if (d[0] >= 0.0) {
@@ -348,18 +349,32 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], double mu,
       u1 = 0.0;
     }
   }
+  // The fixed point acts on the direction u alone.  With den(u) > 0 the
+  // tangential residual r = d_t + lam_n(u) e(u), lam_n = -d_n / den(u),
+  // e(u) = w_tn + mu (W_tt - kappa I) u, is parallel to
+  //   v(u) = den(u) d_t - d_n e(u) = c + G u,
+  // an affine map of u, so a pass is u <- -v / |v| with no division.
+  const double m11 = w11 - kap, m22 = w22 - kap;
+  const double c0 = w00 * d[1] - d[0] * w01, c1 = w00 * d[2] - d[0] * w02;
+  const double g00 = mu * (d[1] * w01 - d[0] * m11), g01 = mu * (d[1] * w02 - d[0] * w12);
+  const double g10 = mu * (d[2] * w01 - d[0] * w12), g11 = mu * (d[2] * w02 - d[0] * m22);
+  const double mw01 = mu * w01, mw02 = mu * w02;
   for (int it = 0; it < j_inner; ++it) {
-    double den = w00 + mu * (w01 * u0 + w02 * u1);
-    if (den <= 0.0) den = w00;
-    double lam_n = -d[0] * frcp(den);
-    double a1 = mu * lam_n * u0, a2 = mu * lam_n * u1;
-    double r1 = d[1] + w01 * lam_n + (w11 - kap) * a1 + w12 * a2;
-    double r2 = d[2] + w02 * lam_n + w12 * a1 + (w22 - kap) * a2;
-    double s2 = r1 * r1 + r2 * r2;
+    const double den = fma(mw01, u0, fma(mw02, u1, w00));
+    double v0, v1;
+    if (den > 0.0) {
+      v0 = fma(g00, u0, fma(g01, u1, c0));
+      v1 = fma(g10, u0, fma(g11, u1, c1));
+    } else {   // den replaced by w_nn, as in the direct form
+      const double e1 = w01 + mu * (m11 * u0 + w12 * u1), e2 = w02 + mu * (w12 * u0 + m22 * u1);
+      v0 = w00 * d[1] - d[0] * e1;
+      v1 = w00 * d[2] - d[0] * e2;
+    }
+    const double s2 = v0 * v0 + v1 * v1;
     if (s2 > 0.0) {
-      double inv = frsqrt(s2);
-      u0 = -r1 * inv;
-      u1 = -r2 * inv;
+      const double inv = frsqrt(s2);
+      u0 = -v0 * inv;
+      u1 = -v1 * inv;
     }
   }
   double den = w00 + mu * (w01 * u0 + w02 * u1);
@@ -528,8 +543,10 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
 // a non-zero force or a negative gap can change; all others are no-ops of
 // Gauss-Seidel.  The kernel keeps the set S of contacts that may change and
 // runs the sequential sweep over S alone, with the compact coupling block
-// W~_SS (gathered once per set, rows for the next contact prefetched into
-// registers) and per-contact records (3x3 block, its factor, mu) in LDS.  It
+// W~_SS (gathered once per set) and per-contact records (3x3 block, its
+// factor, mu) in LDS.  Up to PGS_WAVE_MAX contacts the sweep is one wave's
+// barrier-free chain over register-resident gaps and forces (chain_wave);
+// larger sets use a block-wide chain with two barriers per contact.  It
 // then verifies that every contact outside S was a no-op at its turn, i.e.
 // that its normal gap
 //   g_n(c) = g_n^set(c) + W~_{n(c),S} (lambda^turn - lambda^set) >= 0,
@@ -542,7 +559,11 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
 // outgrows PGS_SMAX the remaining sweeps go to k_pgs_single (ctl[0] = 1).
 constexpr int PGS_SMAX = 512;
 constexpr int PGS_S3 = 3 * PGS_SMAX;
-constexpr int PGS_RW = 14;   // record width in LDS
+constexpr int PGS_RW = 14;    // record width in LDS
+constexpr int PGS_NT = 512;   // threads of the active-set kernel
+constexpr int PGS_NW = PGS_NT / 64;
+constexpr int PGS_WAVE_MAX = 128;   // largest set swept by the single-wave chain (register budget)
+constexpr int PGS_BLK = 10;         // doubles per 3x3 block of the blocked W~_SS (9 used, 16-byte aligned)
 struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
@@ -556,18 +577,136 @@ struct PgsLds {
   int nS, flag, stop, nu;
 };
 
-__global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__restrict__ W,
-                                                     const double *__restrict__ d, const double *__restrict__ g0,
-                                                     const double *__restrict__ mu, double h2,
-                                                     double *__restrict__ lam, int8_t *__restrict__ status,
-                                                     int max_sweeps, double tol, int j_inner,
-                                                     int *__restrict__ sweeps_out, double *__restrict__ eps_out,
-                                                     double *__restrict__ Wss, int *__restrict__ ctl) {
+// Padded contact count of the blocked layout: 64 contacts per register slot.
+__host__ __device__ inline int pgs_wave_pad(int nS) { return nS <= 64 ? 64 : 128; }
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Blocks W~(rows of contacts ln + 64k, columns of contact i) for every slot k.
+template <int NS>
+__device__ inline void chain_load(double2 (&X)[NS][PGS_BLK / 2], const double *__restrict__ Wb, int i, int ln) {
+  const double2 *base = reinterpret_cast<const double2 *>(Wb + ((long)i * (64 * NS) + ln) * PGS_BLK);
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[k * 64 * (PGS_BLK / 2) + j];
+}
+
+// One Gauss-Seidel step of the single-wave chain: contact i is owned by lane
+// i % 64, register slot i / 64.  Every lane runs the local solve on the same
+// (broadcast) data, the owner keeps the new force, and every lane applies
+// W~(own rows, i) dlambda_i to its gaps.
+template <int NS>
+__device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], double (&g)[NS][3],
+                                  double (&lm)[NS][3], int (&st)[NS], const PgsLds &L, int j_inner, double &dsum,
+                                  int ln) {
+  const int ki = i >> 6, li = i & 63;
+  double gi[3], lo[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double gv = g[0][q], lv = lm[0][q];
+#pragma unroll
+    for (int k = 1; k < NS; ++k)
+      if (ki == k) {
+        gv = g[k][q];
+        lv = lm[k][q];
+      }
+    gi[q] = readlane_f64(gv, li);
+    lo[q] = readlane_f64(lv, li);
+  }
+  const double *rc = L.rec + PGS_RW * i;
+  double dd[3];
+  dd[0] = gi[0] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
+  dd[1] = gi[1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
+  dd[2] = gi[2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
+  const Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
+  const double d0 = rs.l[0] - lo[0], d1 = rs.l[1] - lo[1], d2 = rs.l[2] - lo[2];
+  dsum += d0 * d0;
+  dsum += d1 * d1;
+  dsum += d2 * d2;
+  if (ln == li) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (ki == k) {
+        lm[k][0] = rs.l[0];
+        lm[k][1] = rs.l[1];
+        lm[k][2] = rs.l[2];
+        st[k] = rs.st;
+      }
+  }
+  if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const double b[9] = {X[k][0].x, X[k][0].y, X[k][1].x, X[k][1].y, X[k][2].x,
+                           X[k][2].y, X[k][3].x, X[k][3].y, X[k][4].x};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[k][a] += b[3 * a] * d0 + b[3 * a + 1] * d1 + b[3 * a + 2] * d2;
+    }
+  }
+}
+
+// Sequential sweep over S by wave 0 alone: gaps and forces of S live in the
+// lanes' registers, the blocks of the next two contacts are in flight while
+// the current one is solved, and no barrier is taken inside the sweep.
+template <int NS>
+__device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int8_t *__restrict__ status,
+                           int j_inner, double &dsum) {
+  const int ln = threadIdx.x & 63;
+  double g[NS][3], lm[NS][3];
+  int st[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int c = ln + 64 * k;
+    const bool v = c < nS;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      g[k][q] = v ? L.gS[3 * c + q] : 0.0;
+      lm[k][q] = v ? L.lamS[3 * c + q] : 0.0;
+    }
+    st[k] = ICR_SEPARATE;
+  }
+  double2 A[NS][PGS_BLK / 2], B[NS][PGS_BLK / 2];
+  chain_load<NS>(A, Wb, 0, ln);
+  if (nS > 1) chain_load<NS>(B, Wb, 1, ln);
+  for (int i = 0; i < nS; i += 2) {
+    chain_step<NS>(i, A, g, lm, st, L, j_inner, dsum, ln);
+    if (i + 2 < nS) chain_load<NS>(A, Wb, i + 2, ln);
+    if (i + 1 < nS) {
+      chain_step<NS>(i + 1, B, g, lm, st, L, j_inner, dsum, ln);
+      if (i + 3 < nS) chain_load<NS>(B, Wb, i + 3, ln);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int c = ln + 64 * k;
+    if (c < nS) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        L.gS[3 * c + q] = g[k][q];
+        L.lamS[3 * c + q] = lm[k][q];
+      }
+      status[L.Sidx[c]] = (int8_t)st[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__restrict__ W,
+                                                       const double *__restrict__ d, const double *__restrict__ g0,
+                                                       const double *__restrict__ mu, double h2,
+                                                       double *__restrict__ lam, int8_t *__restrict__ status,
+                                                       int max_sweeps, double tol, int j_inner,
+                                                       int *__restrict__ sweeps_out, double *__restrict__ eps_out,
+                                                       double *__restrict__ Wss, int *__restrict__ ctl) {
   extern __shared__ double lds_raw[];
   PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-  for (int c = tid; c < nc; c += 1024) {
+  for (int c = tid; c < nc; c += PGS_NT) {
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
     L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
     L.swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
@@ -578,14 +717,15 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     ctl[1] = 0;
   }
   __syncthreads();
-  int sweep = 0, nS = 0, ldS = 0;
+  int sweep = 0, nS = 0, ldS = 0, nsp = 0;
+  bool blk = true;
   double eps = 0.0;
   bool need_build = true, first_build = true;
   while (sweep < max_sweeps) {
     if (need_build) {
       // ---- ordered list of S (ballot per 64-contact window, prefix by thread 0)
       const int nwin = (nc + 63) / 64;
-      for (int w = wv; w < nwin; w += 16) {
+      for (int w = wv; w < nwin; w += PGS_NW) {
         const int c = 64 * w + ln;
         const unsigned long long bal = __ballot(c < nc && L.inS[c]);
         if (ln == 0) L.wcount[w] = __popcll(bal);
@@ -609,7 +749,7 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
         }
         return;
       }
-      for (int w = wv; w < nwin; w += 16) {
+      for (int w = wv; w < nwin; w += PGS_NW) {
         const int c = 64 * w + ln;
         const bool in = c < nc && L.inS[c];
         const unsigned long long bal = __ballot(in);
@@ -617,22 +757,39 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       }
       __syncthreads();
       ldS = 3 * nS;
-      for (int r = tid; r < ldS; r += 1024) {
+      blk = nS <= PGS_WAVE_MAX;
+      nsp = pgs_wave_pad(nS);
+      for (int r = tid; r < ldS; r += PGS_NT) {
         L.lamS[r] = lam[3 * L.Sidx[r / 3] + r % 3];
         L.lamSet[r] = L.lamS[r];
       }
-      // ---- compact couplings W~_SS
-      const long ns2 = (long)ldS * ldS;
-      for (long e = tid; e < ns2; e += 1024) {
-        const int r = (int)(e / ldS), q = (int)(e % ldS);
-        Wss[e] = h2 * W[(3L * L.Sidx[r / 3] + r % 3) * m + 3L * L.Sidx[q / 3] + q % 3];
+      // ---- compact couplings W~_SS: blocked [i][c] 3x3 blocks of rows c,
+      // columns i (padded to nsp contacts) for the single-wave chain, else
+      // row-major
+      if (blk) {
+        const long nel = (long)nS * nsp * PGS_BLK;
+        for (long e = tid; e < nel; e += PGS_NT) {
+          const int j = (int)(e % PGS_BLK);
+          const long ic = e / PGS_BLK;
+          const int c = (int)(ic % nsp), i = (int)(ic / nsp);
+          double v = 0.0;
+          if (j < 9 && c < nS) v = h2 * W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
+          Wss[e] = v;
+        }
+      } else {
+        const long ns2 = (long)ldS * ldS;
+        for (long e = tid; e < ns2; e += PGS_NT) {
+          const int r = (int)(e / ldS), q = (int)(e % ldS);
+          Wss[e] = h2 * W[(3L * L.Sidx[r / 3] + r % 3) * m + 3L * L.Sidx[q / 3] + q % 3];
+        }
       }
       __threadfence_block();
       __syncthreads();
-      for (int i = tid; i < nS; i += 1024) {
+      for (int i = tid; i < nS; i += PGS_NT) {
         double wb[3][3];
         for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q) wb[p][q] = Wss[(long)(3 * i + p) * ldS + 3 * i + q];
+          for (int q = 0; q < 3; ++q)
+            wb[p][q] = blk ? Wss[((long)i * nsp + i) * PGS_BLK + 3 * p + q] : Wss[(long)(3 * i + p) * ldS + 3 * i + q];
         double *rc = L.rec + PGS_RW * i;
         double tmp[16];
         make_record(wb, tmp);
@@ -642,16 +799,40 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       // ---- gaps at the set's start state (lambda is zero outside S)
       if (first_build) {
         // g0 = d + W~ lambda0 was formed by k_pgs_init for every row
-        for (int r = tid; r < ldS; r += 1024) L.gS[r] = g0[3 * L.Sidx[r / 3] + r % 3];
-        for (int c = tid; c < nc; c += 1024) L.gnSet[c] = g0[3 * c];
+        for (int r = tid; r < ldS; r += PGS_NT) L.gS[r] = g0[3 * L.Sidx[r / 3] + r % 3];
+        for (int c = tid; c < nc; c += PGS_NT) L.gnSet[c] = g0[3 * c];
       } else {
-        for (int r = wv; r < ldS; r += 16) {
-          double a = 0.0;
-          for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], L.lamS[q], a);
-          for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-          if (ln == 0) L.gS[r] = d[3 * L.Sidx[r / 3] + r % 3] + a;
+        if (blk) {
+          for (int c = wv; c < nS; c += PGS_NW) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int i = ln; i < nS; i += 64) {
+              const double *b = Wss + ((long)i * nsp + c) * PGS_BLK;
+              const double l0 = L.lamS[3 * i], l1 = L.lamS[3 * i + 1], l2 = L.lamS[3 * i + 2];
+              a0 += b[0] * l0 + b[1] * l1 + b[2] * l2;
+              a1 += b[3] * l0 + b[4] * l1 + b[5] * l2;
+              a2 += b[6] * l0 + b[7] * l1 + b[8] * l2;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+              a0 += __shfl_xor(a0, o, 64);
+              a1 += __shfl_xor(a1, o, 64);
+              a2 += __shfl_xor(a2, o, 64);
+            }
+            if (ln == 0) {
+              const int cc = 3 * L.Sidx[c];
+              L.gS[3 * c] = d[cc] + a0;
+              L.gS[3 * c + 1] = d[cc + 1] + a1;
+              L.gS[3 * c + 2] = d[cc + 2] + a2;
+            }
+          }
+        } else {
+          for (int r = wv; r < ldS; r += PGS_NW) {
+            double a = 0.0;
+            for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], L.lamS[q], a);
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+            if (ln == 0) L.gS[r] = d[3 * L.Sidx[r / 3] + r % 3] + a;
+          }
         }
-        for (int c = wv; c < nc; c += 16) {
+        for (int c = wv; c < nc; c += PGS_NW) {
           if (L.inS[c]) continue;
           double a = 0.0;
           for (int q = ln; q < ldS; q += 64)
@@ -665,62 +846,75 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
       first_build = false;
     }
     // ---- sweep over S from its start state
-    for (int r = tid; r < ldS; r += 1024) L.lamS0[r] = L.lamS[r];
+    for (int r = tid; r < ldS; r += PGS_NT) L.lamS0[r] = L.lamS[r];
     if (tid == 0) {
       L.flag = 0;
       L.nu = 0;
     }
     double dsum = 0.0;
-    const int r0 = tid, r1 = tid + 1024;
-    double pf0[3] = {0, 0, 0}, pf1[3] = {0, 0, 0};
-    if (nS > 0) {
-      for (int b = 0; b < 3; ++b) {
-        if (r0 < ldS) pf0[b] = Wss[(long)b * ldS + r0];
-        if (r1 < ldS) pf1[b] = Wss[(long)b * ldS + r1];
-      }
-    }
     __syncthreads();
-    for (int i = 0; i < nS; ++i) {
-      if (wv == 0) {
-        const double *rc = L.rec + PGS_RW * i;
-        double lo[3], dd[3];
-        for (int q = 0; q < 3; ++q) lo[q] = L.lamS[3 * i + q];
-        dd[0] = L.gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
-        dd[1] = L.gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
-        dd[2] = L.gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
-        Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
-        double dl[3];
-        for (int q = 0; q < 3; ++q) {
-          dl[q] = rs.l[q] - lo[q];
-          dsum += dl[q] * dl[q];
-        }
-        if (ln == 0) {
-          for (int q = 0; q < 3; ++q) {
-            L.bc[q] = dl[q];
-            L.lamS[3 * i + q] = rs.l[q];
-          }
-          status[L.Sidx[i]] = (int8_t)rs.st;
-        }
+    if (blk) {
+      if (wv == 0 && nS > 0) {
+        if (nsp == 64)
+          chain_wave<1>(nS, Wss, L, status, j_inner, dsum);
+        else
+          chain_wave<2>(nS, Wss, L, status, j_inner, dsum);
       }
       __syncthreads();
-      const double d0 = L.bc[0], d1 = L.bc[1], d2 = L.bc[2];
-      if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
-        if (r0 < ldS) L.gS[r0] += pf0[0] * d0 + pf0[1] * d1 + pf0[2] * d2;
-        if (r1 < ldS) L.gS[r1] += pf1[0] * d0 + pf1[1] * d1 + pf1[2] * d2;
-      }
-      if (i + 1 < nS) {
-        const long base = (long)(3 * (i + 1)) * ldS;
+    } else {
+      // block-wide chain: wave 0 solves, every thread updates three rows
+      constexpr int RB = PGS_S3 / PGS_NT;
+      double pf[RB][3];
+      for (int j = 0; j < RB; ++j)
         for (int b = 0; b < 3; ++b) {
-          if (r0 < ldS) pf0[b] = Wss[base + (long)b * ldS + r0];
-          if (r1 < ldS) pf1[b] = Wss[base + (long)b * ldS + r1];
+          const int r = tid + PGS_NT * j;
+          pf[j][b] = r < ldS ? Wss[(long)b * ldS + r] : 0.0;
         }
+      for (int i = 0; i < nS; ++i) {
+        if (wv == 0) {
+          const double *rc = L.rec + PGS_RW * i;
+          double lo[3], dd[3];
+          for (int q = 0; q < 3; ++q) lo[q] = L.lamS[3 * i + q];
+          dd[0] = L.gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
+          dd[1] = L.gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
+          dd[2] = L.gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
+          Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
+          double dl[3];
+          for (int q = 0; q < 3; ++q) {
+            dl[q] = rs.l[q] - lo[q];
+            dsum += dl[q] * dl[q];
+          }
+          if (ln == 0) {
+            for (int q = 0; q < 3; ++q) {
+              L.bc[q] = dl[q];
+              L.lamS[3 * i + q] = rs.l[q];
+            }
+            status[L.Sidx[i]] = (int8_t)rs.st;
+          }
+        }
+        __syncthreads();
+        const double d0 = L.bc[0], d1 = L.bc[1], d2 = L.bc[2];
+        if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+          for (int j = 0; j < RB; ++j) {
+            const int r = tid + PGS_NT * j;
+            if (r < ldS) L.gS[r] += pf[j][0] * d0 + pf[j][1] * d1 + pf[j][2] * d2;
+          }
+        }
+        if (i + 1 < nS) {
+          const long base = (long)(3 * (i + 1)) * ldS;
+          for (int j = 0; j < RB; ++j)
+            for (int b = 0; b < 3; ++b) {
+              const int r = tid + PGS_NT * j;
+              if (r < ldS) pf[j][b] = Wss[base + (long)b * ldS + r];
+            }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     // ---- verify the skipped contacts
     // bound factor B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
     double bpart = 0.0;
-    for (int r = tid; r < ldS; r += 1024) {
+    for (int r = tid; r < ldS; r += PGS_NT) {
       const double *rc = L.rec + PGS_RW * (r / 3);
       const double wqq = (r % 3 == 0) ? rc[0] : ((r % 3 == 1) ? rc[3] : rc[5]);
       const double dv = fmax(fabs(L.lamS[r] - L.lamSet[r]), fabs(L.lamS0[r] - L.lamSet[r]));
@@ -730,7 +924,7 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     if (tid == 0) L.red[0] = Bsum;
     __syncthreads();
     const double B = L.red[0] * (1.0 + 1e-12);
-    for (int c = tid; c < nc; c += 1024) {
+    for (int c = tid; c < nc; c += PGS_NT) {
       if (L.inS[c]) continue;
       const double g = L.gnSet[c], rb = L.swn[c] * B;
       if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
@@ -738,7 +932,7 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     }
     __syncthreads();
     const int nu = L.nu;
-    for (int u = wv; u < nu; u += 16) {   // exact gap at the turn of the unsettled contacts
+    for (int u = wv; u < nu; u += PGS_NW) {   // exact gap at the turn of the unsettled contacts
       const int c = L.ulist[u];
       double a = 0.0;
       for (int q = ln; q < ldS; q += 64) {
@@ -754,14 +948,14 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     __syncthreads();
     if (L.flag) {
       // a skipped contact was not a no-op: restart the sweep with a larger S
-      for (int r = tid; r < ldS; r += 1024) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS0[r];
+      for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS0[r];
       need_build = true;
       __threadfence_block();
       __syncthreads();
       continue;
     }
     double part = 0.0;
-    for (int r = tid; r < ldS; r += 1024) part += L.lamS[r] * L.lamS[r];
+    for (int r = tid; r < ldS; r += PGS_NT) part += L.lamS[r] * L.lamS[r];
     double nl2 = block_sum(part, L.red);
     if (tid == 0) {
       double diff = sqrt(dsum), nl = sqrt(nl2);
@@ -772,7 +966,7 @@ __global__ __launch_bounds__(1024) void k_pgs_active(int nc, const double *__res
     ++sweep;
     if (L.stop) break;
   }
-  for (int r = tid; r < ldS; r += 1024) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS[r];
+  for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS[r];
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
@@ -874,7 +1068,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   const int m = 3 * nc;
   k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
-  k_pgs_active<<<1, 1024, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
+  k_pgs_active<<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
                                                 sweeps_dev, eps_dev, wk.Wss, wk.ctl);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
@@ -883,7 +1077,9 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   ICR_LAUNCH_CHECK();
 }
 
-size_t pgs_wss_elems() { return (size_t)PGS_S3 * PGS_S3; }
+size_t pgs_wss_elems() {
+  return std::max((size_t)PGS_S3 * PGS_S3, (size_t)PGS_WAVE_MAX * PGS_WAVE_MAX * PGS_BLK);
+}
 
 void pgs_prepare() {
   static bool done = false;
