@@ -74,6 +74,8 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_W = C.arena.alloc<double>(m * m);
   C.pgs.g = C.arena.alloc<double>(m);
   C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
+  C.pgs.gnSet = C.arena.alloc<double>(nc);
+  C.pgs.swn = C.arena.alloc<double>(nc);
   C.pgs.ctl = C.arena.alloc<int>(2);
   pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);

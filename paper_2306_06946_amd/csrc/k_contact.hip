@@ -267,30 +267,40 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
   return out;
 }
 
-// Per-contact record of the active-set PGS, computed once per active set:
-// the symmetric 3x3 block of h^2 W_aa, its Cholesky factor, the reciprocals
-// of the factor's diagonal and the slip shift kappa = (w11 + w22) / 2.
-constexpr int PGS_REC = 16;
-__device__ inline void make_record(const double w[3][3], double *rec) {
-  double l00 = sqrt(w[0][0]);
-  double l10 = w[1][0] / l00, l20 = w[2][0] / l00;
-  double l11 = sqrt(w[1][1] - l10 * l10);
-  double l21 = (w[2][1] - l20 * l10) / l11;
-  double l22 = sqrt(w[2][2] - l20 * l20 - l21 * l21);
-  rec[0] = w[0][0];
-  rec[1] = w[0][1];
-  rec[2] = w[0][2];
-  rec[3] = w[1][1];
-  rec[4] = w[1][2];
-  rec[5] = w[2][2];
-  rec[6] = l10;
-  rec[7] = l20;
-  rec[8] = l21;
-  rec[9] = 1.0 / l00;
-  rec[10] = 1.0 / l11;
-  rec[11] = 1.0 / l22;
-  rec[12] = 0.5 * (w[1][1] + w[2][2]);
-  rec[13] = rec[14] = rec[15] = 0.0;
+// Per-contact record of the active-set PGS, computed once per active set from
+// the symmetric 3x3 block w of h^2 W_aa and mu (kappa = (w11 + w22) / 2):
+//   0-5  w00 w01 w02 w11 w12 w22      6-11 the same entries of w^-1
+//   12   mu (w11 - kappa)   13 mu (w22 - kappa)   14 mu w12
+//   15   mu w01             16 mu w02             17 mu
+//   18   1 if w00 > mu |(w01, w02)| with margin (then den(u) > 0 on the unit
+//        circle and the slip pass needs no fallback), else 0
+constexpr int PGS_RW = 20;   // record width (19 used)
+__device__ inline void make_record(const double w[3][3], double mu, double *rec) {
+  const double w00 = w[0][0], w01 = w[0][1], w02 = w[0][2], w11 = w[1][1], w12 = w[1][2], w22 = w[2][2];
+  const double c00 = w11 * w22 - w12 * w12, c01 = w02 * w12 - w01 * w22, c02 = w01 * w12 - w02 * w11;
+  const double c11 = w00 * w22 - w02 * w02, c12 = w01 * w02 - w00 * w12, c22 = w00 * w11 - w01 * w01;
+  const double idet = 1.0 / (w00 * c00 + w01 * c01 + w02 * c02);
+  const double kap = 0.5 * (w11 + w22);
+  rec[0] = w00;
+  rec[1] = w01;
+  rec[2] = w02;
+  rec[3] = w11;
+  rec[4] = w12;
+  rec[5] = w22;
+  rec[6] = c00 * idet;
+  rec[7] = c01 * idet;
+  rec[8] = c02 * idet;
+  rec[9] = c11 * idet;
+  rec[10] = c12 * idet;
+  rec[11] = c22 * idet;
+  rec[12] = mu * (w11 - kap);
+  rec[13] = mu * (w22 - kap);
+  rec[14] = mu * w12;
+  rec[15] = mu * w01;
+  rec[16] = mu * w02;
+  rec[17] = mu;
+  rec[18] = (w00 > 1.000001 * mu * sqrt(w01 * w01 + w02 * w02)) ? 1.0 : 0.0;
+  rec[19] = 0.0;
 }
 
 // 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
@@ -305,27 +315,36 @@ __device__ inline double frsqrt(double x) {
   y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
   return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
+// One Newton step only: relative error about the square of the estimate's
+// (used inside the slip fixed point, whose iterates are renormalised anyway).
+__device__ inline double frsqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
 
-// Same branches and fixed point as local_solve, with the factor of the
-// diagonal block precomputed, divisions replaced by refined reciprocals and
-// the slip pass written on the direction alone (same iterates up to rounding).
-__device__ Local local_solve_rec(const double *rc, const double d[3], double mu, int j_inner) {
+// Same branches and fixed point as local_solve, from the record: stick trial
+// by the precomputed inverse, refined reciprocals instead of divisions, and
+// the slip pass on the direction u alone.  With den(u) > 0 the tangential
+// residual r = d_t + lam_n(u) e(u), lam_n = -d_n / den(u),
+// e(u) = w_tn + mu (W_tt - kappa I) u, is parallel to
+//   v(u) = den(u) d_t - d_n e(u) = c + G u,
+// an affine map of u, so a pass is u <- -v / |v| (same iterates up to
+// rounding).  Every VALU instruction of the single issuing wave costs the
+// same whatever its dependences, so the pass is kept to 14 of them.
+__device__ Local local_solve_rec(const double *rc, const double d[3], int j_inner) {
   Local out;
   if (d[0] >= 0.0) {
     out.l[0] = out.l[1] = out.l[2] = 0.0;
     out.st = ICR_SEPARATE;
     return out;
   }
-  const double w00 = rc[0], w01 = rc[1], w02 = rc[2], w11 = rc[3], w12 = rc[4], w22 = rc[5];
-  const double l10 = rc[6], l20 = rc[7], l21 = rc[8], r00 = rc[9], r11 = rc[10], r22 = rc[11], kap = rc[12];
-  double y0 = d[0] * r00;
-  double y1 = (d[1] - l10 * y0) * r11;
-  double y2 = (d[2] - l20 * y0 - l21 * y1) * r22;
-  double x2 = y2 * r22;
-  double x1 = (y1 - l21 * x2) * r11;
-  double x0 = (y0 - l10 * x1 - l20 * x2) * r00;
-  double ln = -x0, lt1 = -x1, lt2 = -x2;
-  if (ln > 0.0 && lt1 * lt1 + lt2 * lt2 <= (mu * ln) * (mu * ln)) {
+  const double w00 = rc[0], w01 = rc[1], w02 = rc[2];
+  const double mm11 = rc[12], mm22 = rc[13], mw12 = rc[14], mw01 = rc[15], mw02 = rc[16], mu = rc[17];
+  const double ln = -(rc[6] * d[0] + rc[7] * d[1] + rc[8] * d[2]);
+  const double lt1 = -(rc[7] * d[0] + rc[9] * d[1] + rc[10] * d[2]);
+  const double lt2 = -(rc[8] * d[0] + rc[10] * d[1] + rc[11] * d[2]);
+  const double nt2 = lt1 * lt1 + lt2 * lt2;
+  if (ln > 0.0 && nt2 <= (mu * ln) * (mu * ln)) {
     out.l[0] = ln;
     out.l[1] = lt1;
     out.l[2] = lt2;
@@ -333,15 +352,14 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], double mu,
     return out;
   }
   double u0, u1;
-  double nt2 = lt1 * lt1 + lt2 * lt2;
   if (nt2 > 0.0) {
-    double inv = frsqrt(nt2);
+    const double inv = frsqrt(nt2);
     u0 = lt1 * inv;
     u1 = lt2 * inv;
   } else {
-    double nd2 = d[1] * d[1] + d[2] * d[2];
+    const double nd2 = d[1] * d[1] + d[2] * d[2];
     if (nd2 > 0.0) {
-      double inv = frsqrt(nd2);
+      const double inv = frsqrt(nd2);
       u0 = -d[1] * inv;
       u1 = -d[2] * inv;
     } else {
@@ -349,40 +367,65 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], double mu,
       u1 = 0.0;
     }
   }
-  // The fixed point acts on the direction u alone.  With den(u) > 0 the
-  // tangential residual r = d_t + lam_n(u) e(u), lam_n = -d_n / den(u),
-  // e(u) = w_tn + mu (W_tt - kappa I) u, is parallel to
-  //   v(u) = den(u) d_t - d_n e(u) = c + G u,
-  // an affine map of u, so a pass is u <- -v / |v| with no division.
-  const double m11 = w11 - kap, m22 = w22 - kap;
-  const double c0 = w00 * d[1] - d[0] * w01, c1 = w00 * d[2] - d[0] * w02;
-  const double g00 = mu * (d[1] * w01 - d[0] * m11), g01 = mu * (d[1] * w02 - d[0] * w12);
-  const double g10 = mu * (d[2] * w01 - d[0] * w12), g11 = mu * (d[2] * w02 - d[0] * m22);
-  const double mw01 = mu * w01, mw02 = mu * w02;
-  for (int it = 0; it < j_inner; ++it) {
-    const double den = fma(mw01, u0, fma(mw02, u1, w00));
-    double v0, v1;
-    if (den > 0.0) {
-      v0 = fma(g00, u0, fma(g01, u1, c0));
-      v1 = fma(g10, u0, fma(g11, u1, c1));
-    } else {   // den replaced by w_nn, as in the direct form
-      const double e1 = w01 + mu * (m11 * u0 + w12 * u1), e2 = w02 + mu * (w12 * u0 + m22 * u1);
-      v0 = w00 * d[1] - d[0] * e1;
-      v1 = w00 * d[2] - d[0] * e2;
+  // -v(u) = n + N u
+  const double n0 = fma(d[0], w01, -w00 * d[1]), n1 = fma(d[0], w02, -w00 * d[2]);
+  const double n00 = fma(d[0], mm11, -d[1] * mw01), n01 = fma(d[0], mw12, -d[1] * mw02);
+  const double n10 = fma(d[0], mw12, -d[2] * mw01), n11 = fma(d[0], mm22, -d[2] * mw02);
+  bool safe = rc[18] != 0.0;
+  if (safe) {
+    for (int it = 0; it < j_inner; ++it) {
+      const double v0 = fma(n00, u0, fma(n01, u1, n0));
+      const double v1 = fma(n10, u0, fma(n11, u1, n1));
+      const double inv = frsqrt1(fma(v0, v0, v1 * v1));
+      u0 = v0 * inv;
+      u1 = v1 * inv;
     }
-    const double s2 = v0 * v0 + v1 * v1;
-    if (s2 > 0.0) {
-      const double inv = frsqrt(s2);
-      u0 = -v0 * inv;
-      u1 = -v1 * inv;
+    safe = (u0 == u0) && (u1 == u1);   // |v| = 0 (a NaN) takes the guarded pass below
+  }
+  if (!safe) {
+    // guarded pass: den <= 0 replaced by w_nn as in the direct form, |v| = 0
+    // keeps the direction; restarts from the same initial direction
+    if (nt2 > 0.0) {
+      const double inv = frsqrt(nt2);
+      u0 = lt1 * inv;
+      u1 = lt2 * inv;
+    } else {
+      const double nd2 = d[1] * d[1] + d[2] * d[2];
+      if (nd2 > 0.0) {
+        const double inv = frsqrt(nd2);
+        u0 = -d[1] * inv;
+        u1 = -d[2] * inv;
+      } else {
+        u0 = 1.0;
+        u1 = 0.0;
+      }
+    }
+    for (int it = 0; it < j_inner; ++it) {
+      const double den = fma(mw01, u0, fma(mw02, u1, w00));
+      double v0, v1;
+      if (den > 0.0) {
+        v0 = fma(n00, u0, fma(n01, u1, n0));
+        v1 = fma(n10, u0, fma(n11, u1, n1));
+      } else {
+        const double e1 = fma(mm11, u0, fma(mw12, u1, w01)), e2 = fma(mw12, u0, fma(mm22, u1, w02));
+        v0 = fma(d[0], e1, -w00 * d[1]);
+        v1 = fma(d[0], e2, -w00 * d[2]);
+      }
+      const double s2 = v0 * v0 + v1 * v1;
+      if (s2 > 0.0) {
+        const double inv = frsqrt(s2);
+        u0 = v0 * inv;
+        u1 = v1 * inv;
+      }
     }
   }
-  double den = w00 + mu * (w01 * u0 + w02 * u1);
+  double den = fma(mw01, u0, fma(mw02, u1, w00));
   if (den <= 0.0) den = w00;
-  double lam_n = -d[0] * frcp(den);
+  const double lam_n = -d[0] * frcp(den);
+  const double mln = mu * lam_n;
   out.l[0] = lam_n;
-  out.l[1] = mu * lam_n * u0;
-  out.l[2] = mu * lam_n * u1;
+  out.l[1] = mln * u0;
+  out.l[2] = mln * u1;
   out.st = ICR_SLIP;
   return out;
 }
@@ -559,7 +602,6 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
 // outgrows PGS_SMAX the remaining sweeps go to k_pgs_single (ctl[0] = 1).
 constexpr int PGS_SMAX = 512;
 constexpr int PGS_S3 = 3 * PGS_SMAX;
-constexpr int PGS_RW = 14;    // record width in LDS
 constexpr int PGS_NT = 512;   // threads of the active-set kernel
 constexpr int PGS_NW = PGS_NT / 64;
 constexpr int PGS_WAVE_MAX = 128;   // largest set swept by the single-wave chain (register budget)
@@ -567,10 +609,10 @@ constexpr int PGS_BLK = 10;         // doubles per 3x3 block of the blocked W~_S
 struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
-  double gnSet[PGS_MAX_NC], swn[PGS_MAX_NC];
   double bc[3];
   double red[16];
   int Sidx[PGS_SMAX];
+  unsigned char stS[PGS_SMAX];
   int wcount[64];
   int ulist[PGS_MAX_NC];
   unsigned char inS[PGS_MAX_NC];
@@ -597,100 +639,99 @@ __device__ inline void chain_load(double2 (&X)[NS][PGS_BLK / 2], const double *_
     for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[k * 64 * (PGS_BLK / 2) + j];
 }
 
-// One Gauss-Seidel step of the single-wave chain: contact i is owned by lane
-// i % 64, register slot i / 64.  Every lane runs the local solve on the same
-// (broadcast) data, the owner keeps the new force, and every lane applies
-// W~(own rows, i) dlambda_i to its gaps.
-template <int NS>
-__device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], double (&g)[NS][3],
-                                  double (&lm)[NS][3], int (&st)[NS], const PgsLds &L, int j_inner, double &dsum,
-                                  int ln) {
-  const int ki = i >> 6, li = i & 63;
-  double gi[3], lo[3];
+// Record and current force of contact i (uniform LDS addresses: broadcast reads).
+struct ChainRec {
+  double r[PGS_RW];
+  double lo[3];
+};
+__device__ inline void chain_rec(ChainRec &c, const PgsLds &L, int i) {
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    double gv = g[0][q], lv = lm[0][q];
+  for (int q = 0; q < PGS_RW - 1; ++q) c.r[q] = L.rec[PGS_RW * i + q];
 #pragma unroll
-    for (int k = 1; k < NS; ++k)
-      if (ki == k) {
-        gv = g[k][q];
-        lv = lm[k][q];
-      }
-    gi[q] = readlane_f64(gv, li);
-    lo[q] = readlane_f64(lv, li);
-  }
-  const double *rc = L.rec + PGS_RW * i;
+  for (int q = 0; q < 3; ++q) c.lo[q] = L.lamS[3 * i + q];
+}
+
+// One Gauss-Seidel step of the single-wave chain.  Contact i's gaps are in
+// lane i % 64, register slot K = i / 64 (a compile-time slot, so no register
+// selection); every lane runs the local solve on the same broadcast data;
+// lane 0 stores the new force and status in LDS; every lane applies
+// W~(own rows, i) dlambda_i to its gaps.  Straight-line apart from the local
+// solve and the one-lane store, so loads in flight are waited for only where
+// they are used.
+template <int K, int NS>
+__device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], const ChainRec &c,
+                                  double (&g)[NS][3], PgsLds &L, int j_inner, int ln) {
+  const int li = i & 63;
+  const double g0 = readlane_f64(g[K][0], li), g1 = readlane_f64(g[K][1], li), g2 = readlane_f64(g[K][2], li);
+  const double *rc = c.r;
   double dd[3];
-  dd[0] = gi[0] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
-  dd[1] = gi[1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
-  dd[2] = gi[2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
-  const Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
-  const double d0 = rs.l[0] - lo[0], d1 = rs.l[1] - lo[1], d2 = rs.l[2] - lo[2];
-  dsum += d0 * d0;
-  dsum += d1 * d1;
-  dsum += d2 * d2;
-  if (ln == li) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (ki == k) {
-        lm[k][0] = rs.l[0];
-        lm[k][1] = rs.l[1];
-        lm[k][2] = rs.l[2];
-        st[k] = rs.st;
-      }
+  dd[0] = g0 - (rc[0] * c.lo[0] + rc[1] * c.lo[1] + rc[2] * c.lo[2]);
+  dd[1] = g1 - (rc[1] * c.lo[0] + rc[3] * c.lo[1] + rc[4] * c.lo[2]);
+  dd[2] = g2 - (rc[2] * c.lo[0] + rc[4] * c.lo[1] + rc[5] * c.lo[2]);
+  const Local rs = local_solve_rec(rc, dd, j_inner);
+  if (ln == 0) {
+    L.lamS[3 * i] = rs.l[0];
+    L.lamS[3 * i + 1] = rs.l[1];
+    L.lamS[3 * i + 2] = rs.l[2];
+    L.stS[i] = (unsigned char)rs.st;
   }
-  if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+  const double d0 = rs.l[0] - c.lo[0], d1 = rs.l[1] - c.lo[1], d2 = rs.l[2] - c.lo[2];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const double b[9] = {X[k][0].x, X[k][0].y, X[k][1].x, X[k][1].y, X[k][2].x,
-                           X[k][2].y, X[k][3].x, X[k][3].y, X[k][4].x};
+  for (int k = 0; k < NS; ++k) {
+    const double b[9] = {X[k][0].x, X[k][0].y, X[k][1].x, X[k][1].y, X[k][2].x,
+                         X[k][2].y, X[k][3].x, X[k][3].y, X[k][4].x};
 #pragma unroll
-      for (int a = 0; a < 3; ++a) g[k][a] += b[3 * a] * d0 + b[3 * a + 1] * d1 + b[3 * a + 2] * d2;
-    }
+    for (int a = 0; a < 3; ++a) g[k][a] = fma(b[3 * a + 2], d2, fma(b[3 * a + 1], d1, fma(b[3 * a], d0, g[k][a])));
   }
 }
 
-// Sequential sweep over S by wave 0 alone: gaps and forces of S live in the
-// lanes' registers, the blocks of the next two contacts are in flight while
-// the current one is solved, and no barrier is taken inside the sweep.
+// Contacts 64K .. 64K+63 of the sweep; blocks of the next two contacts and the
+// record of the next one are in flight while the current one is solved.
+// Loads past the end re-read the last contact (unused).
+template <int K, int NS>
+__device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln,
+                                  double (&g)[NS][3], double2 (&A)[NS][PGS_BLK / 2], double2 (&B)[NS][PGS_BLK / 2],
+                                  ChainRec &rA, ChainRec &rB) {
+  const int last = nS - 1, end = min(nS, 64 * K + 64);
+  for (int i = 64 * K; i < end; i += 2) {
+    chain_rec(rB, L, min(i + 1, last));
+    chain_step<K, NS>(i, A, rA, g, L, j_inner, ln);
+    chain_load<NS>(A, Wb, min(i + 2, last), ln);
+    if (i + 1 < end) {
+      chain_rec(rA, L, min(i + 2, last));
+      chain_step<K, NS>(i + 1, B, rB, g, L, j_inner, ln);
+    }
+    chain_load<NS>(B, Wb, min(i + 3, last), ln);
+  }
+}
+
+// Sequential sweep over S by wave 0 alone: gaps of S live in the lanes'
+// registers, forces, records and statuses in LDS; no barrier is taken inside
+// the sweep.
 template <int NS>
-__device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int8_t *__restrict__ status,
-                           int j_inner, double &dsum) {
+__device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int ln = threadIdx.x & 63;
-  double g[NS][3], lm[NS][3];
-  int st[NS];
+  double g[NS][3];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int c = ln + 64 * k;
-    const bool v = c < nS;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      g[k][q] = v ? L.gS[3 * c + q] : 0.0;
-      lm[k][q] = v ? L.lamS[3 * c + q] : 0.0;
-    }
-    st[k] = ICR_SEPARATE;
+    for (int q = 0; q < 3; ++q) g[k][q] = c < nS ? L.gS[3 * c + q] : 0.0;
   }
+  const int last = nS - 1;
   double2 A[NS][PGS_BLK / 2], B[NS][PGS_BLK / 2];
+  ChainRec rA, rB;
   chain_load<NS>(A, Wb, 0, ln);
-  if (nS > 1) chain_load<NS>(B, Wb, 1, ln);
-  for (int i = 0; i < nS; i += 2) {
-    chain_step<NS>(i, A, g, lm, st, L, j_inner, dsum, ln);
-    if (i + 2 < nS) chain_load<NS>(A, Wb, i + 2, ln);
-    if (i + 1 < nS) {
-      chain_step<NS>(i + 1, B, g, lm, st, L, j_inner, dsum, ln);
-      if (i + 3 < nS) chain_load<NS>(B, Wb, i + 3, ln);
-    }
-  }
+  chain_load<NS>(B, Wb, min(1, last), ln);
+  chain_rec(rA, L, 0);
+  chain_slot<0, NS>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
+  if constexpr (NS > 1) chain_slot<1, NS>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int c = ln + 64 * k;
     if (c < nS) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        L.gS[3 * c + q] = g[k][q];
-        L.lamS[3 * c + q] = lm[k][q];
-      }
-      status[L.Sidx[c]] = (int8_t)st[k];
+      for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[k][q];
     }
   }
 }
@@ -701,7 +742,8 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
                                                        double *__restrict__ lam, int8_t *__restrict__ status,
                                                        int max_sweeps, double tol, int j_inner,
                                                        int *__restrict__ sweeps_out, double *__restrict__ eps_out,
-                                                       double *__restrict__ Wss, int *__restrict__ ctl) {
+                                                       double *__restrict__ Wss, double *__restrict__ gnSet,
+                                                       double *__restrict__ swn, int *__restrict__ ctl) {
   extern __shared__ double lds_raw[];
   PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
   const int m = 3 * nc;
@@ -709,7 +751,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   for (int c = tid; c < nc; c += PGS_NT) {
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
     L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
-    L.swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
+    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
   }
   if (tid == 0) {
     L.stop = 0;
@@ -791,16 +833,15 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           for (int q = 0; q < 3; ++q)
             wb[p][q] = blk ? Wss[((long)i * nsp + i) * PGS_BLK + 3 * p + q] : Wss[(long)(3 * i + p) * ldS + 3 * i + q];
         double *rc = L.rec + PGS_RW * i;
-        double tmp[16];
-        make_record(wb, tmp);
-        for (int q = 0; q < 13; ++q) rc[q] = tmp[q];
-        rc[13] = mu[L.Sidx[i]];
+        double tmp[PGS_RW];
+        make_record(wb, mu[L.Sidx[i]], tmp);
+        for (int q = 0; q < PGS_RW; ++q) rc[q] = tmp[q];
       }
       // ---- gaps at the set's start state (lambda is zero outside S)
       if (first_build) {
         // g0 = d + W~ lambda0 was formed by k_pgs_init for every row
         for (int r = tid; r < ldS; r += PGS_NT) L.gS[r] = g0[3 * L.Sidx[r / 3] + r % 3];
-        for (int c = tid; c < nc; c += PGS_NT) L.gnSet[c] = g0[3 * c];
+        for (int c = tid; c < nc; c += PGS_NT) gnSet[c] = g0[3 * c];
       } else {
         if (blk) {
           for (int c = wv; c < nS; c += PGS_NW) {
@@ -838,7 +879,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           for (int q = ln; q < ldS; q += 64)
             a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], L.lamS[q], a);
           for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-          if (ln == 0) L.gnSet[c] = d[3 * c] + a;
+          if (ln == 0) gnSet[c] = d[3 * c] + a;
         }
       }
       __syncthreads();
@@ -856,11 +897,19 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     if (blk) {
       if (wv == 0 && nS > 0) {
         if (nsp == 64)
-          chain_wave<1>(nS, Wss, L, status, j_inner, dsum);
+          chain_wave<1>(nS, Wss, L, j_inner);
         else
-          chain_wave<2>(nS, Wss, L, status, j_inner, dsum);
+          chain_wave<2>(nS, Wss, L, j_inner);
       }
       __syncthreads();
+      // sum of squared changes of the sweep; statuses of S
+      double dpart = 0.0;
+      for (int r = tid; r < ldS; r += PGS_NT) {
+        const double dv = L.lamS[r] - L.lamS0[r];
+        dpart += dv * dv;
+      }
+      for (int i = tid; i < nS; i += PGS_NT) status[L.Sidx[i]] = (int8_t)L.stS[i];
+      dsum = block_sum(dpart, L.red);
     } else {
       // block-wide chain: wave 0 solves, every thread updates three rows
       constexpr int RB = PGS_S3 / PGS_NT;
@@ -878,7 +927,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           dd[0] = L.gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
           dd[1] = L.gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
           dd[2] = L.gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
-          Local rs = local_solve_rec(rc, dd, rc[13], j_inner);
+          Local rs = local_solve_rec(rc, dd, j_inner);
           double dl[3];
           for (int q = 0; q < 3; ++q) {
             dl[q] = rs.l[q] - lo[q];
@@ -926,7 +975,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     const double B = L.red[0] * (1.0 + 1e-12);
     for (int c = tid; c < nc; c += PGS_NT) {
       if (L.inS[c]) continue;
-      const double g = L.gnSet[c], rb = L.swn[c] * B;
+      const double g = gnSet[c], rb = swn[c] * B;
       if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
       status[c] = (int8_t)ICR_SEPARATE;
     }
@@ -940,7 +989,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
       }
       for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      if (ln == 0 && L.gnSet[c] + a < 0.0) {
+      if (ln == 0 && gnSet[c] + a < 0.0) {
         L.inS[c] = 1;
         L.flag = 1;
       }
@@ -1069,7 +1118,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
   k_pgs_active<<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
-                                                sweeps_dev, eps_dev, wk.Wss, wk.ctl);
+                                                sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
   k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,

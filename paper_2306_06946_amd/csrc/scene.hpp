@@ -96,6 +96,7 @@ struct Factor {
 // block (pgs_wss_elems() doubles) and a 2-int control block.
 struct PgsWork {
   double *g = nullptr, *Wss = nullptr;
+  double *gnSet = nullptr, *swn = nullptr;   // per contact: normal gap at the set's start state, sqrt(W~_nn)
   int *ctl = nullptr;
 };
 
