@@ -274,7 +274,7 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
 //   15   mu w01             16 mu w02             17 mu
 //   18   1 if w00 > mu |(w01, w02)| with margin (then den(u) > 0 on the unit
 //        circle and the slip pass needs no fallback), else 0
-constexpr int PGS_RW = 20;   // record width (19 used)
+constexpr int PGS_RW = 22;   // record width: 19 entries, then the contact's current force (chain)
 __device__ inline void make_record(const double w[3][3], double mu, double *rec) {
   const double w00 = w[0][0], w01 = w[0][1], w02 = w[0][2], w11 = w[1][1], w12 = w[1][2], w22 = w[2][2];
   const double c00 = w11 * w22 - w12 * w12, c01 = w02 * w12 - w01 * w22, c02 = w01 * w12 - w02 * w11;
@@ -300,7 +300,6 @@ __device__ inline void make_record(const double w[3][3], double mu, double *rec)
   rec[16] = mu * w02;
   rec[17] = mu;
   rec[18] = (w00 > 1.000001 * mu * sqrt(w01 * w01 + w02 * w02)) ? 1.0 : 0.0;
-  rec[19] = 0.0;
 }
 
 // 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
@@ -629,31 +628,34 @@ __device__ inline double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Blocks W~(rows of contacts ln + 64k, columns of contact i) for every slot k.
+// Blocks W~(rows of contacts ln + 64k, columns of contact i) for every slot k
+// (uniform base, fixed per-lane offset).
 template <int NS>
 __device__ inline void chain_load(double2 (&X)[NS][PGS_BLK / 2], const double *__restrict__ Wb, int i, int ln) {
-  const double2 *base = reinterpret_cast<const double2 *>(Wb + ((long)i * (64 * NS) + ln) * PGS_BLK);
+  const double2 *base = reinterpret_cast<const double2 *>(Wb + (long)i * (64 * NS * PGS_BLK));
+  const int lo = ln * (PGS_BLK / 2);
 #pragma unroll
   for (int k = 0; k < NS; ++k)
 #pragma unroll
-    for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[k * 64 * (PGS_BLK / 2) + j];
+    for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[lo + k * 64 * (PGS_BLK / 2) + j];
 }
 
-// Record and current force of contact i (uniform LDS addresses: broadcast reads).
+// Record and current force of contact i: 11 broadcast 16-byte LDS reads.
 struct ChainRec {
-  double r[PGS_RW];
-  double lo[3];
+  double2 r2[PGS_RW / 2];
+  __device__ double operator[](int q) const { return (q & 1) ? r2[q >> 1].y : r2[q >> 1].x; }
 };
 __device__ inline void chain_rec(ChainRec &c, const PgsLds &L, int i) {
+  const double2 *rp = reinterpret_cast<const double2 *>(L.rec + PGS_RW * i);
 #pragma unroll
-  for (int q = 0; q < PGS_RW - 1; ++q) c.r[q] = L.rec[PGS_RW * i + q];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) c.lo[q] = L.lamS[3 * i + q];
+  for (int q = 0; q < PGS_RW / 2; ++q) c.r2[q] = rp[q];
 }
 
-// One Gauss-Seidel step of the single-wave chain.  Contact i's gaps are in
-// lane i % 64, register slot K = i / 64 (a compile-time slot, so no register
-// selection); every lane runs the local solve on the same broadcast data;
+// One Gauss-Seidel step of the single-wave chain.  Contact i's gap without
+// its own term, e_i = g_i - W~_ii lambda_i (the input of the local solve),
+// is in lane i % 64, register slot K = i / 64 (compile-time: no register
+// selection); the blocked W~ has zero diagonal blocks, so the update keeps
+// e exact.  Every lane runs the local solve on the same broadcast data;
 // lane 0 stores the new force and status in LDS; every lane applies
 // W~(own rows, i) dlambda_i to its gaps.  Straight-line apart from the local
 // solve and the one-lane store, so loads in flight are waited for only where
@@ -662,20 +664,23 @@ template <int K, int NS>
 __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], const ChainRec &c,
                                   double (&g)[NS][3], PgsLds &L, int j_inner, int ln) {
   const int li = i & 63;
-  const double g0 = readlane_f64(g[K][0], li), g1 = readlane_f64(g[K][1], li), g2 = readlane_f64(g[K][2], li);
-  const double *rc = c.r;
+  double rc[19];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) rc[q] = c[q];
+  const double lo0 = c[19], lo1 = c[20], lo2 = c[21];
   double dd[3];
-  dd[0] = g0 - (rc[0] * c.lo[0] + rc[1] * c.lo[1] + rc[2] * c.lo[2]);
-  dd[1] = g1 - (rc[1] * c.lo[0] + rc[3] * c.lo[1] + rc[4] * c.lo[2]);
-  dd[2] = g2 - (rc[2] * c.lo[0] + rc[4] * c.lo[1] + rc[5] * c.lo[2]);
+  dd[0] = readlane_f64(g[K][0], li);
+  dd[1] = readlane_f64(g[K][1], li);
+  dd[2] = readlane_f64(g[K][2], li);
   const Local rs = local_solve_rec(rc, dd, j_inner);
   if (ln == 0) {
-    L.lamS[3 * i] = rs.l[0];
-    L.lamS[3 * i + 1] = rs.l[1];
-    L.lamS[3 * i + 2] = rs.l[2];
+    double *lp = L.rec + PGS_RW * i + 19;
+    lp[0] = rs.l[0];
+    lp[1] = rs.l[1];
+    lp[2] = rs.l[2];
     L.stS[i] = (unsigned char)rs.st;
   }
-  const double d0 = rs.l[0] - c.lo[0], d1 = rs.l[1] - c.lo[1], d2 = rs.l[2] - c.lo[2];
+  const double d0 = rs.l[0] - lo0, d1 = rs.l[1] - lo1, d2 = rs.l[2] - lo2;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double b[9] = {X[k][0].x, X[k][0].y, X[k][1].x, X[k][1].y, X[k][2].x,
@@ -705,9 +710,9 @@ __device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds 
   }
 }
 
-// Sequential sweep over S by wave 0 alone: gaps of S live in the lanes'
-// registers, forces, records and statuses in LDS; no barrier is taken inside
-// the sweep.
+// Sequential sweep over S by wave 0 alone: gaps of S (without own term) live
+// in the lanes' registers, forces, records and statuses in LDS; no barrier is
+// taken inside the sweep.
 template <int NS>
 __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int ln = threadIdx.x & 63;
@@ -815,7 +820,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           const long ic = e / PGS_BLK;
           const int c = (int)(ic % nsp), i = (int)(ic / nsp);
           double v = 0.0;
-          if (j < 9 && c < nS) v = h2 * W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
+          if (j < 9 && c < nS && c != i) v = h2 * W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
           Wss[e] = v;
         }
       } else {
@@ -829,18 +834,25 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       __syncthreads();
       for (int i = tid; i < nS; i += PGS_NT) {
         double wb[3][3];
+        const long ci = 3L * L.Sidx[i];
         for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q)
-            wb[p][q] = blk ? Wss[((long)i * nsp + i) * PGS_BLK + 3 * p + q] : Wss[(long)(3 * i + p) * ldS + 3 * i + q];
+          for (int q = 0; q < 3; ++q) wb[p][q] = h2 * W[(ci + p) * m + ci + q];
         double *rc = L.rec + PGS_RW * i;
-        double tmp[PGS_RW];
+        double tmp[19];
         make_record(wb, mu[L.Sidx[i]], tmp);
-        for (int q = 0; q < PGS_RW; ++q) rc[q] = tmp[q];
+        for (int q = 0; q < 19; ++q) rc[q] = tmp[q];
       }
       // ---- gaps at the set's start state (lambda is zero outside S)
       if (first_build) {
         // g0 = d + W~ lambda0 was formed by k_pgs_init for every row
-        for (int r = tid; r < ldS; r += PGS_NT) L.gS[r] = g0[3 * L.Sidx[r / 3] + r % 3];
+        // (single-wave chain: without the contact's own term)
+        for (int r = tid; r < ldS; r += PGS_NT) {
+          const long cr = 3L * L.Sidx[r / 3];
+          double own = 0.0;
+          if (blk)
+            for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
+          L.gS[r] = g0[cr + r % 3] - own;
+        }
         for (int c = tid; c < nc; c += PGS_NT) gnSet[c] = g0[3 * c];
       } else {
         if (blk) {
@@ -895,6 +907,8 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     double dsum = 0.0;
     __syncthreads();
     if (blk) {
+      for (int r = tid; r < ldS; r += PGS_NT) L.rec[PGS_RW * (r / 3) + 19 + r % 3] = L.lamS[r];
+      __syncthreads();
       if (wv == 0 && nS > 0) {
         if (nsp == 64)
           chain_wave<1>(nS, Wss, L, j_inner);
@@ -902,9 +916,10 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           chain_wave<2>(nS, Wss, L, j_inner);
       }
       __syncthreads();
-      // sum of squared changes of the sweep; statuses of S
+      // forces back from the records; sum of squared changes; statuses of S
       double dpart = 0.0;
       for (int r = tid; r < ldS; r += PGS_NT) {
+        L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
         const double dv = L.lamS[r] - L.lamS0[r];
         dpart += dv * dv;
       }
