@@ -206,7 +206,9 @@ typedef struct {
  */
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep);
 
-/* Scene state, device buffers of n = 3N doubles (read / overwrite). */
+/* Scene state, device buffers of n = 3N doubles (read / overwrite).
+ * icr_set_state starts a new trajectory: it also clears the per-node contact
+ * forces that warm-start the next step's PGS. */
 icr_status icr_get_state(icr_scene *s, double *q, double *v, double *t_out);
 icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double t);
 

@@ -692,6 +692,7 @@ icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double 
     ICR_HIP(hipMemcpyAsync(s->st.d_v, v, bytes, hipMemcpyDeviceToDevice, s->stream));
     s->st.t = t;
     launch_set_ctx(s, nullptr, &t);
+    launch_fill(s, s->st.d_node_force, (long)s->mesh.n, 0.0);   // a new trajectory: no warm start
     return ICR_OK;
   });
 }

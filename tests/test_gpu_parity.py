@@ -212,6 +212,33 @@ def test_step_is_deterministic(medium):
         assert torch.equal(a, b)
 
 
+def test_set_state_restarts_the_trajectory(medium):
+    """Restoring the initial state (which also clears the warm start) replays
+    the same steps bit for bit, as a fresh scene would."""
+    sc, _ = medium
+    icr = _icr()
+    s = icr.scene_from_dict(sc)
+    q0, v0, t0 = s.get_state()
+    q0, v0 = q0.clone(), v0.clone()
+    runs = []
+    for rep in range(2):
+        _say(f"[gpu] restart run {rep}")
+        s.set_state(q0, v0, t0)
+        for _ in range(2):
+            s.step(sc["obstacle"], sc["n_contacts"], sc["n_newton"], 40, 0.0, sc["j_inner"])
+        q, v, t = s.get_state()
+        r = s.step_results(sc["n_contacts"])
+        runs.append((q.cpu(), v.cpu(), r["lam"].cpu(), t))
+    fresh = icr.scene_from_dict(sc)
+    for _ in range(2):
+        fresh.step(sc["obstacle"], sc["n_contacts"], sc["n_newton"], 40, 0.0, sc["j_inner"])
+    qf, vf, tf = fresh.get_state()
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert torch.equal(a, b)
+    assert runs[0][3] == runs[1][3] == tf
+    assert torch.equal(runs[0][0], qf.cpu()) and torch.equal(runs[0][1], vf.cpu())
+
+
 def test_precision_config_sampled_against_oracle():
     """61k DOF / 1000 contacts, the benchmark configuration (30 fixed sweeps).
 
