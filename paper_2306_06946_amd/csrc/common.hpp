@@ -279,6 +279,102 @@ __device__ inline void AccM::acc(const double *A, long ars, long acs, const doub
   }
 }
 
+// Generalised MFMA tile: 4 waves as 2x2, each (16 WB) x (16 WB) of 16x16
+// blocks, output tile T = 32 WB.  The K-chunk of A (T x KT) and B (KT x T)
+// is staged in LDS as [k][i] / [k][j] rows padded to T + 1 doubles (no bank
+// conflicts for either staging order or the MFMA operand reads), the next
+// chunk is prefetched into registers while the MFMAs of the current one run.
+// WB = 4 (128 x 128) halves the operand traffic per flop of the 64 x 64 tile.
+template <int WB, int KC = KT>
+struct AccMT {
+  static constexpr int T = 32 * WB;
+  static constexpr int TP = T + 1;
+  static constexpr int NE = T * KC / 256;   // staged elements per thread and operand
+  static constexpr int LDS = 2 * KC * TP;   // doubles of LDS
+  mfma_d4 c[WB][WB];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b) c[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  // Thread tid stages, for every q < NE, element (i, k) of A: with rows
+  // contiguous (AF) i = tid % T, k = tid / T + q (256 / T); else k = tid % KC,
+  // i = tid / KC + (256 / KC) q; likewise (k, j) of B with BF.  One base pointer per
+  // operand and a constant stride per q.
+  // c += A(i, k) B(k, j) over k in [k0, k1); A(i, k) = A[i ars + k acs],
+  // B(k, j) = B[k brs + j bcs]; rows i < M and columns j < N of the tile.
+  template <bool AF, bool BF>
+  __device__ void acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M, int N, int k0,
+                      int k1, double *lds) {
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int r0 = (T / 2) * (w >> 1), c0 = (T / 2) * (w & 1);
+    const int li = l & 15, lk = l >> 4;
+    if (k0 >= k1) return;
+    constexpr int QS = 256 / T;    // k step per q when rows are contiguous
+    constexpr int QK = 256 / KC;   // row step per q when k is contiguous
+    const int ia = AF ? tid % T : tid / KC, ka = AF ? tid / T : tid % KC;
+    const int jb = BF ? tid % T : tid / KC, kbb = BF ? tid / T : tid % KC;
+    const long qa = AF ? QS * acs : QK * ars, qb = BF ? QS * brs : QK * bcs;
+    const double *pa = A + (long)ia * ars + (long)(k0 + ka) * acs;
+    const double *pb = B + (long)(k0 + kbb) * brs + (long)jb * bcs;
+    double *sa = lds + ka * TP + ia, *sb = lds + KC * TP + kbb * TP + jb;
+    const int sqa = AF ? QS * TP : QK, sqb = BF ? QS * TP : QK;
+    double ra[NE], rb[NE];
+    auto load = [&](int kb) {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int i = AF ? ia : ia + QK * q, k = kb + (AF ? ka + QS * q : ka);
+        ra[q] = (i < M && k < k1) ? pa[q * qa] : 0.0;
+        const int j = BF ? jb : jb + QK * q, kq = kb + (BF ? kbb + QS * q : kbb);
+        rb[q] = (j < N && kq < k1) ? pb[q * qb] : 0.0;
+      }
+    };
+    load(k0);
+    for (int kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        sa[q * sqa] = ra[q];
+        sb[q * sqb] = rb[q];
+      }
+      __syncthreads();
+      if (kb + KC < k1) {
+        pa += KC * acs;
+        pb += KC * brs;
+        load(kb + KC);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int k = kk + lk;
+        double av[WB], bv[WB];
+#pragma unroll
+        for (int a = 0; a < WB; ++a) av[a] = lds[k * TP + r0 + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < WB; ++b) bv[b] = lds[KC * TP + k * TP + c0 + 16 * b + li];
+#pragma unroll
+        for (int a = 0; a < WB; ++a)
+#pragma unroll
+          for (int b = 0; b < WB; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  template <class F>
+  __device__ void for_each(F &&f) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r0 = (T / 2) * (w >> 1), c0 = (T / 2) * (w & 1);
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f(r0 + 16 * a + 4 * t + (l >> 4), c0 + 16 * b + (l & 15), c[a][b][t]);
+  }
+};
+typedef AccMT<2> AccS;   // 64 x 64
+typedef AccMT<4> AccL;   // 128 x 128
+
 // The tile accumulator used by the dense kernels.
 #ifndef ICR_TILE_MFMA
 #define ICR_TILE_MFMA 1

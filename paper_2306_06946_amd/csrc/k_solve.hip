@@ -152,21 +152,23 @@ __global__ void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__rest
 }
 
 // Z_s = L_ss^{-1} X_s[:n_s]; grid (row tile, col tile, supernode)
+template <class Ac>
 __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                   const int *__restrict__ lohi, const double *__restrict__ linv,
                                                   const double *__restrict__ X, double *__restrict__ Z) {
-  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  constexpr int T = Ac::T;
+  __shared__ double lds[Ac::LDS];
   const int s = level_sup[blockIdx.z];
   const SupDev S = sup[s];
   const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
   const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
-  const int i0 = TILE * blockIdx.x, j0 = TILE * blockIdx.y;
+  const int i0 = T * blockIdx.x, j0 = T * blockIdx.y;
   if (i0 >= n3 || j0 >= r) return;
-  const int M = min(TILE, n3 - i0), N = min(TILE, r - j0);
-  const int kend = min(n3, i0 + TILE);
-  Acc acc;
+  const int M = min(T, n3 - i0), N = min(T, r - j0);
+  const int kend = min(n3, i0 + T);
+  Ac acc;
   acc.zero();
-  acc.acc(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, sA, sB);
+  acc.template acc<true, false>(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, lds);
   double *Zs = Z + S.z_off;
   acc.for_each([&](int i, int j, double v) {
     if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = v;
@@ -174,20 +176,23 @@ __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup
 }
 
 // X_s[n_s:] -= L_21 Z_s
+template <class Ac>
 __global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                  const int *__restrict__ lohi, const double *__restrict__ front,
                                                  const double *__restrict__ Z, double *__restrict__ X) {
-  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  constexpr int T = Ac::T;
+  __shared__ double lds[Ac::LDS];
   const int s = level_sup[blockIdx.z];
   const SupDev S = sup[s];
   const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int i0 = TILE * blockIdx.x, j0 = TILE * blockIdx.y;
+  const int i0 = T * blockIdx.x, j0 = T * blockIdx.y;
   if (i0 >= b3 || j0 >= r) return;
-  const int M = min(TILE, b3 - i0), N = min(TILE, r - j0);
-  Acc acc;
+  const int M = min(T, b3 - i0), N = min(T, r - j0);
+  Ac acc;
   acc.zero();
-  acc.acc(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
+  acc.template acc<true, false>(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3,
+                               lds);
   double *Xs = X + S.x_off;
   acc.for_each([&](int i, int j, double v) {
     if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= v;
@@ -195,25 +200,27 @@ __global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup,
 }
 
 // Wp[3lo + i][3lo + j] += sum_k Z(k, i) Z(k, j), lower tiles of the r x r block
+template <class Ac>
 __global__ __launch_bounds__(256) void k_rhs_syrk(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
                                                   const int *__restrict__ lohi, const double *__restrict__ Z, int m,
                                                   double *__restrict__ Wp) {
-  __shared__ double sA[KT * TILE], sB[KT * TILE];
+  constexpr int T = Ac::T;
+  __shared__ double lds[Ac::LDS];
   const int s = level_sup[blockIdx.y];
   const SupDev S = sup[s];
   const int lo = lohi[3 * s];
   const int r = 3 * (lohi[3 * s + 2] - lo);
-  const int nt = (r + TILE - 1) / TILE;
+  const int nt = (r + T - 1) / T;
   if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
   int I, J;
   tri_index(blockIdx.x, I, J);
   const int n3 = 3 * S.ncol;
-  const int i0 = TILE * I, j0 = TILE * J;
-  const int M = min(TILE, r - i0), N = min(TILE, r - j0);
+  const int i0 = T * I, j0 = T * J;
+  const int M = min(T, r - i0), N = min(T, r - j0);
   const double *Zs = Z + S.z_off;
-  Acc acc;
+  Ac acc;
   acc.zero();
-  acc.acc(Zs + (long)i0 * n3, n3, 1, Zs + (long)j0 * n3, 1, n3, M, N, 0, n3, sA, sB);
+  acc.template acc<false, false>(Zs + (long)i0 * n3, n3, 1, Zs + (long)j0 * n3, 1, n3, M, N, 0, n3, lds);
   const long base = (long)(3 * lo) * m + 3 * lo;
   acc.for_each([&](int i, int j, double v) {
     if (i < M && j < N) Wp[base + (long)(i0 + i) * m + (j0 + j)] += v;
@@ -510,15 +517,16 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     k_rhs_assemble<<<dim3(gx, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
                                                       F.d_lohi, F.d_order, node_ids, F.d_iperm, frames, F.d_X);
     ICR_LAUNCH_CHECK();
-    const int ct = cdiv(rmax, TILE);
-    k_rhs_diag<<<dim3(L.max_rows_tiles, ct, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_linv, F.d_X, F.d_Z);
+    k_rhs_diag<AccS><<<dim3(cdiv(L.max_n3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
+        F.d_sup, ls, F.d_lohi, F.d_linv, F.d_X, F.d_Z);
     ICR_LAUNCH_CHECK();
-    if (L.max_below_tiles > 0) {
-      k_rhs_off<<<dim3(L.max_below_tiles, ct, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_front, F.d_Z,
-                                                                      F.d_X);
+    if (L.max_b3 > 0) {
+      k_rhs_off<AccS><<<dim3(cdiv(L.max_b3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
+          F.d_sup, ls, F.d_lohi, F.d_front, F.d_Z, F.d_X);
       ICR_LAUNCH_CHECK();
     }
-    k_rhs_syrk<<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
+    const int ct = cdiv(rmax, AccS::T);
+    k_rhs_syrk<AccS><<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
   }
   k_wh_unpermute<<<2048, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH);
