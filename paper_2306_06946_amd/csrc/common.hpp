@@ -372,7 +372,7 @@ struct AccMT {
         for (int t = 0; t < 4; ++t) f(r0 + 16 * a + 4 * t + (l >> 4), c0 + 16 * b + (l & 15), c[a][b][t]);
   }
 };
-typedef AccMT<2> AccS;   // 64 x 64
+typedef AccMT<2, 32> AccS;   // 64 x 64, K-chunk 32
 typedef AccMT<4> AccL;   // 128 x 128
 
 // The tile accumulator used by the dense kernels.

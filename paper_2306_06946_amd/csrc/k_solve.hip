@@ -264,87 +264,128 @@ __global__ void k_fwd1_assemble(const SupDev *__restrict__ sup, const int *__res
   }
 }
 
-// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]: 16 rows x 16 k-phases per block
-__global__ __launch_bounds__(256) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                   const double *__restrict__ linv, const double *__restrict__ x1,
-                                                   double *__restrict__ y) {
-  __shared__ double part[16][17];
+// Single-RHS products, 1024 threads per block.  Column-major A times x: lane
+// = row (64 rows, coalesced), wave = k-phase (16 phases), four independent
+// accumulators per thread, phases summed in a fixed order through LDS.
+// Transposed products: one wave per column, 16 columns per block, the
+// vector staged in LDS once per block.
+constexpr int GV_R = 64, GV_P = 16, GV_X = 4096;
+
+__device__ inline double gemv_part(const double *__restrict__ A, long lda, const double *__restrict__ x, int i,
+                                   int nrows, int k0, int k1, int ph) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (i < nrows) {
+    int k = k0 + ph;
+    for (; k + 3 * GV_P < k1; k += 4 * GV_P) {
+      a0 = fma(A[i + (long)k * lda], x[k], a0);
+      a1 = fma(A[i + (long)(k + GV_P) * lda], x[k + GV_P], a1);
+      a2 = fma(A[i + (long)(k + 2 * GV_P) * lda], x[k + 2 * GV_P], a2);
+      a3 = fma(A[i + (long)(k + 3 * GV_P) * lda], x[k + 3 * GV_P], a3);
+    }
+    for (; k < k1; k += GV_P) a0 = fma(A[i + (long)k * lda], x[k], a0);
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
+// Sum of the 16 phase partials of row r (valid in wave 0).
+__device__ inline double phase_sum(double v, double (*part)[GV_R + 1]) {
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  part[ph][r] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (ph == 0)
+    for (int q = 0; q < GV_P; ++q) t += part[q][r];
+  return t;
+}
+
+// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]
+__global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                    const double *__restrict__ linv, const double *__restrict__ x1,
+                                                    double *__restrict__ y) {
+  __shared__ double part[GV_P][GV_R + 1];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
-  const int i0 = 16 * blockIdx.x;
-  if (i0 >= n3) return;
-  const int r = threadIdx.x & 15, ph = threadIdx.x >> 4;
-  const int i = i0 + r;
-  const int kend = min(n3, i0 + 16);
-  const double *Li = linv + S.linv_off;
-  const double *xs = x1 + S.x1_off;
-  double acc = 0.0;
-  if (i < n3)
-    for (int k = ph; k < kend; k += 16) acc = fma(Li[i + (long)k * n3], xs[k], acc);
-  part[ph][r] = acc;
-  __syncthreads();
-  if (ph == 0 && i < n3) {
-    double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += part[q][r];
-    y[3 * S.col0 + i] = t;
-  }
+  const int i0 = GV_R * blockIdx.x;
+  if (i0 >= n3) return;   // uniform over the block
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
+  const double v = gemv_part(linv + S.linv_off, n3, x1 + S.x1_off, i, n3, 0, min(n3, i0 + GV_R), ph);
+  const double t = phase_sum(v, part);
+  if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
 }
 
-// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]: 16 rows x 16 k-phases per block
-__global__ __launch_bounds__(256) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                  const double *__restrict__ front, const double *__restrict__ y,
-                                                  double *__restrict__ x1) {
-  __shared__ double part[16][17];
+// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]
+__global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                   const double *__restrict__ front, const double *__restrict__ y,
+                                                   double *__restrict__ x1) {
+  __shared__ double part[GV_P][GV_R + 1];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int i0 = 16 * blockIdx.x;
+  const int i0 = GV_R * blockIdx.x;
   if (i0 >= b3) return;
-  const int r = threadIdx.x & 15, ph = threadIdx.x >> 4;
-  const int i = i0 + r;
-  const double *F = front + S.front_off + n3;
-  const double *ys = y + 3 * S.col0;
-  double acc = 0.0;
-  if (i < b3)
-    for (int k = ph; k < n3; k += 16) acc = fma(F[i + (long)k * f], ys[k], acc);
-  part[ph][r] = acc;
-  __syncthreads();
-  if (ph == 0 && i < b3) {
-    double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += part[q][r];
-    x1[S.x1_off + n3 + i] -= t;
-  }
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
+  const double v = gemv_part(front + S.front_off + n3, f, y + 3 * S.col0, i, b3, 0, n3, ph);
+  const double t = phase_sum(v, part);
+  if (ph == 0 && i < b3) x1[S.x1_off + n3 + i] -= t;
 }
 
-// y_s[j] -= sum_i L21(i, j) x[below row i]: one wave per column, 4 columns per block
-__global__ __launch_bounds__(256) void k_bwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                  const int *__restrict__ rows, const double *__restrict__ front,
-                                                  const double *__restrict__ xp, double *__restrict__ y) {
+// y_s[j] -= sum_i L21(i, j) x[below row i]
+__global__ __launch_bounds__(1024) void k_bwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                   const int *__restrict__ rows, const double *__restrict__ front,
+                                                   const double *__restrict__ xp, double *__restrict__ y) {
+  __shared__ double xg[GV_X];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int j = 4 * blockIdx.x + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
+  const int j0 = GV_P * blockIdx.x;
+  if (j0 >= n3) return;
+  const int *rw = rows + S.rows_off;
+  const int bs = min(b3, GV_X);
+  for (int i = threadIdx.x; i < bs; i += 1024) xg[i] = xp[3 * rw[i / 3] + i % 3];
+  __syncthreads();
+  const int j = j0 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (j >= n3) return;
   const double *F = front + S.front_off + n3 + (long)j * f;
-  const int *rw = rows + S.rows_off;
-  double acc = 0.0;
-  for (int i = l; i < b3; i += 64) acc = fma(F[i], xp[3 * rw[i / 3] + i % 3], acc);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = l;
+  for (; i + 192 < bs; i += 256) {
+    a0 = fma(F[i], xg[i], a0);
+    a1 = fma(F[i + 64], xg[i + 64], a1);
+    a2 = fma(F[i + 128], xg[i + 128], a2);
+    a3 = fma(F[i + 192], xg[i + 192], a3);
+  }
+  for (; i < bs; i += 64) a0 = fma(F[i], xg[i], a0);
+  for (; i < b3; i += 64) a0 = fma(F[i], xp[3 * rw[i / 3] + i % 3], a0);
+  double acc = (a0 + a1) + (a2 + a3);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (l == 0) y[3 * S.col0 + j] -= acc;
 }
 
-// xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]: one wave per column
-__global__ __launch_bounds__(256) void k_bwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                   const double *__restrict__ linv, const double *__restrict__ y,
-                                                   double *__restrict__ xp) {
+// xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]
+__global__ __launch_bounds__(1024) void k_bwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                    const double *__restrict__ linv, const double *__restrict__ y,
+                                                    double *__restrict__ xp) {
+  __shared__ double yg[GV_X];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
-  const int j = 4 * blockIdx.x + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
+  const int j0 = GV_P * blockIdx.x;
+  if (j0 >= n3) return;
+  const double *ys = y + 3 * S.col0;
+  const int ns = min(n3, GV_X);
+  for (int i = j0 + threadIdx.x; i < ns; i += 1024) yg[i] = ys[i];
+  __syncthreads();
+  const int j = j0 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (j >= n3) return;
   const double *Lc = linv + S.linv_off + (long)j * n3;
-  const double *ys = y + 3 * S.col0;
-  double acc = 0.0;
-  for (int i = j + l; i < n3; i += 64) acc = fma(Lc[i], ys[i], acc);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = j + l;
+  for (; i + 192 < ns; i += 256) {
+    a0 = fma(Lc[i], yg[i], a0);
+    a1 = fma(Lc[i + 64], yg[i + 64], a1);
+    a2 = fma(Lc[i + 128], yg[i + 128], a2);
+    a3 = fma(Lc[i + 192], yg[i + 192], a3);
+  }
+  for (; i < ns; i += 64) a0 = fma(Lc[i], yg[i], a0);
+  for (; i < n3; i += 64) a0 = fma(Lc[i], ys[i], a0);
+  double acc = (a0 + a1) + (a2 + a3);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (l == 0) xp[3 * S.col0 + j] = acc;
 }
@@ -373,10 +414,10 @@ void backward_solve(icr_scene *s, double *x) {
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
     if (L.max_b3 > 0) {
-      k_bwd1_off<<<dim3(cdiv(L.max_n3, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
+      k_bwd1_off<<<dim3(cdiv(L.max_n3, GV_P), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
       ICR_LAUNCH_CHECK();
     }
-    k_bwd1_diag<<<dim3(cdiv(L.max_n3, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
+    k_bwd1_diag<<<dim3(cdiv(L.max_n3, GV_P), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
     ICR_LAUNCH_CHECK();
   }
   k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
@@ -385,29 +426,20 @@ void backward_solve(icr_scene *s, double *x) {
 
 // y[3 col0_s + i] = sum_c Z_s(i, c) f[contact at column c]: the forward half of
 // A^-1 H^T f reuses Z = L^-1 P H^T from the W_H build of the same contacts.
-// One block per (64-row tile, supernode): 64 rows x 4 column phases.
-__global__ __launch_bounds__(256) void k_zf(const SupDev *__restrict__ sup, const int *__restrict__ lohi,
-                                            const double *__restrict__ Z, const double *__restrict__ fpos,
-                                            double *__restrict__ y) {
-  __shared__ double part[4][64];
+__global__ __launch_bounds__(1024) void k_zf(const SupDev *__restrict__ sup, const int *__restrict__ lohi,
+                                             const double *__restrict__ Z, const double *__restrict__ fpos,
+                                             double *__restrict__ y) {
+  __shared__ double part[GV_P][GV_R + 1];
   const int s = blockIdx.y;
   const SupDev S = sup[s];
   const int n3 = 3 * S.ncol;
-  const int i0 = 64 * blockIdx.x;
+  const int i0 = GV_R * blockIdx.x;
   if (i0 >= n3) return;
   const int lo = lohi[3 * s], r = 3 * (lohi[3 * s + 2] - lo);
-  const int rr = threadIdx.x & 63, ph = threadIdx.x >> 6;
-  const int i = i0 + rr;
-  const double *Zs = Z + S.z_off;
-  const double *fs = fpos + 3 * lo;
-  double acc = 0.0;
-  if (i < n3) {
-#pragma unroll 4
-    for (int c = ph; c < r; c += 4) acc = fma(Zs[i + (long)c * n3], fs[c], acc);
-  }
-  part[ph][rr] = acc;
-  __syncthreads();
-  if (ph == 0 && i < n3) y[3 * S.col0 + i] = (part[0][rr] + part[1][rr]) + (part[2][rr] + part[3][rr]);
+  const int rr = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + rr;
+  const double v = gemv_part(Z + S.z_off, n3, fpos + 3 * lo, i, n3, 0, r, ph);
+  const double t = phase_sum(v, part);
+  if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
 }
 
 // fpos[3 p + a] = f[3 order[p] + a]
@@ -432,10 +464,10 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
     k_fwd1_assemble<<<dim3(cdiv(L.max_f3, 256), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
                                                                           F.d_invmap, F.d_perm, b, F.d_x1);
     ICR_LAUNCH_CHECK();
-    k_fwd1_diag<<<dim3(cdiv(L.max_n3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
+    k_fwd1_diag<<<dim3(cdiv(L.max_n3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
     ICR_LAUNCH_CHECK();
     if (L.max_b3 > 0) {
-      k_fwd1_off<<<dim3(cdiv(L.max_b3, 16), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
+      k_fwd1_off<<<dim3(cdiv(L.max_b3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
       ICR_LAUNCH_CHECK();
     }
   }
@@ -450,7 +482,7 @@ void contact_force_solve(icr_scene *s, const double *f, double *x) {
   const int nc = s->last_build_nc;
   k_gather_fpos<<<cdiv(3 * nc, 256), 256, 0, s->stream>>>(nc, F.d_order, f, F.d_fpos);
   ICR_LAUNCH_CHECK();
-  k_zf<<<dim3(cdiv(max_n3, 64), nsup), 256, 0, s->stream>>>(F.d_sup, F.d_lohi, F.d_Z, F.d_fpos, F.d_y);
+  k_zf<<<dim3(cdiv(max_n3, GV_R), nsup), 1024, 0, s->stream>>>(F.d_sup, F.d_lohi, F.d_Z, F.d_fpos, F.d_y);
   ICR_LAUNCH_CHECK();
   backward_solve(s, x);
 }
