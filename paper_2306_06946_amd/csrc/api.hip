@@ -76,6 +76,10 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
   C.pgs.gnSet = C.arena.alloc<double>(nc);
   C.pgs.swn = C.arena.alloc<double>(nc);
+  C.pgs.Sidx = C.arena.alloc<int>(nc);
+  C.pgs.nS = C.arena.alloc<int>(1);
+  C.pgs.rec = C.arena.alloc<double>(pgs_rec_elems());
+  C.pgs.gS = C.arena.alloc<double>(pgs_rec_elems());
   C.pgs.ctl = C.arena.alloc<int>(2);
   pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);

@@ -741,6 +741,89 @@ __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int
   }
 }
 
+// The active set of the first sweep, its compact couplings and records are
+// prepared by wide kernels before the sequential kernel starts (a set that
+// grows later is rebuilt inside k_pgs_active).
+// k_pgs_set: S = {c : lambda_c != 0 or g0_n(c) < 0} in ascending order,
+// the normal gaps at the set's start and sqrt(W~_nn) of every contact.
+__global__ __launch_bounds__(1024) void k_pgs_set(int nc, const double *__restrict__ W, const double *__restrict__ g0,
+                                                  const double *__restrict__ lam, double h2, int *__restrict__ Sidx,
+                                                  int *__restrict__ nS_out, double *__restrict__ gnSet,
+                                                  double *__restrict__ swn) {
+  __shared__ int wcount[PGS_MAX_NC / 64 + 1];
+  const int m = 3 * nc;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int nwin = (nc + 63) / 64;
+  auto in_set = [&](int c) {
+    return c < nc && (lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0 || g0[3 * c] < 0.0);
+  };
+  for (int w = wv; w < nwin; w += 16) {
+    const unsigned long long bal = __ballot(in_set(64 * w + ln));
+    if (ln == 0) wcount[w] = __popcll(bal);
+  }
+  for (int c = tid; c < nc; c += 1024) {
+    gnSet[c] = g0[3 * c];
+    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int w = 0; w < nwin; ++w) {
+      const int t = wcount[w];
+      wcount[w] = acc;
+      acc += t;
+    }
+    *nS_out = acc;
+  }
+  __syncthreads();
+  for (int w = wv; w < nwin; w += 16) {
+    const int c = 64 * w + ln;
+    const bool in = in_set(c);
+    const unsigned long long bal = __ballot(in);
+    if (in) Sidx[wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+  }
+}
+
+// k_pgs_gather (any grid): for a set of at most PGS_WAVE_MAX contacts, the
+// blocked W~_SS with zero diagonal blocks, the per-contact records and the
+// gaps without the own term, e = g0 - W~_cc lambda_c.
+__global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__restrict__ W,
+                                                    const double *__restrict__ g0, const double *__restrict__ lam,
+                                                    const double *__restrict__ mu, double h2,
+                                                    const int *__restrict__ Sidx, const int *__restrict__ nS_in,
+                                                    double *__restrict__ Wss, double *__restrict__ rec,
+                                                    double *__restrict__ gS) {
+  const int nS = *nS_in;
+  if (nS == 0 || nS > PGS_WAVE_MAX) return;
+  const int m = 3 * nc, nsp = pgs_wave_pad(nS);
+  const long stride = (long)gridDim.x * blockDim.x, t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nel = (long)nS * nsp * PGS_BLK;
+  for (long e = t0; e < nel; e += stride) {
+    const int j = (int)(e % PGS_BLK);
+    const long ic = e / PGS_BLK;
+    const int c = (int)(ic % nsp), i = (int)(ic / nsp);
+    double v = 0.0;
+    if (j < 9 && c < nS && c != i) v = h2 * W[(3L * Sidx[c] + j / 3) * m + 3L * Sidx[i] + j % 3];
+    Wss[e] = v;
+  }
+  for (long i = t0; i < nS; i += stride) {
+    double wb[3][3];
+    const long ci = 3L * Sidx[i];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) wb[p][q] = h2 * W[(ci + p) * m + ci + q];
+    double tmp[19];
+    make_record(wb, mu[Sidx[i]], tmp);
+    for (int q = 0; q < 19; ++q) rec[PGS_RW * i + q] = tmp[q];
+  }
+  for (long r = t0; r < 3L * nS; r += stride) {
+    const long cr = 3L * Sidx[r / 3];
+    const int a = (int)(r % 3);
+    double own = 0.0;
+    for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + a) * m + cr + q], lam[cr + q], own);
+    gS[r] = g0[cr + a] - own;
+  }
+}
+
 __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__restrict__ W,
                                                        const double *__restrict__ d, const double *__restrict__ g0,
                                                        const double *__restrict__ mu, double h2,
@@ -748,7 +831,10 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
                                                        int max_sweeps, double tol, int j_inner,
                                                        int *__restrict__ sweeps_out, double *__restrict__ eps_out,
                                                        double *__restrict__ Wss, double *__restrict__ gnSet,
-                                                       double *__restrict__ swn, int *__restrict__ ctl) {
+                                                       const double *__restrict__ swn, int *__restrict__ ctl,
+                                                       const int *__restrict__ preSidx, const int *__restrict__ preN,
+                                                       const double *__restrict__ preRec,
+                                                       const double *__restrict__ preGS) {
   extern __shared__ double lds_raw[];
   PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
   const int m = 3 * nc;
@@ -756,8 +842,8 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   for (int c = tid; c < nc; c += PGS_NT) {
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
     L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
-    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
   }
+  const int npre = *preN;   // set prepared by k_pgs_set / k_pgs_gather
   if (tid == 0) {
     L.stop = 0;
     ctl[0] = 0;
@@ -769,6 +855,24 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   double eps = 0.0;
   bool need_build = true, first_build = true;
   while (sweep < max_sweeps) {
+    if (need_build && first_build && npre <= PGS_WAVE_MAX) {
+      // ---- the prepared first set: copy it in
+      nS = npre;
+      ldS = 3 * nS;
+      blk = true;
+      nsp = pgs_wave_pad(nS);
+      for (int i = tid; i < nS; i += PGS_NT) L.Sidx[i] = preSidx[i];
+      for (int e = tid; e < nS * 19; e += PGS_NT) L.rec[PGS_RW * (e / 19) + e % 19] = preRec[PGS_RW * (e / 19) + e % 19];
+      for (int r = tid; r < ldS; r += PGS_NT) L.gS[r] = preGS[r];
+      __syncthreads();
+      for (int r = tid; r < ldS; r += PGS_NT) {
+        L.lamS[r] = lam[3 * L.Sidx[r / 3] + r % 3];
+        L.lamSet[r] = L.lamS[r];
+      }
+      __syncthreads();
+      need_build = false;
+      first_build = false;
+    }
     if (need_build) {
       // ---- ordered list of S (ballot per 64-contact window, prefix by thread 0)
       const int nwin = (nc + 63) / 64;
@@ -853,7 +957,6 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
             for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
           L.gS[r] = g0[cr + r % 3] - own;
         }
-        for (int c = tid; c < nc; c += PGS_NT) gnSet[c] = g0[3 * c];
       } else {
         if (blk) {
           for (int c = wv; c < nS; c += PGS_NW) {
@@ -1132,14 +1235,21 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   const int m = 3 * nc;
   k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
+  k_pgs_set<<<1, 1024, 0, st>>>(nc, W, wk.g, lam, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn);
+  ICR_LAUNCH_CHECK();
+  k_pgs_gather<<<512, 256, 0, st>>>(nc, W, wk.g, lam, mu, h * h, wk.Sidx, wk.nS, wk.Wss, wk.rec, wk.gS);
+  ICR_LAUNCH_CHECK();
   k_pgs_active<<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
-                                                sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl);
+                                                sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl, wk.Sidx,
+                                                wk.nS, wk.rec, wk.gS);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
   k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
                                    eps_dev, wk.ctl);
   ICR_LAUNCH_CHECK();
 }
+
+size_t pgs_rec_elems() { return (size_t)PGS_WAVE_MAX * PGS_RW; }
 
 size_t pgs_wss_elems() {
   return std::max((size_t)PGS_S3 * PGS_S3, (size_t)PGS_WAVE_MAX * PGS_WAVE_MAX * PGS_BLK);

@@ -97,6 +97,8 @@ struct Factor {
 struct PgsWork {
   double *g = nullptr, *Wss = nullptr;
   double *gnSet = nullptr, *swn = nullptr;   // per contact: normal gap at the set's start state, sqrt(W~_nn)
+  int *Sidx = nullptr, *nS = nullptr;         // first active set (ascending contact ids) and its size
+  double *rec = nullptr, *gS = nullptr;       // its records and gaps (sets of at most 128 contacts)
   int *ctl = nullptr;
 };
 
@@ -206,6 +208,7 @@ void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 2560;
 size_t pgs_wss_elems();
+size_t pgs_rec_elems();   // doubles of the prepared records (and gaps) of a first active set
 void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
