@@ -442,6 +442,43 @@ __device__ double block_sum(double v, double *red) {
   return s;   // valid in thread 0
 }
 
+// Deterministic block reductions over the active-set kernel's threads (valid
+// in thread 0): three sums at once, and a minimum.
+__device__ void block_sum3(double &a, double &b, double &c, double *red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  __syncthreads();
+  if (l == 0) {
+    red[w] = a;
+    red[16 + w] = b;
+    red[32 + w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = c = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      a += red[i];
+      b += red[16 + i];
+      c += red[32 + i];
+    }
+  }
+}
+__device__ double block_min(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double r = INFINITY;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) r = fmin(r, red[i]);
+  return r;
+}
+
 // g0 = d + h^2 W lambda0, one wave per row (the PGS start state).
 __global__ __launch_bounds__(256) void k_pgs_init(int m, const double *__restrict__ W, const double *__restrict__ d,
                                                   const double *__restrict__ lam, double h2, double *__restrict__ g) {
@@ -609,13 +646,14 @@ struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
   double bc[3];
-  double red[16];
+  double red[48];
   int Sidx[PGS_SMAX];
   unsigned char stS[PGS_SMAX];
   int wcount[64];
   int ulist[PGS_MAX_NC];
   unsigned char inS[PGS_MAX_NC];
-  int nS, flag, stop, nu;
+  double Rmin;   // settle threshold of the set: B below it settles every skipped contact
+  int nS, flag, stop, nu, zflag, settled;
 };
 
 // Padded contact count of the blocked layout: 64 contacts per register slot.
@@ -846,6 +884,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   const int npre = *preN;   // set prepared by k_pgs_set / k_pgs_gather
   if (tid == 0) {
     L.stop = 0;
+    L.zflag = 0;
     ctl[0] = 0;
     ctl[1] = 0;
   }
@@ -853,7 +892,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   int sweep = 0, nS = 0, ldS = 0, nsp = 0;
   bool blk = true;
   double eps = 0.0;
-  bool need_build = true, first_build = true;
+  bool need_build = true, first_build = true, built = false;
   while (sweep < max_sweeps) {
     if (need_build && first_build && npre <= PGS_WAVE_MAX) {
       // ---- the prepared first set: copy it in
@@ -872,6 +911,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       __syncthreads();
       need_build = false;
       first_build = false;
+      built = true;
     }
     if (need_build) {
       // ---- ordered list of S (ballot per 64-contact window, prefix by thread 0)
@@ -1000,6 +1040,30 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       __syncthreads();
       need_build = false;
       first_build = false;
+      built = true;
+    }
+    if (built) {
+      // Settle threshold of the new set.  A skipped contact c is settled when
+      // g - sqrt(W~_cc) B > 1e-13 (|g| + sqrt(W~_cc) B), i.e. (sqrt(W~_cc) > 0)
+      // B < (g - 1e-13 |g|) / (sqrt(W~_cc) (1 + 1e-13)); Rmin is the smallest
+      // of these bounds, shrunk by 1e-12 for rounding, so B < Rmin settles
+      // all of them at once (else the per-contact test runs).
+      double rmin = INFINITY;
+      int zf = 0;
+      for (int c = tid; c < nc; c += PGS_NT) {
+        if (L.inS[c]) continue;
+        const double g = gnSet[c], w = swn[c];
+        if (w > 0.0)
+          rmin = fmin(rmin, (g - 1e-13 * fabs(g)) / (w * (1.0 + 1e-13)));
+        else if (!(g > 0.0))
+          zf = 1;
+        status[c] = (int8_t)ICR_SEPARATE;
+      }
+      if (zf) atomicOr(&L.zflag, 1);
+      const double rm = block_min(rmin, L.red);
+      if (tid == 0) L.Rmin = rm > 0.0 ? rm * (1.0 - 1e-12) : rm * (1.0 + 1e-12);
+      __syncthreads();
+      built = false;
     }
     // ---- sweep over S from its start state
     for (int r = tid; r < ldS; r += PGS_NT) L.lamS0[r] = L.lamS[r];
@@ -1019,15 +1083,9 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           chain_wave<2>(nS, Wss, L, j_inner);
       }
       __syncthreads();
-      // forces back from the records; sum of squared changes; statuses of S
-      double dpart = 0.0;
-      for (int r = tid; r < ldS; r += PGS_NT) {
-        L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
-        const double dv = L.lamS[r] - L.lamS0[r];
-        dpart += dv * dv;
-      }
-      for (int i = tid; i < nS; i += PGS_NT) status[L.Sidx[i]] = (int8_t)L.stS[i];
-      dsum = block_sum(dpart, L.red);
+      // forces back from the records
+      for (int r = tid; r < ldS; r += PGS_NT) L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
+      __syncthreads();
     } else {
       // block-wide chain: wave 0 solves, every thread updates three rows
       constexpr int RB = PGS_S3 / PGS_NT;
@@ -1078,24 +1136,36 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         __syncthreads();
       }
     }
-    // ---- verify the skipped contacts
-    // bound factor B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
-    double bpart = 0.0;
+    // ---- one pass over S: sum of squared changes of the sweep, |lambda|^2,
+    // and the bound factor of the skipped contacts' gaps
+    // B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
+    double dpart = 0.0, bpart = 0.0, npart = 0.0;
     for (int r = tid; r < ldS; r += PGS_NT) {
       const double *rc = L.rec + PGS_RW * (r / 3);
       const double wqq = (r % 3 == 0) ? rc[0] : ((r % 3 == 1) ? rc[3] : rc[5]);
-      const double dv = fmax(fabs(L.lamS[r] - L.lamSet[r]), fabs(L.lamS0[r] - L.lamSet[r]));
-      bpart += sqrt(wqq) * dv;
+      const double ls = L.lamS[r], l0 = L.lamS0[r], lset = L.lamSet[r];
+      const double dv = ls - l0;
+      dpart += dv * dv;
+      bpart += sqrt(wqq) * fmax(fabs(ls - lset), fabs(l0 - lset));
+      npart += ls * ls;
     }
-    const double Bsum = block_sum(bpart, L.red);
-    if (tid == 0) L.red[0] = Bsum;
+    block_sum3(dpart, bpart, npart, L.red);
+    if (tid == 0) {
+      const double diff = sqrt(blk ? dpart : dsum), nl = sqrt(npart);
+      eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
+      L.stop = (eps <= tol) ? 1 : 0;
+      L.red[0] = bpart * (1.0 + 1e-12);
+      L.settled = (L.zflag == 0 && L.red[0] < L.Rmin) ? 1 : 0;
+    }
     __syncthreads();
-    const double B = L.red[0] * (1.0 + 1e-12);
-    for (int c = tid; c < nc; c += PGS_NT) {
-      if (L.inS[c]) continue;
-      const double g = gnSet[c], rb = swn[c] * B;
-      if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
-      status[c] = (int8_t)ICR_SEPARATE;
+    const double B = L.red[0];
+    // ---- verify the skipped contacts (all settled at once when B < Rmin)
+    if (!L.settled) {
+      for (int c = tid; c < nc; c += PGS_NT) {
+        if (L.inS[c]) continue;
+        const double g = gnSet[c], rb = swn[c] * B;
+        if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
+      }
     }
     __syncthreads();
     const int nu = L.nu;
@@ -1121,19 +1191,12 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       __syncthreads();
       continue;
     }
-    double part = 0.0;
-    for (int r = tid; r < ldS; r += PGS_NT) part += L.lamS[r] * L.lamS[r];
-    double nl2 = block_sum(part, L.red);
-    if (tid == 0) {
-      double diff = sqrt(dsum), nl = sqrt(nl2);
-      eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
-      L.stop = (eps <= tol) ? 1 : 0;
-    }
-    __syncthreads();
     ++sweep;
     if (L.stop) break;
   }
   for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS[r];
+  if (blk)
+    for (int i = tid; i < nS; i += PGS_NT) status[L.Sidx[i]] = (int8_t)L.stS[i];
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
