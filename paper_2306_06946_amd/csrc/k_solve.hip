@@ -106,48 +106,59 @@ __global__ void k_ranges(int nsup, int nc, const SupDev *__restrict__ sup, const
 
 // ---- multi-RHS forward ------------------------------------------------------
 
-__global__ void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                               const int *__restrict__ child, const int *__restrict__ invmap_off,
-                               const int *__restrict__ invmap, const int *__restrict__ lohi,
-                               const int *__restrict__ order, const int *__restrict__ node_ids,
-                               const int *__restrict__ iperm, const double *__restrict__ frames,
-                               double *__restrict__ X) {
+// X_s column by column (one wave per column, 4 columns per block): a column
+// of an own contact is a unit vector of H^T (or a column of J^T = H^T C^T
+// when frames are given); a column of a contact below a child is the child's
+// below-row part extended into the front rows (extend-add through invmap).
+// Everything that identifies the column is uniform over the wave.
+__global__ __launch_bounds__(256) void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                      const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                                      const int *__restrict__ invmap, const int *__restrict__ lohi,
+                                                      const int *__restrict__ order, const int *__restrict__ node_ids,
+                                                      const int *__restrict__ iperm, const double *__restrict__ frames,
+                                                      double *__restrict__ X) {
   const int s = level_sup[blockIdx.y];
   const SupDev S = sup[s];
   const int lo = lohi[3 * s], own = lohi[3 * s + 1], hi = lohi[3 * s + 2];
   const int r = 3 * (hi - lo);
-  if (r == 0) return;
+  const int jc = 4 * blockIdx.x + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (jc >= r) return;
   const int f = 3 * (S.ncol + S.nb);
-  const long total = (long)f * r;
-  double *Xs = X + S.x_off;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(e % f), jc = (int)(e / f);
-    const int p = lo + jc / 3, a = jc % 3;
-    double v = 0.0;
-    if (p >= own) {
-      // column of H^T (unit vector), or of J^T = H^T C^T when frames are given
-      const int c = order[p];
-      const int base = 3 * (iperm[node_ids[c]] - S.col0);
+  double *Xc = X + S.x_off + (long)jc * f;
+  const int p = lo + jc / 3, a = jc % 3;
+  if (p >= own) {
+    const int c = order[p];
+    const int base = 3 * (iperm[node_ids[c]] - S.col0);
+    for (int i = l; i < f; i += 64) {
+      double v;
       if (frames == nullptr)
         v = (i == base + a) ? 1.0 : 0.0;
       else
         v = (i >= base && i < base + 3) ? frames[9L * c + 3 * a + (i - base)] : 0.0;
-    } else {
-      for (int c = 0; c < S.nchild; ++c) {
-        const int ch = child[S.child_off + c];
-        const int clo = lohi[3 * ch], chi = lohi[3 * ch + 2];
-        if (p >= clo && p < chi) {
-          const int ii = invmap[invmap_off[S.child_off + c] + i / 3];
-          if (ii >= 0) {
-            const SupDev C = sup[ch];
-            const int fc = 3 * (C.ncol + C.nb);
-            v = X[C.x_off + (long)(3 * C.ncol + 3 * ii + i % 3) + (long)(jc - 3 * (clo - lo)) * fc];
-          }
-          break;
-        }
-      }
+      Xc[i] = v;
     }
-    Xs[e] = v;
+    return;
+  }
+  int cc = -1, clo = 0;
+  for (int q = 0; q < S.nchild; ++q) {
+    const int ch = child[S.child_off + q];
+    if (p >= lohi[3 * ch] && p < lohi[3 * ch + 2]) {
+      cc = q;
+      clo = lohi[3 * ch];
+      break;
+    }
+  }
+  if (cc < 0) {   // not below any child (cannot happen for sorted contacts)
+    for (int i = l; i < f; i += 64) Xc[i] = 0.0;
+    return;
+  }
+  const SupDev C = sup[child[S.child_off + cc]];
+  const int fc = 3 * (C.ncol + C.nb);
+  const int *im = invmap + invmap_off[S.child_off + cc];
+  const double *src = X + C.x_off + (long)(jc - 3 * (clo - lo)) * fc + 3 * C.ncol;
+  for (int i = l; i < f; i += 64) {
+    const int ii = im[i / 3];
+    Xc[i] = (ii >= 0) ? src[3 * ii + i % 3] : 0.0;
   }
 }
 
@@ -231,16 +242,38 @@ __global__ void k_fill(long n, double v, double *__restrict__ x) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
 }
 
-// W_H[3c+a][3c'+b] = Wp at the positions of c, c' (lower triangle read).
-__global__ void k_wh_unpermute(int nc, const int *__restrict__ pos, const double *__restrict__ Wp,
-                               double *__restrict__ WH) {
-  const int m = 3 * nc;
-  const long total = (long)m * m;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    int i = (int)(e / m), j = (int)(e % m);
-    int pi = 3 * pos[i / 3] + i % 3, pj = 3 * pos[j / 3] + j % 3;
-    WH[e] = (pi >= pj) ? Wp[(long)pi * m + pj] : Wp[(long)pj * m + pi];
+// Mirror the lower triangle of Wp (supernode order) into the upper one,
+// 64 x 64 tiles through LDS so that both the read and the transposed write
+// are coalesced; tiles (I >= J) of the lower triangle.
+__global__ __launch_bounds__(256) void k_wp_mirror(int m, double *__restrict__ Wp) {
+  __shared__ double t[64][65];
+  const int nt = (m + 63) / 64;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int I, J;
+  tri_index(blockIdx.x, I, J);
+  const int i0 = 64 * I, j0 = 64 * J;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    t[r][tx] = (i < m && j < m) ? Wp[(long)i * m + j] : 0.0;
   }
+  __syncthreads();
+  // upper entry (j0 + r, i0 + tx) = lower entry (i0 + tx, j0 + r) when strictly below the diagonal
+  for (int r = ty; r < 64; r += 4) {
+    const int row = j0 + r, col = i0 + tx;
+    if (row < m && col < m && col > row) Wp[(long)row * m + col] = t[tx][r];
+  }
+}
+
+// W_H[3c+a][3c'+b] = Wp[3 pos(c) + a][3 pos(c') + b] (Wp symmetric): one
+// block per output row, the source row stays in cache.
+__global__ __launch_bounds__(256) void k_wh_unpermute(int nc, const int *__restrict__ pos, const double *__restrict__ Wp,
+                                                      double *__restrict__ WH) {
+  const int m = 3 * nc;
+  const int i = blockIdx.x;
+  const double *src = Wp + (long)(3 * pos[i / 3] + i % 3) * m;
+  double *dst = WH + (long)i * m;
+  for (int j = threadIdx.x; j < m; j += 256) dst[j] = src[3 * pos[j / 3] + j % 3];
 }
 
 // ---- single RHS -------------------------------------------------------------
@@ -270,6 +303,7 @@ __global__ void k_fwd1_assemble(const SupDev *__restrict__ sup, const int *__res
 // Transposed products: one wave per column, 16 columns per block, the
 // vector staged in LDS once per block.
 constexpr int GV_R = 64, GV_P = 16, GV_X = 4096;
+constexpr int ZF_K = 256;   // columns of Z per chunk of the Z f product
 
 __device__ inline double gemv_part(const double *__restrict__ A, long lda, const double *__restrict__ x, int i,
                                    int nrows, int k0, int k1, int ph) {
@@ -426,20 +460,35 @@ void backward_solve(icr_scene *s, double *x) {
 
 // y[3 col0_s + i] = sum_c Z_s(i, c) f[contact at column c]: the forward half of
 // A^-1 H^T f reuses Z = L^-1 P H^T from the W_H build of the same contacts.
-__global__ __launch_bounds__(1024) void k_zf(const SupDev *__restrict__ sup, const int *__restrict__ lohi,
-                                             const double *__restrict__ Z, const double *__restrict__ fpos,
-                                             double *__restrict__ y) {
-  __shared__ double part[GV_P][GV_R + 1];
-  const int s = blockIdx.y;
+// k_zf_part: one task = 64 rows x one chunk of ZF_K columns of Z_s, partial
+// sums to part[off + chunk n3 + row]; k_zf_sum adds the chunks in order.
+__global__ __launch_bounds__(1024) void k_zf_part(const int4 *__restrict__ tasks, const SupDev *__restrict__ sup,
+                                                  const int *__restrict__ lohi, const double *__restrict__ Z,
+                                                  const double *__restrict__ fpos, double *__restrict__ part) {
+  __shared__ double ps[GV_P][GV_R + 1];
+  const int4 tk = tasks[blockIdx.x];
+  const int s = tk.x, i0 = tk.y, k0 = tk.z;
   const SupDev S = sup[s];
   const int n3 = 3 * S.ncol;
-  const int i0 = GV_R * blockIdx.x;
-  if (i0 >= n3) return;
   const int lo = lohi[3 * s], r = 3 * (lohi[3 * s + 2] - lo);
+  if (k0 >= r && k0 > 0) return;   // chunk beyond this call's columns (chunk 0 always writes)
   const int rr = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + rr;
-  const double v = gemv_part(Z + S.z_off, n3, fpos + 3 * lo, i, n3, 0, r, ph);
-  const double t = phase_sum(v, part);
-  if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
+  const double v = gemv_part(Z + S.z_off, n3, fpos + 3 * lo, i, n3, k0, min(r, k0 + ZF_K), ph);
+  const double t = phase_sum(v, ps);
+  if (ph == 0 && i < n3) part[tk.w + (long)(k0 / ZF_K) * n3 + i] = t;
+}
+__global__ void k_zf_sum(const int4 *__restrict__ tasks, const SupDev *__restrict__ sup,
+                         const int *__restrict__ lohi, const double *__restrict__ part, double *__restrict__ y) {
+  const int4 tk = tasks[blockIdx.x];
+  const int s = tk.x, i = tk.y + (int)threadIdx.x;
+  const SupDev S = sup[s];
+  const int n3 = 3 * S.ncol;
+  if (i >= n3) return;
+  const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
+  const int nch = max(1, (r + ZF_K - 1) / ZF_K);
+  double acc = 0.0;
+  for (int ch = 0; ch < nch; ++ch) acc += part[tk.w + (long)ch * n3 + i];
+  y[3 * S.col0 + i] = acc;
 }
 
 // fpos[3 p + a] = f[3 order[p] + a]
@@ -476,13 +525,12 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
 
 void contact_force_solve(icr_scene *s, const double *f, double *x) {
   auto &F = s->fac;
-  int max_n3 = 0;
-  for (const auto &L : F.levels) max_n3 = std::max(max_n3, L.max_n3);
-  const int nsup = (int)F.sup.size();
   const int nc = s->last_build_nc;
   k_gather_fpos<<<cdiv(3 * nc, 256), 256, 0, s->stream>>>(nc, F.d_order, f, F.d_fpos);
   ICR_LAUNCH_CHECK();
-  k_zf<<<dim3(cdiv(max_n3, GV_R), nsup), 1024, 0, s->stream>>>(F.d_sup, F.d_lohi, F.d_Z, F.d_fpos, F.d_y);
+  k_zf_part<<<F.n_zf_tasks, 1024, 0, s->stream>>>(F.d_zf_tasks, F.d_sup, F.d_lohi, F.d_Z, F.d_fpos, F.d_zf_part);
+  ICR_LAUNCH_CHECK();
+  k_zf_sum<<<F.n_zf_sum_tasks, GV_R, 0, s->stream>>>(F.d_zf_tasks, F.d_sup, F.d_lohi, F.d_zf_part, F.d_y);
   ICR_LAUNCH_CHECK();
   backward_solve(s, x);
 }
@@ -518,6 +566,27 @@ void ensure_rhs_capacity(icr_scene *s, int nc) {
   F.d_lohi = F.rhs_arena.alloc<int>(3LL * F.sup.size());
   F.d_fpos = F.rhs_arena.alloc<double>(3LL * nc);
   F.d_cerr = F.rhs_arena.alloc<int>(1);
+  {
+    // Z f tasks: one per (supernode, 64-row block, column chunk of ZF_K), the
+    // chunk-0 tasks first (they also do the sums); partials per supernode at
+    // off_s + chunk * n3 + row
+    std::vector<int4> first, rest;
+    long long off = 0;
+    for (int i = 0; i < (int)F.sup.size(); ++i) {
+      const SupDev &d = F.sup[i];
+      const int n3 = 3 * d.ncol, nch = std::max(1, cdiv(d.rmax, ZF_K));
+      for (int i0 = 0; i0 < n3; i0 += GV_R)
+        for (int ch = 0; ch < nch; ++ch) (ch == 0 ? first : rest).push_back(make_int4(i, i0, ch * ZF_K, (int)off));
+      off += (long long)n3 * nch;
+    }
+    F.n_zf_sum_tasks = (int)first.size();
+    first.insert(first.end(), rest.begin(), rest.end());
+    F.n_zf_tasks = (int)first.size();
+    F.d_zf_tasks = F.rhs_arena.alloc<int4>(first.size());
+    F.d_zf_part = F.rhs_arena.alloc<double>(std::max<long long>(1, off));
+    ICR_HIP(hipMemcpyAsync(F.d_zf_tasks, first.data(), first.size() * sizeof(int4), hipMemcpyHostToDevice,
+                           s->stream));
+  }
   ICR_HIP(hipMemcpyAsync(F.d_sup, F.sup.data(), F.sup.size() * sizeof(SupDev), hipMemcpyHostToDevice, s->stream));
   ICR_HIP(hipStreamSynchronize(s->stream));
   F.nc_cap = nc;
@@ -544,9 +613,7 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     int rmax = 0;
     for (int q = 0; q < L.count; ++q) rmax = std::max(rmax, F.sup[F.sym.level_sup[L.first + q]].rmax);
     if (rmax == 0) continue;
-    long long fr = (long long)L.max_f3 * rmax;
-    int gx = (int)std::min<long long>(2048, (fr + 255) / 256);
-    k_rhs_assemble<<<dim3(gx, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
+    k_rhs_assemble<<<dim3(cdiv(rmax, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
                                                       F.d_lohi, F.d_order, node_ids, F.d_iperm, frames, F.d_X);
     ICR_LAUNCH_CHECK();
     k_rhs_diag<AccS><<<dim3(cdiv(L.max_n3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
@@ -561,7 +628,12 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     k_rhs_syrk<AccS><<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, st>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
   }
-  k_wh_unpermute<<<2048, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH);
+  {
+    const int nt = cdiv(m, 64);
+    k_wp_mirror<<<nt * (nt + 1) / 2, 256, 0, st>>>((int)m, F.d_Wp);
+    ICR_LAUNCH_CHECK();
+  }
+  k_wh_unpermute<<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH);
   ICR_LAUNCH_CHECK();
 }
 

@@ -87,6 +87,10 @@ struct Factor {
   int nc_cap = 0;
   double *d_X = nullptr, *d_Z = nullptr, *d_Wp = nullptr, *d_fpos = nullptr;
   int *d_keys = nullptr, *d_order = nullptr, *d_pos = nullptr, *d_lohi = nullptr, *d_cerr = nullptr;
+  // Z f in column chunks: tasks (supernode, first row, first column, partial offset)
+  int4 *d_zf_tasks = nullptr;
+  int n_zf_tasks = 0, n_zf_sum_tasks = 0;   // the first n_zf_sum_tasks tasks have chunk 0
+  double *d_zf_part = nullptr;
   Arena rhs_arena;
   // single-RHS work vectors (permuted)
   double *d_y = nullptr;
