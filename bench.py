@@ -78,6 +78,90 @@ def profiled_traffic(kernel):
     return None
 
 
+def serving_leg(n_scenes, rate, sweeps, seconds=2.0):
+    """Serving mix through icr_server: closed-loop saturation with 1 and 4
+    slots, then Poisson arrivals at `rate` steps/s over `seconds`."""
+    import torch
+    from paper_2306_06946_amd import icr
+    from paper_2306_06946_amd.scenes import make_scene
+    t0 = time.perf_counter()
+    scs = [make_scene("serving", 100 + i) for i in range(n_scenes)]
+    scenes = []
+    for sc in scs:
+        s = icr.scene_from_dict(sc)
+        s.step(sc["obstacle"], sc["n_contacts"], sc["n_newton"], sweeps, 0.0, sc["j_inner"], report=False)
+        scenes.append(s)
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {n_scenes} scenes ready in {time.perf_counter() - t0:.1f} s")
+    out = {"scenes": n_scenes, "nodes": [len(sc["nodes"]) for sc in scs], "contacts": [sc["n_contacts"] for sc in scs],
+           "pgs_sweeps": sweeps, "hbm_budget_bytes": 200 << 30}
+
+    def closed_loop(slots, per_scene):
+        srv = icr.Server(hbm_budget=200 << 30, slots=slots)
+        ids = [srv.admit(s) for s in scenes]
+        left = {i: per_scene for i in ids}
+        lat = []
+        ts = time.perf_counter()
+        for i, sc in zip(ids, scs):
+            srv.submit(i, sc["obstacle"], sc["n_contacts"], sc["n_newton"], sweeps, 0.0, sc["j_inner"])
+            left[i] -= 1
+        done = 0
+        while done < per_scene * len(ids):
+            comp, _ = srv.poll(wait=True)
+            for c in comp:
+                done += 1
+                lat.append(c["latency_ms"])
+                i = c["scene"]
+                if left[i] > 0:
+                    sc = scs[ids.index(i)]
+                    srv.submit(i, sc["obstacle"], sc["n_contacts"], sc["n_newton"], sweeps, 0.0, sc["j_inner"])
+                    left[i] -= 1
+        el = time.perf_counter() - ts
+        used = srv.used()
+        srv.close()
+        for s in scenes:
+            s.set_stream(torch.cuda.current_stream().cuda_stream)
+        lat = np.array(lat)
+        return dict(slots=slots, steps=int(done), steps_per_s=done / el, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), admitted_bytes=int(used))
+
+    out["closed_loop_1_slot"] = closed_loop(1, 10)
+    out["closed_loop_4_slots"] = closed_loop(4, 10)
+    log(f"[bench] serving closed loop: 1 slot {out['closed_loop_1_slot']['steps_per_s']:.0f} steps/s, "
+        f"4 slots {out['closed_loop_4_slots']['steps_per_s']:.0f} steps/s")
+    # open loop: Poisson arrivals, random scene per arrival
+    rng = np.random.default_rng(7)
+    n_req = int(rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    which = rng.integers(0, n_scenes, size=n_req)
+    srv = icr.Server(hbm_budget=200 << 30, slots=4)
+    ids = [srv.admit(s) for s in scenes]
+    lat = []
+    k = 0
+    ts = time.perf_counter()
+    while len(lat) < n_req:
+        now = time.perf_counter() - ts
+        while k < n_req and arrivals[k] <= now:
+            sc = scs[which[k]]
+            srv.submit(ids[which[k]], sc["obstacle"], sc["n_contacts"], sc["n_newton"], sweeps, 0.0, sc["j_inner"],
+                       tag=k)
+            k += 1
+        comp, _ = srv.poll(wait=False)
+        lat += [c["latency_ms"] for c in comp]   # from submission, made as soon as the arrival time passes
+    el = time.perf_counter() - ts
+    srv.close()
+    for s in scenes:
+        s.set_stream(torch.cuda.current_stream().cuda_stream)
+    lat = np.array(lat)
+    out["poisson"] = dict(rate_steps_per_s=rate, requests=n_req, elapsed_s=el, achieved_steps_per_s=n_req / el,
+                          p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), slots=4)
+    log(f"[bench] serving poisson {rate:.0f}/s: achieved {n_req / el:.0f}/s p50 {out['poisson']['p50_ms']:.2f} ms "
+        f"p99 {out['poisson']['p99_ms']:.2f} ms")
+    for s in scenes:
+        s.close()
+    return out
+
+
 def cpu_baseline(sc, sweeps, budget_cols):
     """The FP64 oracle on a bounded sample of the same step.
 
@@ -151,6 +235,10 @@ def main():
                     help="also time this many steps of the standard rebuild scheme (Algorithm 2); 0 = skip")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step eagerly instead of replaying the captured step graph")
+    ap.add_argument("--serving", type=int, default=0, metavar="SCENES",
+                    help="also run the serving mix: this many independent scenes (node count 500-8000, 10-500 "
+                         "contacts) stepped through icr_server; 0 = skip")
+    ap.add_argument("--serving-rate", type=float, default=2000.0, help="Poisson arrival rate (steps/s, all scenes)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (5 launches) and exit: the "
                          "calibration kernel for HBM byte counters")
@@ -285,6 +373,8 @@ def main():
             "metric_scope_speedup": sp["ms_newton"] / (fp["ms_build_WH"] + fp["ms_newton"]),
         }
         s2.close()
+    if args.serving > 0:
+        out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)...")
         out["cpu_baseline"] = cpu_baseline(sc, args.sweeps, args.cpu_cols)

@@ -234,6 +234,62 @@ icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int3
                        int32_t *sup, int32_t nsup_cap, int32_t *rows_ptr, int32_t *rows, int32_t rows_cap,
                        int32_t *nsup_out, int32_t *nrows_out);
 
+/* ---------------------------------------------------------------------------
+ * Serving: many independent scenes stepped concurrently on one GPU.
+ *
+ * A server holds admitted scenes (each keeps its factor, W_H buffers and
+ * warm start resident) and a FIFO of step requests.  icr_server_poll launches
+ * queued requests on free slots -- one HIP stream per slot, one request in
+ * flight per slot and per scene -- as soon as a slot frees up (continuous
+ * admission), and returns the requests that completed.  Requests of one
+ * scene run in submission order; those of different scenes overlap on the
+ * device.  A request runs exactly icr_step(scene, obstacle, opts, NULL) on
+ * the slot's stream, so its results equal the same step run alone.
+ * Scenes are admitted against a device-memory budget: the sum of the
+ * admitted scenes' library-owned device bytes (icr_factor_info.device_bytes
+ * at admission; admit a scene after one warm-up step so that its contact
+ * and multi-RHS buffers are counted) may not exceed it.  Not thread-safe; the
+ * server does not own the scenes (destroy them after the server).
+ * ------------------------------------------------------------------------- */
+typedef struct icr_server icr_server;
+
+typedef struct {
+  uint64_t tag;        /* the caller's request id (icr_server_submit) */
+  int32_t scene;       /* scene id (icr_server_admit) */
+  int32_t status;      /* icr_status of the step */
+  double latency_ms;   /* submission -> completion seen by icr_server_poll (host clock) */
+  double queue_ms;     /* submission -> launch */
+} icr_completion;
+
+/* slots in [1, 16] (the GPU runs up to its hardware queue count of streams
+ * at once); hbm_budget in bytes (> 0). */
+icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots);
+void icr_server_destroy(icr_server *srv); /* waits for the requests in flight */
+const char *icr_server_last_error(const icr_server *srv);
+
+/* Admit a factored scene with candidates set; *scene_id receives its id.
+ * Synchronises the device once (the scene's set-up work must be complete
+ * before its steps run on the slot streams).  ICR_E_OOM (nothing admitted)
+ * when it would exceed the budget.  While admitted, the scene's stream is
+ * the slot stream of its last request: set it back (icr_set_stream) before
+ * calling the scene directly, after its requests have completed. */
+icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id);
+/* Remove an idle scene (no request queued or in flight: else ICR_E_STATE);
+ * its bytes return to the budget.  The scene itself is not destroyed. */
+icr_status icr_server_evict(icr_server *srv, int32_t scene_id);
+/* Device bytes currently admitted (host out). */
+icr_status icr_server_used(const icr_server *srv, int64_t *bytes);
+
+/* Queue one time step of an admitted scene (obstacle and options copied). */
+icr_status icr_server_submit(icr_server *srv, int32_t scene_id, const icr_obstacle *obs, const icr_step_opts *opt,
+                             uint64_t tag);
+/* Launch what fits on free slots, then collect completed requests into
+ * out[0 .. cap); *n_out receives their count.  With wait != 0 it blocks until
+ * at least one request completes (returns at once if nothing is queued or in
+ * flight).  *pending_out (may be NULL) receives queued + in-flight requests. */
+icr_status icr_server_poll(icr_server *srv, icr_completion *out, int32_t cap, int32_t *n_out, int32_t wait,
+                           int32_t *pending_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,13 +73,13 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_WH = C.arena.alloc<double>(m * m);
   C.d_W = C.arena.alloc<double>(m * m);
   C.pgs.g = C.arena.alloc<double>(m);
-  C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems());
+  C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems(nc));
   C.pgs.gnSet = C.arena.alloc<double>(nc);
   C.pgs.swn = C.arena.alloc<double>(nc);
   C.pgs.Sidx = C.arena.alloc<int>(nc);
   C.pgs.nS = C.arena.alloc<int>(1);
-  C.pgs.rec = C.arena.alloc<double>(pgs_rec_elems());
-  C.pgs.gS = C.arena.alloc<double>(pgs_rec_elems());
+  C.pgs.rec = C.arena.alloc<double>(pgs_rec_elems(nc));
+  C.pgs.gS = C.arena.alloc<double>(pgs_rec_elems(nc));
   C.pgs.ctl = C.arena.alloc<int>(2);
   pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);

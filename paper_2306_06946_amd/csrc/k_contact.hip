@@ -640,12 +640,13 @@ constexpr int PGS_SMAX = 512;
 constexpr int PGS_S3 = 3 * PGS_SMAX;
 constexpr int PGS_NT = 512;   // threads of the active-set kernel
 constexpr int PGS_NW = PGS_NT / 64;
-constexpr int PGS_WAVE_MAX = 128;   // largest set swept by the single-wave chain (register budget)
+constexpr int PGS_WAVE_MAX = 512;   // largest set swept by the register chains (= PGS_SMAX)
 constexpr int PGS_BLK = 10;         // doubles per 3x3 block of the blocked W~_SS (9 used, 16-byte aligned)
 struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
   double bc[3];
+  double ebuf[2][3];   // gap of the current contact, published by its owning wave
   double red[48];
   int Sidx[PGS_SMAX];
   unsigned char stS[PGS_SMAX];
@@ -656,8 +657,9 @@ struct PgsLds {
   int nS, flag, stop, nu, zflag, settled;
 };
 
-// Padded contact count of the blocked layout: 64 contacts per register slot.
-__host__ __device__ inline int pgs_wave_pad(int nS) { return nS <= 64 ? 64 : 128; }
+// Padded contact count of the blocked layout: 64 contacts per register slot,
+// two slots per chain wave beyond 64 contacts.
+__host__ __device__ inline int pgs_wave_pad(int nS) { return nS <= 64 ? 64 : 128 * ((nS + 127) / 128); }
 
 __device__ inline double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -779,6 +781,98 @@ __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int
   }
 }
 
+// Sweep over a set of 129..512 contacts by Q = ceil(nS / 128) chain waves:
+// wave w keeps the gaps of contacts 128 w .. 128 w + 127 in two register
+// slots.  Per contact the owning wave publishes e_i through LDS, one block
+// barrier follows, then every chain wave runs the same local solve and
+// updates its own rows (the other waves only take the barriers).
+__device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
+  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const bool chain = w < Q;
+  const long colstride = (long)(128 * Q) * (PGS_BLK / 2);   // double2 per contact column (nsp = 128 Q)
+  double g[2][3];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int c = 128 * w + 64 * k + ln;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[k][q] = (chain && c < nS) ? L.gS[3 * c + q] : 0.0;
+  }
+  const int last = nS - 1;
+  // block (rows of contact c, columns of contact i) at double2 (i nsp + c) 5
+  const double2 *W2 = reinterpret_cast<const double2 *>(Wb) + (long)(128 * w + ln) * (PGS_BLK / 2);
+  auto load = [&](double2 (&X)[2][PGS_BLK / 2], int i) {
+    const double2 *base = W2 + (long)i * colstride;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[k * 64 * (PGS_BLK / 2) + j];
+  };
+  double2 A[2][PGS_BLK / 2], B[2][PGS_BLK / 2];
+  ChainRec rA, rB;
+  if (chain) {
+    load(A, 0);
+    load(B, min(1, last));
+    chain_rec(rA, L, 0);
+  }
+  auto step = [&](int i, const double2 (&X)[2][PGS_BLK / 2], const ChainRec &c) {
+    const int owner = i >> 7, k = (i >> 6) & 1, li = i & 63;
+    if (w == owner) {
+      const double e0 = readlane_f64(k ? g[1][0] : g[0][0], li);
+      const double e1 = readlane_f64(k ? g[1][1] : g[0][1], li);
+      const double e2 = readlane_f64(k ? g[1][2] : g[0][2], li);
+      if (ln == 0) {
+        L.ebuf[i & 1][0] = e0;
+        L.ebuf[i & 1][1] = e1;
+        L.ebuf[i & 1][2] = e2;
+      }
+    }
+    __syncthreads();
+    if (!chain) return;
+    double rc[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) rc[q] = c[q];
+    const double lo0 = c[19], lo1 = c[20], lo2 = c[21];
+    double dd[3] = {L.ebuf[i & 1][0], L.ebuf[i & 1][1], L.ebuf[i & 1][2]};
+    const Local rs = local_solve_rec(rc, dd, j_inner);
+    if (w == 0 && ln == 0) {
+      double *lp = L.rec + PGS_RW * i + 19;
+      lp[0] = rs.l[0];
+      lp[1] = rs.l[1];
+      lp[2] = rs.l[2];
+      L.stS[i] = (unsigned char)rs.st;
+    }
+    const double d0 = rs.l[0] - lo0, d1 = rs.l[1] - lo1, d2 = rs.l[2] - lo2;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const double b[9] = {X[kk][0].x, X[kk][0].y, X[kk][1].x, X[kk][1].y, X[kk][2].x,
+                           X[kk][2].y, X[kk][3].x, X[kk][3].y, X[kk][4].x};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        g[kk][a] = fma(b[3 * a + 2], d2, fma(b[3 * a + 1], d1, fma(b[3 * a], d0, g[kk][a])));
+    }
+  };
+  for (int i = 0; i < nS; i += 2) {
+    if (chain) chain_rec(rB, L, min(i + 1, last));
+    step(i, A, rA);
+    if (chain) load(A, min(i + 2, last));
+    if (i + 1 < nS) {
+      if (chain) chain_rec(rA, L, min(i + 2, last));
+      step(i + 1, B, rB);
+    }
+    if (chain) load(B, min(i + 3, last));
+  }
+  if (chain) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int c = 128 * w + 64 * k + ln;
+      if (c < nS) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[k][q];
+      }
+    }
+  }
+}
+
 // The active set of the first sweep, its compact couplings and records are
 // prepared by wide kernels before the sequential kernel starts (a set that
 // grows later is rebuilt inside k_pgs_active).
@@ -890,7 +984,6 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
   }
   __syncthreads();
   int sweep = 0, nS = 0, ldS = 0, nsp = 0;
-  bool blk = true;
   double eps = 0.0;
   bool need_build = true, first_build = true, built = false;
   while (sweep < max_sweeps) {
@@ -898,7 +991,6 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       // ---- the prepared first set: copy it in
       nS = npre;
       ldS = 3 * nS;
-      blk = true;
       nsp = pgs_wave_pad(nS);
       for (int i = tid; i < nS; i += PGS_NT) L.Sidx[i] = preSidx[i];
       for (int e = tid; e < nS * 19; e += PGS_NT) L.rec[PGS_RW * (e / 19) + e % 19] = preRec[PGS_RW * (e / 19) + e % 19];
@@ -948,16 +1040,14 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       }
       __syncthreads();
       ldS = 3 * nS;
-      blk = nS <= PGS_WAVE_MAX;
       nsp = pgs_wave_pad(nS);
       for (int r = tid; r < ldS; r += PGS_NT) {
         L.lamS[r] = lam[3 * L.Sidx[r / 3] + r % 3];
         L.lamSet[r] = L.lamS[r];
       }
       // ---- compact couplings W~_SS: blocked [i][c] 3x3 blocks of rows c,
-      // columns i (padded to nsp contacts) for the single-wave chain, else
-      // row-major
-      if (blk) {
+      // columns i (padded to nsp contacts), zero diagonal blocks
+      {
         const long nel = (long)nS * nsp * PGS_BLK;
         for (long e = tid; e < nel; e += PGS_NT) {
           const int j = (int)(e % PGS_BLK);
@@ -966,12 +1056,6 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           double v = 0.0;
           if (j < 9 && c < nS && c != i) v = h2 * W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
           Wss[e] = v;
-        }
-      } else {
-        const long ns2 = (long)ldS * ldS;
-        for (long e = tid; e < ns2; e += PGS_NT) {
-          const int r = (int)(e / ldS), q = (int)(e % ldS);
-          Wss[e] = h2 * W[(3L * L.Sidx[r / 3] + r % 3) * m + 3L * L.Sidx[q / 3] + q % 3];
         }
       }
       __threadfence_block();
@@ -988,44 +1072,34 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       }
       // ---- gaps at the set's start state (lambda is zero outside S)
       if (first_build) {
-        // g0 = d + W~ lambda0 was formed by k_pgs_init for every row
-        // (single-wave chain: without the contact's own term)
+        // g0 = d + W~ lambda0 was formed by k_pgs_init for every row; the
+        // chains keep the gap without the contact's own term
         for (int r = tid; r < ldS; r += PGS_NT) {
           const long cr = 3L * L.Sidx[r / 3];
           double own = 0.0;
-          if (blk)
-            for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
+          for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
           L.gS[r] = g0[cr + r % 3] - own;
         }
       } else {
-        if (blk) {
-          for (int c = wv; c < nS; c += PGS_NW) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int i = ln; i < nS; i += 64) {
-              const double *b = Wss + ((long)i * nsp + c) * PGS_BLK;
-              const double l0 = L.lamS[3 * i], l1 = L.lamS[3 * i + 1], l2 = L.lamS[3 * i + 2];
-              a0 += b[0] * l0 + b[1] * l1 + b[2] * l2;
-              a1 += b[3] * l0 + b[4] * l1 + b[5] * l2;
-              a2 += b[6] * l0 + b[7] * l1 + b[8] * l2;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-              a0 += __shfl_xor(a0, o, 64);
-              a1 += __shfl_xor(a1, o, 64);
-              a2 += __shfl_xor(a2, o, 64);
-            }
-            if (ln == 0) {
-              const int cc = 3 * L.Sidx[c];
-              L.gS[3 * c] = d[cc] + a0;
-              L.gS[3 * c + 1] = d[cc + 1] + a1;
-              L.gS[3 * c + 2] = d[cc + 2] + a2;
-            }
+        for (int c = wv; c < nS; c += PGS_NW) {
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+          for (int i = ln; i < nS; i += 64) {
+            const double *b = Wss + ((long)i * nsp + c) * PGS_BLK;
+            const double l0 = L.lamS[3 * i], l1 = L.lamS[3 * i + 1], l2 = L.lamS[3 * i + 2];
+            a0 += b[0] * l0 + b[1] * l1 + b[2] * l2;
+            a1 += b[3] * l0 + b[4] * l1 + b[5] * l2;
+            a2 += b[6] * l0 + b[7] * l1 + b[8] * l2;
           }
-        } else {
-          for (int r = wv; r < ldS; r += PGS_NW) {
-            double a = 0.0;
-            for (int q = ln; q < ldS; q += 64) a = fma(Wss[(long)r * ldS + q], L.lamS[q], a);
-            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-            if (ln == 0) L.gS[r] = d[3 * L.Sidx[r / 3] + r % 3] + a;
+          for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+            a2 += __shfl_xor(a2, o, 64);
+          }
+          if (ln == 0) {
+            const int cc = 3 * L.Sidx[c];
+            L.gS[3 * c] = d[cc] + a0;
+            L.gS[3 * c + 1] = d[cc + 1] + a1;
+            L.gS[3 * c + 2] = d[cc + 2] + a2;
           }
         }
         for (int c = wv; c < nc; c += PGS_NW) {
@@ -1071,71 +1145,25 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       L.flag = 0;
       L.nu = 0;
     }
-    double dsum = 0.0;
     __syncthreads();
-    if (blk) {
-      for (int r = tid; r < ldS; r += PGS_NT) L.rec[PGS_RW * (r / 3) + 19 + r % 3] = L.lamS[r];
-      __syncthreads();
-      if (wv == 0 && nS > 0) {
-        if (nsp == 64)
-          chain_wave<1>(nS, Wss, L, j_inner);
-        else
-          chain_wave<2>(nS, Wss, L, j_inner);
-      }
-      __syncthreads();
-      // forces back from the records
-      for (int r = tid; r < ldS; r += PGS_NT) L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
-      __syncthreads();
-    } else {
-      // block-wide chain: wave 0 solves, every thread updates three rows
-      constexpr int RB = PGS_S3 / PGS_NT;
-      double pf[RB][3];
-      for (int j = 0; j < RB; ++j)
-        for (int b = 0; b < 3; ++b) {
-          const int r = tid + PGS_NT * j;
-          pf[j][b] = r < ldS ? Wss[(long)b * ldS + r] : 0.0;
-        }
-      for (int i = 0; i < nS; ++i) {
+    for (int r = tid; r < ldS; r += PGS_NT) L.rec[PGS_RW * (r / 3) + 19 + r % 3] = L.lamS[r];
+    __syncthreads();
+    if (nS > 0) {
+      if (nS <= 128) {
         if (wv == 0) {
-          const double *rc = L.rec + PGS_RW * i;
-          double lo[3], dd[3];
-          for (int q = 0; q < 3; ++q) lo[q] = L.lamS[3 * i + q];
-          dd[0] = L.gS[3 * i] - (rc[0] * lo[0] + rc[1] * lo[1] + rc[2] * lo[2]);
-          dd[1] = L.gS[3 * i + 1] - (rc[1] * lo[0] + rc[3] * lo[1] + rc[4] * lo[2]);
-          dd[2] = L.gS[3 * i + 2] - (rc[2] * lo[0] + rc[4] * lo[1] + rc[5] * lo[2]);
-          Local rs = local_solve_rec(rc, dd, j_inner);
-          double dl[3];
-          for (int q = 0; q < 3; ++q) {
-            dl[q] = rs.l[q] - lo[q];
-            dsum += dl[q] * dl[q];
-          }
-          if (ln == 0) {
-            for (int q = 0; q < 3; ++q) {
-              L.bc[q] = dl[q];
-              L.lamS[3 * i + q] = rs.l[q];
-            }
-            status[L.Sidx[i]] = (int8_t)rs.st;
-          }
+          if (nsp == 64)
+            chain_wave<1>(nS, Wss, L, j_inner);
+          else
+            chain_wave<2>(nS, Wss, L, j_inner);
         }
-        __syncthreads();
-        const double d0 = L.bc[0], d1 = L.bc[1], d2 = L.bc[2];
-        if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
-          for (int j = 0; j < RB; ++j) {
-            const int r = tid + PGS_NT * j;
-            if (r < ldS) L.gS[r] += pf[j][0] * d0 + pf[j][1] * d1 + pf[j][2] * d2;
-          }
-        }
-        if (i + 1 < nS) {
-          const long base = (long)(3 * (i + 1)) * ldS;
-          for (int j = 0; j < RB; ++j)
-            for (int b = 0; b < 3; ++b) {
-              const int r = tid + PGS_NT * j;
-              if (r < ldS) pf[j][b] = Wss[base + (long)b * ldS + r];
-            }
-        }
-        __syncthreads();
+      } else {
+        chain_multi(nS, (nS + 127) / 128, Wss, L, j_inner);
       }
     }
+    __syncthreads();
+    // forces back from the records
+    for (int r = tid; r < ldS; r += PGS_NT) L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
+    __syncthreads();
     // ---- one pass over S: sum of squared changes of the sweep, |lambda|^2,
     // and the bound factor of the skipped contacts' gaps
     // B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
@@ -1151,7 +1179,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     }
     block_sum3(dpart, bpart, npart, L.red);
     if (tid == 0) {
-      const double diff = sqrt(blk ? dpart : dsum), nl = sqrt(npart);
+      const double diff = sqrt(dpart), nl = sqrt(npart);
       eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
       L.stop = (eps <= tol) ? 1 : 0;
       L.red[0] = bpart * (1.0 + 1e-12);
@@ -1195,8 +1223,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     if (L.stop) break;
   }
   for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS[r];
-  if (blk)
-    for (int i = tid; i < nS; i += PGS_NT) status[L.Sidx[i]] = (int8_t)L.stS[i];
+  for (int i = tid; i < nS; i += PGS_NT) status[L.Sidx[i]] = (int8_t)L.stS[i];
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
@@ -1312,10 +1339,11 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   ICR_LAUNCH_CHECK();
 }
 
-size_t pgs_rec_elems() { return (size_t)PGS_WAVE_MAX * PGS_RW; }
+size_t pgs_rec_elems(int nc) { return (size_t)std::min(nc, PGS_WAVE_MAX) * PGS_RW; }
 
-size_t pgs_wss_elems() {
-  return std::max((size_t)PGS_S3 * PGS_S3, (size_t)PGS_WAVE_MAX * PGS_WAVE_MAX * PGS_BLK);
+size_t pgs_wss_elems(int nc) {
+  const int n = std::min(nc, PGS_WAVE_MAX);
+  return (size_t)n * pgs_wave_pad(n) * PGS_BLK;
 }
 
 void pgs_prepare() {

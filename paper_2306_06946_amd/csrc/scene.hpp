@@ -211,8 +211,8 @@ void launch_advance_time(icr_scene *s);
 void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 2560;
-size_t pgs_wss_elems();
-size_t pgs_rec_elems();   // doubles of the prepared records (and gaps) of a first active set
+size_t pgs_wss_elems(int nc);   // doubles of the blocked coupling matrix of an active set (n_c contacts)
+size_t pgs_rec_elems(int nc);   // doubles of the prepared records (and gaps) of a first active set
 void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,

@@ -1,0 +1,259 @@
+// Serving runtime: admitted scenes, a FIFO of step requests and a fixed set
+// of slots (one HIP stream each).  Only the public C ABI of the scenes is
+// used: a request is icr_step(scene, obstacle, opts, NULL) enqueued on the
+// slot's stream, followed by an event that marks its completion.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "icr.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Request {
+  uint64_t tag = 0;
+  int scene = -1;
+  icr_obstacle obs{};
+  icr_step_opts opt{};
+  Clock::time_point t_submit, t_launch;
+};
+
+struct SceneEntry {
+  icr_scene *s = nullptr;
+  int64_t bytes = 0;
+  bool admitted = false;
+  bool busy = false;   // a request of this scene is in flight
+  int queued = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool running = false;
+  Request req;
+};
+
+struct ServerError : std::runtime_error {
+  icr_status code;
+  ServerError(icr_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) throw ServerError(ICR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct icr_server {
+  int64_t budget = 0, used = 0;
+  std::vector<Slot> slots;
+  std::vector<SceneEntry> scenes;
+  std::deque<Request> queue;
+  std::string err;
+};
+
+namespace {
+
+template <class F>
+icr_status guarded_srv(icr_server *srv, F &&body) {
+  if (!srv) return ICR_E_ARG;
+  srv->err.clear();
+  try {
+    return body();
+  } catch (const ServerError &e) {
+    srv->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    srv->err = "host allocation failed";
+    return ICR_E_OOM;
+  } catch (const std::exception &e) {
+    srv->err = e.what();
+    return ICR_E_HIP;
+  }
+}
+
+SceneEntry &entry(icr_server *srv, int id) {
+  if (id < 0 || id >= (int)srv->scenes.size() || !srv->scenes[id].admitted)
+    throw ServerError(ICR_E_ARG, "unknown scene id " + std::to_string(id));
+  return srv->scenes[id];
+}
+
+// Start queued requests on free slots: the oldest request whose scene is idle.
+void launch_ready(icr_server *srv) {
+  for (auto &sl : srv->slots) {
+    if (sl.running) continue;
+    auto it = srv->queue.begin();
+    while (it != srv->queue.end() && srv->scenes[it->scene].busy) ++it;
+    if (it == srv->queue.end()) return;
+    Request r = *it;
+    srv->queue.erase(it);
+    SceneEntry &se = srv->scenes[r.scene];
+    se.queued--;
+    icr_status st = icr_set_stream(se.s, sl.stream);
+    if (st == ICR_OK) st = icr_step(se.s, &r.obs, &r.opt, nullptr);
+    if (st != ICR_OK && st != ICR_WARN_NOT_CONVERGED)
+      throw ServerError(st, std::string("step of scene ") + std::to_string(r.scene) + " failed: " +
+                                icr_last_error(se.s));
+    hip_check(hipEventRecord(sl.done, sl.stream), "hipEventRecord");
+    r.t_launch = Clock::now();
+    sl.req = r;
+    sl.running = true;
+    se.busy = true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots) {
+  if (!out) return ICR_E_ARG;
+  *out = nullptr;
+  if (hbm_budget <= 0 || slots < 1 || slots > 16) return ICR_E_ARG;
+  icr_server *srv = new (std::nothrow) icr_server;
+  if (!srv) return ICR_E_OOM;
+  srv->budget = hbm_budget;
+  srv->slots.resize(slots);
+  for (auto &sl : srv->slots) {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      icr_server_destroy(srv);
+      return ICR_E_HIP;
+    }
+  }
+  *out = srv;
+  return ICR_OK;
+}
+
+void icr_server_destroy(icr_server *srv) {
+  if (!srv) return;
+  for (auto &sl : srv->slots) {
+    if (sl.running && sl.done) (void)hipEventSynchronize(sl.done);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  delete srv;
+}
+
+const char *icr_server_last_error(const icr_server *srv) { return srv ? srv->err.c_str() : "null server"; }
+
+icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id) {
+  return guarded_srv(srv, [&] {
+    if (!scene || !scene_id) throw ServerError(ICR_E_ARG, "NULL scene or id pointer");
+    for (const auto &e : srv->scenes)
+      if (e.admitted && e.s == scene) throw ServerError(ICR_E_ARG, "scene already admitted");
+    // the scene's own stream may still hold its set-up work; requests will run
+    // on the slot streams, so drain the device once here
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    icr_factor_info info{};
+    const icr_status st = icr_get_factor_info(scene, &info);
+    if (st != ICR_OK) throw ServerError(st, std::string("scene not ready: ") + icr_last_error(scene));
+    if (srv->used + info.device_bytes > srv->budget)
+      throw ServerError(ICR_E_OOM, "admission refused: " + std::to_string(info.device_bytes) + " bytes with " +
+                                       std::to_string(srv->used) + " of " + std::to_string(srv->budget) +
+                                       " in use");
+    SceneEntry e;
+    e.s = scene;
+    e.bytes = info.device_bytes;
+    e.admitted = true;
+    srv->scenes.push_back(e);
+    srv->used += info.device_bytes;
+    *scene_id = (int32_t)srv->scenes.size() - 1;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_server_evict(icr_server *srv, int32_t scene_id) {
+  return guarded_srv(srv, [&] {
+    SceneEntry &e = entry(srv, scene_id);
+    if (e.busy || e.queued > 0) throw ServerError(ICR_E_STATE, "scene has requests queued or in flight");
+    srv->used -= e.bytes;
+    e.admitted = false;
+    e.s = nullptr;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_server_used(const icr_server *srv, int64_t *bytes) {
+  if (!srv || !bytes) return ICR_E_ARG;
+  *bytes = srv->used;
+  return ICR_OK;
+}
+
+icr_status icr_server_submit(icr_server *srv, int32_t scene_id, const icr_obstacle *obs, const icr_step_opts *opt,
+                             uint64_t tag) {
+  return guarded_srv(srv, [&] {
+    SceneEntry &e = entry(srv, scene_id);
+    if (!obs || !opt) throw ServerError(ICR_E_ARG, "NULL obstacle or options");
+    Request r;
+    r.tag = tag;
+    r.scene = scene_id;
+    r.obs = *obs;
+    r.opt = *opt;
+    r.t_submit = Clock::now();
+    srv->queue.push_back(r);
+    e.queued++;
+    return ICR_OK;
+  });
+}
+
+icr_status icr_server_poll(icr_server *srv, icr_completion *out, int32_t cap, int32_t *n_out, int32_t wait,
+                           int32_t *pending_out) {
+  return guarded_srv(srv, [&] {
+    if (!n_out || (cap > 0 && !out) || cap < 0) throw ServerError(ICR_E_ARG, "bad output arguments");
+    int n = 0;
+    while (true) {
+      launch_ready(srv);
+      bool any_running = false;
+      for (auto &sl : srv->slots) {
+        if (!sl.running) continue;
+        if (n >= cap) {
+          any_running = true;
+          continue;
+        }
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) {
+          any_running = true;
+          continue;
+        }
+        hip_check(q, "hipEventQuery");
+        const auto now = Clock::now();
+        icr_completion &c = out[n++];
+        c.tag = sl.req.tag;
+        c.scene = sl.req.scene;
+        c.status = ICR_OK;
+        c.latency_ms = ms_since(sl.req.t_submit, now);
+        c.queue_ms = ms_since(sl.req.t_submit, sl.req.t_launch);
+        srv->scenes[sl.req.scene].busy = false;
+        sl.running = false;
+      }
+      if (n > 0) launch_ready(srv);   // freed slots take the next requests at once
+      if (n > 0 || !wait || n >= cap || (!any_running && srv->queue.empty())) break;
+      // block on the slot that was launched first
+      Slot *first = nullptr;
+      for (auto &sl : srv->slots)
+        if (sl.running && (!first || sl.req.t_launch < first->req.t_launch)) first = &sl;
+      if (first) hip_check(hipEventSynchronize(first->done), "hipEventSynchronize");
+    }
+    *n_out = n;
+    if (pending_out) {
+      int p = (int)srv->queue.size();
+      for (auto &sl : srv->slots) p += sl.running ? 1 : 0;
+      *pending_out = p;
+    }
+    return ICR_OK;
+  });
+}
+
+}  // extern "C"

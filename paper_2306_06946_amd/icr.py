@@ -51,6 +51,11 @@ class FactorInfo(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("scene", C.c_int32), ("status", C.c_int32), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double)]
+
+
 _P = C.c_void_p
 _I = C.c_int32
 _D = C.c_double
@@ -74,6 +79,14 @@ _SIGS = {
     "icr_set_state": (C.c_int, [_P, _P, _P, _D]),
     "icr_get_step_results": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "icr_analyze": (C.c_int, [_P, _I, _P, _I, _P, _P, _I, _P, _P, _I, C.POINTER(_I), C.POINTER(_I)]),
+    "icr_server_create": (C.c_int, [C.POINTER(_P), C.c_int64, _I]),
+    "icr_server_destroy": (None, [_P]),
+    "icr_server_last_error": (C.c_char_p, [_P]),
+    "icr_server_admit": (C.c_int, [_P, _P, C.POINTER(_I)]),
+    "icr_server_evict": (C.c_int, [_P, _I]),
+    "icr_server_used": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "icr_server_submit": (C.c_int, [_P, _I, C.POINTER(Obstacle), C.POINTER(StepOpts), C.c_uint64]),
+    "icr_server_poll": (C.c_int, [_P, C.POINTER(Completion), _I, C.POINTER(_I), _I, C.POINTER(_I)]),
 }
 
 _lib = None
@@ -229,13 +242,7 @@ class Scene:
 
     def step(self, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, timing=False,
              report=True, standard=False, graph=True):
-        ob = Obstacle()
-        ob.kind = 1 if obstacle["kind"] == "sphere" else 0
-        for i in range(3):
-            ob.c0[i] = float(obstacle["c0"][i])
-            ob.vel[i] = float(obstacle["vel"][i])
-            ob.normal[i] = float(obstacle["normal"][i])
-        ob.radius = float(obstacle.get("radius", 0.0))
+        ob = _obstacle(obstacle)
         op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, 1 if standard else 0,
                       1 if graph else 0)
         rep = StepReport()
@@ -275,6 +282,75 @@ class Scene:
         if with_WH:
             out["WH"] = WH
         return out
+
+
+def _obstacle(obstacle):
+    ob = Obstacle()
+    ob.kind = 1 if obstacle["kind"] == "sphere" else 0
+    for i in range(3):
+        ob.c0[i] = float(obstacle["c0"][i])
+        ob.vel[i] = float(obstacle["vel"][i])
+        ob.normal[i] = float(obstacle["normal"][i])
+    ob.radius = float(obstacle.get("radius", 0.0))
+    return ob
+
+
+class Server:
+    """Serving runtime over many admitted scenes (wraps an icr_server handle)."""
+
+    def __init__(self, hbm_budget, slots=4):
+        self.L = lib()
+        h = C.c_void_p()
+        st = self.L.icr_server_create(C.byref(h), int(hbm_budget), int(slots))
+        if st != OK:
+            raise IcrError(st, "icr_server_create failed")
+        self._h = h
+        self._scenes = {}
+
+    def _check(self, st):
+        if st != OK:
+            raise IcrError(st, self.L.icr_server_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L.icr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, scene):
+        sid = C.c_int32(0)
+        self._check(self.L.icr_server_admit(self._h, scene._h, C.byref(sid)))
+        self._scenes[sid.value] = scene
+        return sid.value
+
+    def evict(self, sid):
+        self._check(self.L.icr_server_evict(self._h, int(sid)))
+        self._scenes.pop(sid, None)
+
+    def used(self):
+        b = C.c_int64(0)
+        self._check(self.L.icr_server_used(self._h, C.byref(b)))
+        return b.value
+
+    def submit(self, sid, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, tag=0,
+               graph=True):
+        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 0, 0, 1 if graph else 0)
+        self._check(self.L.icr_server_submit(self._h, int(sid), C.byref(_obstacle(obstacle)), C.byref(op),
+                                             C.c_uint64(tag)))
+
+    def poll(self, wait=False, cap=256):
+        """Launch what fits, return (completions, pending) with completions as dicts."""
+        out = (Completion * cap)()
+        n, pend = C.c_int32(0), C.c_int32(0)
+        self._check(self.L.icr_server_poll(self._h, out, cap, C.byref(n), 1 if wait else 0, C.byref(pend)))
+        res = [dict(tag=out[i].tag, scene=out[i].scene, status=out[i].status, latency_ms=out[i].latency_ms,
+                    queue_ms=out[i].queue_ms) for i in range(n.value)]
+        return res, pend.value
 
 
 def scene_from_dict(sc, stream=None):

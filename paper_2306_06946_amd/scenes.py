@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-CONFIGS = ("tiny", "medium", "precision")
+CONFIGS = ("tiny", "medium", "precision", "serving")
 
 
 def box_grid(nx: int, ny: int, nz: int, s: float, jitter: float, rng: np.random.Generator):
@@ -128,6 +128,34 @@ def make_scene(config: str, seed: int = 0) -> dict:
             mu = np.full(len(cand), 0.4)
             sc.update(n_contacts=1000, n_steps=20)
         sc.update(gravity=np.array([0.0, 0.0, -9.81]))
+    elif config == "serving":
+        # one scene of the serving mix: node count log-uniform in [500, 8000],
+        # 10-500 contacts, a tilted plane or a sphere rising into the bottom
+        # face, mu ~ U[0.1, 0.6] per candidate node
+        target = math.exp(rng.uniform(math.log(500.0), math.log(8000.0)))
+        nxy = max(4, int(round(target ** (1.0 / 3.0) * rng.uniform(0.85, 1.15))))
+        nz = max(4, int(round(target / (nxy * nxy))))
+        nx, ny = nxy, nxy
+        nodes, tets, ijk = box_grid(nx, ny, nz, s, 0.2, rng)
+        E = np.full(len(tets), 5.0e3)
+        dims = np.array([nx, ny, nz])
+        fixed = (ijk[:, 2] == nz - 1)
+        surface = np.any((ijk == 0) | (ijk == dims[None, :] - 1), axis=1)
+        cand = np.nonzero(surface & ~fixed)[0]
+        width = (nx - 1) * s
+        if rng.uniform() < 0.5:
+            theta = math.radians(rng.uniform(0.0, 15.0))
+            c0 = np.array([(nx - 1) * s / 2, (ny - 1) * s / 2, -0.1 * s])
+            obs = dict(kind="plane", normal=np.array([0.0, math.sin(theta), math.cos(theta)]), c0=c0,
+                       vel=np.array([0.0, 0.0, 0.05]), radius=0.0)
+        else:
+            R = 0.6 * width
+            off = rng.uniform(-0.1, 0.1, size=2) * width
+            c0 = np.array([(nx - 1) * s / 2 + off[0], (ny - 1) * s / 2 + off[1], -R + 0.1 * s])
+            obs = dict(kind="sphere", normal=np.zeros(3), c0=c0, vel=np.array([0.0, 0.0, 0.05]), radius=R)
+        mu = rng.uniform(0.1, 0.6, size=len(cand))
+        n_c = int(min(len(cand), rng.integers(10, 501)))
+        sc.update(gravity=np.array([0.0, 0.0, -9.81]), n_contacts=n_c, n_steps=20)
     else:
         raise ValueError(f"unknown config {config!r}")
 

@@ -120,7 +120,7 @@ def test_update_W_matches_oracle(nc, tiny):
     assert np.array_equal(got, got.T)
 
 
-@pytest.mark.parametrize("nc,mu_zero", [(1, False), (12, True), (12, False), (150, False), (700, False)])
+@pytest.mark.parametrize("nc,mu_zero", [(1, False), (12, True), (12, False), (150, False), (300, False), (700, False)])
 def test_solve_contacts_matches_oracle(nc, mu_zero, tiny):
     _, s = tiny
     rng = np.random.default_rng(200 + nc)

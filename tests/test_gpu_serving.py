@@ -1,0 +1,142 @@
+"""Serving runtime (icr_server_*): many scenes stepped concurrently.
+
+- a request served in the mix gives bit-for-bit the result of the same step
+  run alone (the server only chooses the stream and the moment);
+- steps of one scene complete in submission order;
+- admission against the device-memory budget, eviction;
+- scenes of the serving mix (plane or sphere, 10-500 contacts) against the
+  FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle.icr_oracle as O
+from paper_2306_06946_amd.scenes import make_scene
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SEEDS = (2, 3, 6)   # 1053, 640 and 2160 nodes; plane, sphere, sphere
+
+
+def _icr():
+    from paper_2306_06946_amd import icr
+    return icr
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _run_alone(sc, steps):
+    s = _icr().scene_from_dict(sc)
+    for _ in range(steps):
+        s.step(sc["obstacle"], sc["n_contacts"], sc["n_newton"], 30, 0.0, sc["j_inner"], report=False)
+    q, v, t = s.get_state()
+    lam = s.step_results(sc["n_contacts"])["lam"]
+    torch.cuda.synchronize()
+    return q.cpu(), v.cpu(), lam.cpu(), t
+
+
+def test_mixed_equals_alone():
+    icr = _icr()
+    scs = [make_scene("serving", sd) for sd in SEEDS]
+    steps = 3
+    alone = []
+    for sc in scs:
+        _say(f"[gpu] serving alone seed={sc['seed']} nodes={len(sc['nodes'])} nc={sc['n_contacts']}")
+        alone.append(_run_alone(sc, steps))
+    _say("[gpu] serving mixed")
+    srv = icr.Server(hbm_budget=64 << 30, slots=4)
+    scenes = [icr.scene_from_dict(sc) for sc in scs]
+    ids = [srv.admit(s) for s in scenes]
+    tag = 0
+    for k in range(steps):
+        for sid, sc in zip(ids, scs):
+            srv.submit(sid, sc["obstacle"], sc["n_contacts"], sc["n_newton"], 30, 0.0, sc["j_inner"], tag=tag)
+            tag += 1
+    done = []
+    while len(done) < tag:
+        out, pending = srv.poll(wait=True)
+        done += out
+        assert all(c["status"] == icr.OK for c in out)
+        if not out:
+            assert pending > 0
+    torch.cuda.synchronize()
+    for s, sc, ref in zip(scenes, scs, alone):
+        s.set_stream(torch.cuda.current_stream().cuda_stream)
+        q, v, t = s.get_state()
+        lam = s.step_results(sc["n_contacts"])["lam"]
+        torch.cuda.synchronize()
+        assert torch.equal(q.cpu(), ref[0]) and torch.equal(v.cpu(), ref[1]) and torch.equal(lam.cpu(), ref[2])
+        assert t == ref[3]
+    srv.close()
+
+
+def test_steps_of_one_scene_complete_in_order():
+    icr = _icr()
+    sc = make_scene("serving", SEEDS[1])
+    srv = icr.Server(hbm_budget=64 << 30, slots=4)
+    s = icr.scene_from_dict(sc)
+    sid = srv.admit(s)
+    for tag in range(4):
+        srv.submit(sid, sc["obstacle"], sc["n_contacts"], sc["n_newton"], 30, 0.0, sc["j_inner"], tag=tag)
+    order = []
+    while len(order) < 4:
+        out, _ = srv.poll(wait=True)
+        order += [c["tag"] for c in out]
+    assert order == [0, 1, 2, 3]
+    torch.cuda.synchronize()
+    s.set_stream(torch.cuda.current_stream().cuda_stream)
+    _, _, t = s.get_state()
+    assert abs(t - 4 * sc["h"]) < 1e-15
+    srv.close()
+
+
+def test_admission_budget_and_eviction():
+    icr = _icr()
+    a = icr.scene_from_dict(make_scene("serving", SEEDS[0]))
+    b = icr.scene_from_dict(make_scene("serving", SEEDS[1]))
+    ba = a.factor_info()["device_bytes"]
+    srv = icr.Server(hbm_budget=ba + 1, slots=2)
+    ia = srv.admit(a)
+    assert srv.used() == ba
+    with pytest.raises(icr.IcrError) as e:
+        srv.admit(b)
+    assert e.value.code == icr.E_OOM
+    assert srv.used() == ba
+    srv.evict(ia)
+    assert srv.used() == 0
+    srv.admit(b)
+    assert srv.used() == b.factor_info()["device_bytes"]
+    srv.close()
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_serving_scene_matches_oracle(seed):
+    """Scenes of the serving mix (plane at seed 2, sphere at seed 3) step like the oracle."""
+    sc = make_scene("serving", seed)
+    s = _icr().scene_from_dict(sc)
+    sim = O.Simulation(sc)
+    nc = sc["n_contacts"]
+    for k in range(2):
+        _say(f"[gpu] serving scene seed={seed} step {k}")
+        rep = s.step(sc["obstacle"], nc, sc["n_newton"], 40, 1e-10, sc["j_inner"])
+        rec = []
+        out = sim.step(record=rec, max_sweeps=40, tol=1e-10)
+        res = s.step_results(nc)
+        q, v, _ = s.get_state()
+        assert np.array_equal(res["node_ids"].cpu().numpy(), out["nodes_c"])
+        assert rep["sweeps"] == [r["sweeps"] for r in rec]
+        assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+        assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+        assert _rel(q.cpu().numpy() - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+        assert _rel(v.cpu().numpy(), out["v"]) <= 1e-10
