@@ -1139,14 +1139,15 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       __syncthreads();
       built = false;
     }
-    // ---- sweep over S from its start state
-    for (int r = tid; r < ldS; r += PGS_NT) L.lamS0[r] = L.lamS[r];
+    // ---- sweep over S from its start state (forces into the records)
+    for (int r = tid; r < ldS; r += PGS_NT) {
+      L.lamS0[r] = L.lamS[r];
+      L.rec[PGS_RW * (r / 3) + 19 + r % 3] = L.lamS[r];
+    }
     if (tid == 0) {
       L.flag = 0;
       L.nu = 0;
     }
-    __syncthreads();
-    for (int r = tid; r < ldS; r += PGS_NT) L.rec[PGS_RW * (r / 3) + 19 + r % 3] = L.lamS[r];
     __syncthreads();
     if (nS > 0) {
       if (nS <= 128) {
@@ -1161,17 +1162,16 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       }
     }
     __syncthreads();
-    // forces back from the records
-    for (int r = tid; r < ldS; r += PGS_NT) L.lamS[r] = L.rec[PGS_RW * (r / 3) + 19 + r % 3];
-    __syncthreads();
     // ---- one pass over S: sum of squared changes of the sweep, |lambda|^2,
     // and the bound factor of the skipped contacts' gaps
     // B = sum_q sqrt(W~_qq) max(|lamS - lamSet|, |lamS0 - lamSet|)
+    // (the forces come back from the records in the same pass)
     double dpart = 0.0, bpart = 0.0, npart = 0.0;
     for (int r = tid; r < ldS; r += PGS_NT) {
       const double *rc = L.rec + PGS_RW * (r / 3);
       const double wqq = (r % 3 == 0) ? rc[0] : ((r % 3 == 1) ? rc[3] : rc[5]);
-      const double ls = L.lamS[r], l0 = L.lamS0[r], lset = L.lamSet[r];
+      const double ls = rc[19 + r % 3], l0 = L.lamS0[r], lset = L.lamSet[r];
+      L.lamS[r] = ls;
       const double dv = ls - l0;
       dpart += dv * dv;
       bpart += sqrt(wqq) * fmax(fabs(ls - lset), fabs(l0 - lset));
@@ -1194,23 +1194,23 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         const double g = gnSet[c], rb = swn[c] * B;
         if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
       }
-    }
-    __syncthreads();
-    const int nu = L.nu;
-    for (int u = wv; u < nu; u += PGS_NW) {   // exact gap at the turn of the unsettled contacts
-      const int c = L.ulist[u];
-      double a = 0.0;
-      for (int q = ln; q < ldS; q += 64) {
-        const double lt = (L.Sidx[q / 3] < c) ? L.lamS[q] : L.lamS0[q];
-        a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
+      __syncthreads();
+      const int nu = L.nu;
+      for (int u = wv; u < nu; u += PGS_NW) {   // exact gap at the turn of the unsettled contacts
+        const int c = L.ulist[u];
+        double a = 0.0;
+        for (int q = ln; q < ldS; q += 64) {
+          const double lt = (L.Sidx[q / 3] < c) ? L.lamS[q] : L.lamS0[q];
+          a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
+        }
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (ln == 0 && gnSet[c] + a < 0.0) {
+          L.inS[c] = 1;
+          L.flag = 1;
+        }
       }
-      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      if (ln == 0 && gnSet[c] + a < 0.0) {
-        L.inS[c] = 1;
-        L.flag = 1;
-      }
+      __syncthreads();
     }
-    __syncthreads();
     if (L.flag) {
       // a skipped contact was not a no-op: restart the sweep with a larger S
       for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS0[r];

@@ -9,6 +9,7 @@
 #include <deque>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "icr.h"
@@ -240,11 +241,9 @@ icr_status icr_server_poll(icr_server *srv, icr_completion *out, int32_t cap, in
       }
       if (n > 0) launch_ready(srv);   // freed slots take the next requests at once
       if (n > 0 || !wait || n >= cap || (!any_running && srv->queue.empty())) break;
-      // block on the slot that was launched first
-      Slot *first = nullptr;
-      for (auto &sl : srv->slots)
-        if (sl.running && (!first || sl.req.t_launch < first->req.t_launch)) first = &sl;
-      if (first) hip_check(hipEventSynchronize(first->done), "hipEventSynchronize");
+      // wait for whichever slot finishes first (not the oldest: a long step
+      // must not hold the other slots idle)
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     *n_out = n;
     if (pending_out) {
