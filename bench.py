@@ -78,9 +78,10 @@ def profiled_traffic(kernel):
     return None
 
 
-def serving_leg(n_scenes, rate, sweeps, seconds=2.0):
-    """Serving mix through icr_server: closed-loop saturation with 1 and 4
-    slots, then Poisson arrivals at `rate` steps/s over `seconds`."""
+def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
+    """Serving mix through icr_server: closed-loop saturation with 1, 4 and
+    `slots` slots, then Poisson arrivals at `rate` steps/s over `seconds` on
+    `slots` slots."""
     import torch
     from paper_2306_06946_amd import icr
     from paper_2306_06946_amd.scenes import make_scene
@@ -132,11 +133,13 @@ def serving_leg(n_scenes, rate, sweeps, seconds=2.0):
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     admitted_bytes=int(used))
 
-    out["closed_loop_1_slot"] = closed_loop(1, seconds)
-    out["closed_loop_4_slots"] = closed_loop(4, seconds)
-    cap = out["closed_loop_4_slots"]["steps_per_s"]
-    log(f"[bench] serving closed loop: 1 slot {out['closed_loop_1_slot']['steps_per_s']:.0f} steps/s, "
-        f"4 slots {cap:.0f} steps/s")
+    out["hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES")
+    for k in sorted({1, 4, slots}):
+        out[f"closed_loop_{k}_slot" + ("s" if k > 1 else "")] = closed_loop(k, seconds)
+    cap = out[f"closed_loop_{slots}_slot" + ("s" if slots > 1 else "")]["steps_per_s"]
+    log("[bench] serving closed loop: " + ", ".join(
+        f"{v['slots']} slots {v['steps_per_s']:.0f} steps/s" for k, v in out.items() if k.startswith("closed_loop"))
+        + f" (hardware queues {out['hw_queues']})")
     if rate <= 0:
         rate = 0.7 * cap   # an offered load the slots can carry
     # open loop: Poisson arrivals, random scene per arrival
@@ -144,7 +147,7 @@ def serving_leg(n_scenes, rate, sweeps, seconds=2.0):
     n_req = int(rate * seconds)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     which = rng.integers(0, n_scenes, size=n_req)
-    srv = icr.Server(hbm_budget=200 << 30, slots=4)
+    srv = icr.Server(hbm_budget=200 << 30, slots=slots)
     ids = [srv.admit(s) for s in scenes]
     lat = []
     k = 0
@@ -164,7 +167,7 @@ def serving_leg(n_scenes, rate, sweeps, seconds=2.0):
         s.set_stream(torch.cuda.current_stream().cuda_stream)
     lat = np.array(lat)
     out["poisson"] = dict(rate_steps_per_s=rate, requests=n_req, elapsed_s=el, achieved_steps_per_s=n_req / el,
-                          p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), slots=4)
+                          p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)), slots=slots)
     log(f"[bench] serving poisson {rate:.0f}/s: achieved {n_req / el:.0f}/s p50 {out['poisson']['p50_ms']:.2f} ms "
         f"p99 {out['poisson']['p99_ms']:.2f} ms")
     for s in scenes:
@@ -234,7 +237,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200,
                     help="timed steps: repeats of the --trajectory-step trajectory from the initial state")
-    ap.add_argument("--trajectory", type=int, default=20, help="steps per trajectory (the workload's 20 steps)")
+    ap.add_argument("--trajectory", type=int, default=0,
+                    help="steps per trajectory; 0 = the configuration's own count (20 for precision)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="precision")
     ap.add_argument("--seed", type=int, default=0)
@@ -249,7 +253,9 @@ def main():
                     help="also run the serving mix: this many independent scenes (node count 500-8000, 10-500 "
                          "contacts) stepped through icr_server; 0 = skip")
     ap.add_argument("--serving-rate", type=float, default=0.0,
-                    help="Poisson arrival rate (steps/s, all scenes); 0 = 70%% of the measured 4-slot capacity")
+                    help="Poisson arrival rate (steps/s, all scenes); 0 = 70%% of the measured capacity")
+    ap.add_argument("--serving-slots", type=int, default=16,
+                    help="server slots (streams) of the serving mix; HIP gets as many hardware queues (1..32)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (5 launches) and exit: the "
                          "calibration kernel for HBM byte counters")
@@ -262,6 +268,12 @@ def main():
                                    "design, not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.serving > 0:
+        if not 1 <= args.serving_slots <= 32:
+            ap.error("--serving-slots must be in 1..32")
+        # streams beyond the process's hardware queues share a queue and run
+        # one after another; must be set before HIP starts
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, args.serving_slots))
     import torch
     from paper_2306_06946_amd import icr
     from paper_2306_06946_amd.scenes import make_scene
@@ -290,7 +302,7 @@ def main():
     torch.cuda.synchronize()
     reps = []
     wall = []
-    traj = max(1, min(args.trajectory, args.steps))
+    traj = max(1, min(args.trajectory or sc["n_steps"], args.steps))
     t0 = time.perf_counter()
     for i in range(args.steps):
         if i % traj == 0:
@@ -328,7 +340,9 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = profiled_traffic(roof["kernel"])
     out = {
-        "metric": "time-steps/sec (W_H build + Newton W updates) at 60k DOF; p50/p99 step latency",
+        "metric": ("time-steps/sec (W_H build + Newton W updates) at "
+                   + ("60k" if args.config == "precision" else f"{3 * len(sc['nodes']) / 1000:.1f}k")
+                   + " DOF; p50/p99 step latency"),
         "value": steps_per_s,
         "unit": "time-steps/s",
         "n_gpus": 1,
@@ -385,7 +399,7 @@ def main():
         }
         s2.close()
     if args.serving > 0:
-        out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps)
+        out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)...")
         out["cpu_baseline"] = cpu_baseline(sc, args.sweeps, args.cpu_cols)

@@ -131,11 +131,13 @@ icr_status icr_update_W(icr_scene *s, int32_t n_c, const double *WH, const doubl
  * tangential gap) by j_inner passes of a shifted fixed point.  After every
  * sweep eps = |lam_i - lam_{i-1}|_2 / |lam_i|_2; stop when eps <= tol or after
  * max_sweeps sweeps.
- *   W [m*m], d [m], mu [n_c] device; lambda [m] device in/out (warm start);
+ *   W [m*m] device, exactly symmetric (as icr_update_W writes it: rows are
+ *   read in place of columns); d [m], mu [n_c] device; lambda [m] device
+ *   in/out (warm start);
  *   status [n_c] device int8 (branch of the last sweep)
  *   sweeps_out, eps_out: host, may be NULL (then the call does not synchronise)
  * Returns ICR_WARN_NOT_CONVERGED (when eps_out/sweeps_out are given and
- * eps > tol).  ICR_E_ARG on n_c < 1, max_sweeps < 1, j_inner < 0, h <= 0.
+ * eps > tol).  ICR_E_ARG on n_c < 1 or n_c > 4096, max_sweeps < 1, j_inner < 0, h <= 0.
  */
 icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const double *d, const double *mu,
                               double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
@@ -144,7 +146,9 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
 /*
  * Proximity update p = p_free + h^2 W_H f (Eq. 31 with the total force
  * f = C_k^T lambda_k in world frame, one 3-vector per contact).
- *   WH [m*m], p_free [m], f [m] device; p [m] device output.
+ *   WH [m*m] device, exactly symmetric (as icr_build_WH writes it: rows are
+ *   read in place of columns, and only those of contacts with a non-zero
+ *   force); p_free [m], f [m] device; p [m] device output.
  */
 icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, const double *p_free,
                                 const double *f, double h, double *p);
@@ -261,8 +265,11 @@ typedef struct {
   double queue_ms;     /* submission -> launch */
 } icr_completion;
 
-/* slots in [1, 16] (the GPU runs up to its hardware queue count of streams
- * at once); hbm_budget in bytes (> 0). */
+/* slots in [1, 32]; hbm_budget in bytes (> 0).  HIP spreads streams over the
+ * process's hardware queues (GPU_MAX_HW_QUEUES, 4 unless set): slots beyond
+ * that count share a queue and their steps run one after another, so a
+ * server with more than 4 slots wants the variable set to at least `slots`
+ * before the process's first HIP call. */
 icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots);
 void icr_server_destroy(icr_server *srv); /* waits for the requests in flight */
 const char *icr_server_last_error(const icr_server *srv);

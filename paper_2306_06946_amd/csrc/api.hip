@@ -460,7 +460,7 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
                               double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
                               int32_t j_inner, int32_t *sweeps_out, double *eps_out) {
   return guarded(s, [&] {
-    REQUIRE(n_c >= 1 && n_c <= kPgsMaxContacts, "n_c must be in [1, 2560]");
+    REQUIRE(n_c >= 1 && n_c <= kPgsMaxContacts, "n_c must be in [1, 4096]");
     REQUIRE(max_sweeps >= 1, "max_sweeps must be >= 1");
     REQUIRE(j_inner >= 0, "j_inner must be >= 0");
     REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
@@ -593,7 +593,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     REQUIRE(opt, "NULL options");
     const int nc = opt->n_contacts;
     REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
-    REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (2560)");
+    REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
     REQUIRE(opt->n_newton >= 1 && opt->n_newton <= 64, "n_newton must be in [1, 64]");
     REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
     REQUIRE(opt->scheme == 0 || opt->scheme == 1, "scheme must be 0 (fast) or 1 (standard)");

@@ -480,16 +480,70 @@ __device__ double block_min(double v, double *red) {
 }
 
 // g0 = d + h^2 W lambda0, one wave per row (the PGS start state).
-__global__ __launch_bounds__(256) void k_pgs_init(int m, const double *__restrict__ W, const double *__restrict__ d,
-                                                  const double *__restrict__ lam, double h2, double *__restrict__ g) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ln = threadIdx.x & 63;
-  if (row >= m) return;
-  const double *Wr = W + (long)row * m;
+// y = x0 + h2 M v for a symmetric m x m row-major M (m = 3 nc) and a vector v
+// that is non-zero on few contacts (3-blocks of v): by symmetry
+// (M v)_i = sum over contacts k with a non-zero block of M[3k+a][i] v[3k+a],
+// so only those rows of M are read, each contiguous in the output index i.
+// A skipped term is an exact zero, so only the summation order differs from
+// the dense product.  Every block compacts the non-zero contacts (ascending,
+// SG_CHUNK at a time) into LDS, then its waves split that list over the same
+// 64 outputs and add their partial sums in a fixed order.
+constexpr int SG_NT = 512;
+constexpr int SG_NW = SG_NT / 64;
+constexpr int SG_CHUNK = 4096;
+__device__ inline bool block_nonzero(const double *__restrict__ v, long c) {
+  return (v[3 * c] != 0.0) | (v[3 * c + 1] != 0.0) | (v[3 * c + 2] != 0.0);
+}
+__global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double *__restrict__ M,
+                                                           const double *__restrict__ x0,
+                                                           const double *__restrict__ v, double h2,
+                                                           double *__restrict__ y) {
+  __shared__ int list[SG_CHUNK];
+  __shared__ int wsum[SG_NW];
+  __shared__ double part[SG_NW][64];
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const long m = 3L * nc;
+  const long i = (long)blockIdx.x * 64 + ln;
   double s = 0.0;
-  for (int j = ln; j < m; j += 64) s = fma(Wr[j], lam[j], s);
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (ln == 0) g[row] = d[row] + h2 * s;
+  for (int c0 = 0; c0 < nc; c0 += SG_CHUNK) {
+    const int cn = min(SG_CHUNK, nc - c0);
+    const int per = (cn + SG_NT - 1) / SG_NT;   // contiguous contacts per thread
+    const int lo = c0 + min(cn, tid * per), hi = c0 + min(cn, (tid + 1) * per);
+    int cnt = 0;
+    for (int c = lo; c < hi; ++c) cnt += block_nonzero(v, c) ? 1 : 0;
+    int incl = cnt;   // inclusive scan over the wave, then over the waves
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (ln >= o) incl += t;
+    }
+    if (ln == 63) wsum[wv] = incl;
+    __syncthreads();
+    int pos = incl - cnt, total = 0;
+    for (int w = 0; w < SG_NW; ++w) {
+      pos += (w < wv) ? wsum[w] : 0;
+      total += wsum[w];
+    }
+    for (int c = lo; c < hi; ++c)
+      if (block_nonzero(v, c)) list[pos++] = c;
+    __syncthreads();
+    if (i < m) {
+#pragma unroll 4
+      for (int q = wv; q < total; q += SG_NW) {
+        const long r = 3L * list[q];
+        s = fma(M[r * m + i], v[r], s);
+        s = fma(M[(r + 1) * m + i], v[r + 1], s);
+        s = fma(M[(r + 2) * m + i], v[r + 2], s);
+      }
+    }
+    __syncthreads();   // list and wsum are rewritten by the next chunk
+  }
+  part[wv][ln] = s;
+  __syncthreads();
+  if (wv == 0 && i < m) {
+    double t = 0.0;
+    for (int w = 0; w < SG_NW; ++w) t += part[w][ln];
+    y[i] = x0[i] + h2 * t;
+  }
 }
 
 // Single-workgroup PGS.  g = d + W~ lambda (all contacts, own term included)
@@ -499,7 +553,9 @@ __global__ __launch_bounds__(256) void k_pgs_init(int m, const double *__restric
 // no-op of Gauss-Seidel (it stays separated and changes nothing), so wave 0
 // scans 64 contacts at a time with a ballot and jumps to the first contact
 // that can change; the iterates are those of the sequential sweep.
-constexpr int PGS_MAX_NC = 2560;
+constexpr int PGS_MAX_NC = 4096;
+// dynamic LDS of k_pgs_single: g[3 nc] doubles, then nz[nc] bytes
+__host__ __device__ inline size_t pgs_single_lds(int nc) { return (size_t)nc * (3 * sizeof(double) + 1); }
 __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__restrict__ W,
                                                      const double *__restrict__ d, const double *__restrict__ g0,
                                                      const double *__restrict__ mu, double h2,
@@ -507,8 +563,9 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
                                                      int max_sweeps, double tol, int j_inner,
                                                      int *__restrict__ sweeps_out, double *__restrict__ eps_out,
                                                      const int *__restrict__ ctl) {
-  __shared__ double g[3 * PGS_MAX_NC];
-  __shared__ unsigned char nz[PGS_MAX_NC];
+  extern __shared__ double lds_g[];
+  double *g = lds_g;
+  unsigned char *nz = reinterpret_cast<unsigned char *>(lds_g + 3 * nc);
   __shared__ double bc[3];
   __shared__ double red[16];
   __shared__ int ctl_s;
@@ -656,6 +713,9 @@ struct PgsLds {
   double Rmin;   // settle threshold of the set: B below it settles every skipped contact
   int nS, flag, stop, nu, zflag, settled;
 };
+
+static_assert(sizeof(PgsLds) <= 160 * 1024, "active-set PGS state must fit one CU's LDS");
+static_assert(3 * PGS_MAX_NC * sizeof(double) + PGS_MAX_NC + 512 <= 160 * 1024, "k_pgs_single LDS");
 
 // Padded contact count of the blocked layout: 64 contacts per register slot,
 // two slots per chain wave beyond 64 contacts.
@@ -1072,7 +1132,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
       }
       // ---- gaps at the set's start state (lambda is zero outside S)
       if (first_build) {
-        // g0 = d + W~ lambda0 was formed by k_pgs_init for every row; the
+        // g0 = d + W~ lambda0 was formed by k_sym_gemv_sparse for every row; the
         // chains keep the gap without the contact's own term
         for (int r = tid; r < ldS; r += PGS_NT) {
           const long cr = 3L * L.Sidx[r / 3];
@@ -1239,20 +1299,6 @@ __global__ void k_world_force(int nc, const double *__restrict__ C, const double
     f[3 * c + a] = R[a] * lam[3 * c] + R[3 + a] * lam[3 * c + 1] + R[6 + a] * lam[3 * c + 2];
 }
 
-// p = p_free + h^2 W_H f, one wave per row.
-__global__ __launch_bounds__(256) void k_proximity(int m, const double *__restrict__ WH,
-                                                   const double *__restrict__ pfree, const double *__restrict__ f,
-                                                   double h2, double *__restrict__ p) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ln = threadIdx.x & 63;
-  if (row >= m) return;
-  const double *Wr = WH + (long)row * m;
-  double s = 0.0;
-  for (int j = ln; j < m; j += 64) s = fma(Wr[j], f[j], s);
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (ln == 0) p[row] = pfree[row] + h2 * s;
-}
-
 __global__ void k_zero(long n, double *__restrict__ x) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = 0.0;
 }
@@ -1323,7 +1369,8 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
                 int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev,
                 const PgsWork &wk) {
   const int m = 3 * nc;
-  k_pgs_init<<<cdiv(m, 4), 256, 0, st>>>(m, W, d, lam, h * h, wk.g);
+  // g0 = d + W~ lambda over the contacts with a warm-start force
+  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g);
   ICR_LAUNCH_CHECK();
   k_pgs_set<<<1, 1024, 0, st>>>(nc, W, wk.g, lam, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn);
   ICR_LAUNCH_CHECK();
@@ -1334,7 +1381,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
                                                 wk.nS, wk.rec, wk.gS);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
-  k_pgs_single<<<1, 1024, 0, st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
+  k_pgs_single<<<1, 1024, pgs_single_lds(nc), st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
                                    eps_dev, wk.ctl);
   ICR_LAUNCH_CHECK();
 }
@@ -1351,6 +1398,8 @@ void pgs_prepare() {
   if (done) return;
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pgs_single_lds(PGS_MAX_NC)));
   done = true;
 }
 
@@ -1362,7 +1411,8 @@ void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *
 void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
                       double *p) {
   const int m = 3 * nc;
-  k_proximity<<<cdiv(m, 4), 256, 0, st>>>(m, WH, p_free, f, h * h, p);
+  // p = p_free + h^2 W_H f; f is zero at separated contacts
+  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, f, h * h, p);
   ICR_LAUNCH_CHECK();
 }
 

@@ -121,7 +121,7 @@ extern "C" {
 icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots) {
   if (!out) return ICR_E_ARG;
   *out = nullptr;
-  if (hbm_budget <= 0 || slots < 1 || slots > 16) return ICR_E_ARG;
+  if (hbm_budget <= 0 || slots < 1 || slots > 32) return ICR_E_ARG;
   icr_server *srv = new (std::nothrow) icr_server;
   if (!srv) return ICR_E_OOM;
   srv->budget = hbm_budget;

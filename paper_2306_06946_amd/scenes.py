@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-CONFIGS = ("tiny", "medium", "precision", "serving")
+CONFIGS = ("tiny", "medium", "precision", "serving", "stress")
 
 
 def box_grid(nx: int, ny: int, nz: int, s: float, jitter: float, rng: np.random.Generator):
@@ -156,6 +156,27 @@ def make_scene(config: str, seed: int = 0) -> dict:
         mu = rng.uniform(0.1, 0.6, size=len(cand))
         n_c = int(min(len(cand), rng.integers(10, 501)))
         sc.update(gravity=np.array([0.0, 0.0, -9.81]), n_contacts=n_c, n_steps=20)
+    elif config == "stress":
+        # the stress shape on one body: 30x30x28 jittered grid (75 600 DOF),
+        # E = 1e4, 3000 contacts (m = 9000) among the surface nodes, mu = 0.5,
+        # a sphere pressed into the bottom face and sliding along x at
+        # 0.5 m/s; 5 steps x 8 Newton iterations.  (Two stacked bodies with
+        # barycentric interface points need a two-body mapping H, which this
+        # nodal-contact library does not have.)
+        nx, ny, nz = 30, 30, 28
+        nodes, tets, ijk = box_grid(nx, ny, nz, s, 0.2, rng)
+        E = np.full(len(tets), 1.0e4)
+        dims = np.array([nx, ny, nz])
+        fixed = (ijk[:, 2] == nz - 1)
+        surface = np.any((ijk == 0) | (ijk == dims[None, :] - 1), axis=1)
+        cand = np.nonzero(surface & ~fixed)[0]
+        width = (nx - 1) * s
+        R = 0.6 * width
+        off = rng.uniform(-0.1, 0.1, size=2) * width
+        c0 = np.array([(nx - 1) * s / 2 + off[0], (ny - 1) * s / 2 + off[1], -R + 0.2 * s])
+        obs = dict(kind="sphere", normal=np.zeros(3), c0=c0, vel=np.array([0.5, 0.0, 0.1]), radius=R)
+        mu = np.full(len(cand), 0.5)
+        sc.update(gravity=np.array([0.0, 0.0, -9.81]), n_contacts=3000, n_steps=5, n_newton=8)
     else:
         raise ValueError(f"unknown config {config!r}")
 

@@ -120,7 +120,8 @@ def test_update_W_matches_oracle(nc, tiny):
     assert np.array_equal(got, got.T)
 
 
-@pytest.mark.parametrize("nc,mu_zero", [(1, False), (12, True), (12, False), (150, False), (300, False), (700, False)])
+@pytest.mark.parametrize("nc,mu_zero", [(1, False), (12, True), (12, False), (150, False), (300, False), (700, False),
+                                        (2600, False)])
 def test_solve_contacts_matches_oracle(nc, mu_zero, tiny):
     _, s = tiny
     rng = np.random.default_rng(200 + nc)
@@ -128,7 +129,7 @@ def test_solve_contacts_matches_oracle(nc, mu_zero, tiny):
     if mu_zero:
         mu[:] = 0.0
     h = 0.01
-    sweeps_max = 60 if nc >= 150 else 400
+    sweeps_max = 20 if nc > 1000 else 60 if nc >= 150 else 400
     lam_ref, st_ref, sw_ref, eps_ref = O.pgs(W, d, mu, h, lam0, sweeps_max, 1e-12, 8)
     _say(f"[gpu] solve_contacts nc={nc} mu0={mu_zero}")
     lam = _cuda(lam0)
@@ -152,6 +153,32 @@ def test_proximity_update_matches_formula(tiny):
     torch.cuda.synchronize()
     ref = pf + (h * h) * (WH @ f)
     assert _rel(p.cpu().numpy() - pf, ref - pf) <= 1e-13
+
+
+def test_proximity_update_sparse_force_two_chunks(tiny):
+    """Force non-zero on few contacts (the kernel reads only their rows of the
+    symmetric W_H) and more contacts than one compaction pass holds."""
+    _, s = tiny
+    rng = np.random.default_rng(4)
+    nc = 4200
+    m = 3 * nc
+    G = rng.standard_normal((m, m))
+    WH = G + G.T          # exactly symmetric; the product needs no definiteness
+    del G
+    pf = rng.standard_normal(m)
+    f = rng.standard_normal(m).reshape(nc, 3)
+    f[rng.uniform(size=nc) < 0.7] = 0.0
+    f[4100:4105, 1] = 0.0   # blocks with some zero entries stay non-zero blocks
+    f = f.ravel()
+    h = 0.01
+    p = torch.empty(m, dtype=torch.float64, device="cuda")
+    s.proximity_update(_cuda(WH.ravel()), _cuda(pf), _cuda(f), h, p)
+    torch.cuda.synchronize()
+    ref = (h * h) * (WH @ f)
+    assert _rel(p.cpu().numpy() - pf, ref) <= 1e-13
+    f0 = np.zeros(m)
+    s.proximity_update(_cuda(WH.ravel()), _cuda(pf), _cuda(f0), h, p)
+    assert np.array_equal(p.cpu().numpy(), pf)
 
 
 def _compare_step(sim, s, sc, steps, tag):
@@ -239,24 +266,26 @@ def test_set_state_restarts_the_trajectory(medium):
     assert torch.equal(runs[0][0], qf.cpu()) and torch.equal(runs[0][1], vf.cpu())
 
 
-def test_precision_config_sampled_against_oracle():
-    """61k DOF / 1000 contacts, the benchmark configuration (30 fixed sweeps).
+@pytest.mark.parametrize("cfg", ["precision", "stress"])
+def test_full_size_config_sampled_against_oracle(cfg):
+    """Full-size configurations (30 fixed sweeps): 61k DOF / 1000 contacts, the
+    benchmark configuration, and 75k DOF / 3000 contacts (W_H 9000 x 9000).
 
     Full vectors where the oracle is cheap (q_free, contact selection), sampled
     columns of W_H by the oracle's banded solves, and properties that hold at
     any size for the Newton loop (exact symmetry of W_H, cone feasibility,
     separated contacts carry no force, proximity = p_free + h^2 W_H C^T lambda).
     """
-    sc = make_scene("precision", 0)
+    sc = make_scene(cfg, 0)
     icr = _icr()
-    _say("[gpu] precision: assemble+factor")
+    _say(f"[gpu] {cfg}: assemble+factor")
     s = icr.scene_from_dict(sc)
     nc = sc["n_contacts"]
     m = 3 * nc
-    _say("[gpu] precision: one step (30 sweeps)")
+    _say(f"[gpu] {cfg}: one step (30 sweeps)")
     s.step(sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"])
     res = s.step_results(nc, with_WH=True)
-    _say("[gpu] precision: oracle assembly + banded factor")
+    _say(f"[gpu] {cfg}: oracle assembly + banded factor")
     asm = O.assemble(sc)
     fac = O.CholeskyFactor(asm["A"])
     q0 = sc["nodes"].ravel()
@@ -267,8 +296,8 @@ def test_precision_config_sampled_against_oracle():
     assert np.array_equal(res["node_ids"].cpu().numpy(), nodes)
     WH = res["WH"].cpu().numpy().reshape(m, m)
     assert np.array_equal(WH, WH.T)
-    cols = np.array([0, 1, 2, 449, 1500, 2998, 2999])
-    _say("[gpu] precision: oracle W_H columns")
+    cols = np.array([0, 1, 2, 449, m // 2, m - 2, m - 1])
+    _say(f"[gpu] {cfg}: oracle W_H columns")
     ref = O.build_WH(fac, nodes, asm["n"], columns=cols)
     assert _rel(WH[:, cols], ref) <= 1e-10
     lam = res["lam"].cpu().numpy().reshape(-1, 3)
