@@ -258,8 +258,12 @@ icr_status icr_create(icr_scene **out, void *stream) {
 void icr_destroy(icr_scene *s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  if (s->side) (void)hipStreamSynchronize(s->side);
   s->sg.reset();
   if (s->sg.cap) (void)hipStreamDestroy(s->sg.cap);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
   s->con.arena.release();
   s->fac.rhs_arena.release();
   s->fac_arena.release();

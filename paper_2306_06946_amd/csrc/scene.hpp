@@ -178,6 +178,10 @@ struct icr_scene {
   long epoch = 0;          // bumped whenever device buffers are (re)allocated
   int clock_khz = 0;       // device wall-clock rate used by the phase stamps
   StepGraph sg;
+  // second stream of the multi-RHS solve: the W_H products of a tree level
+  // run there while the main stream goes on with the next level's solve
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace icr {
