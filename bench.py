@@ -247,13 +247,17 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=40)
     ap.add_argument("--standard-steps", type=int, default=20,
                     help="also time this many steps of the standard rebuild scheme (Algorithm 2); 0 = skip")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="launch every step eagerly instead of replaying the captured step graph")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the captured step graph instead of launching every step eagerly (eager is about "
+                         "1%% faster here: the graph replay loses part of the overlap of the W_H products)")
+    ap.add_argument("--no-graph", action="store_true", help="eager launches (the default; kept for old commands)")
     ap.add_argument("--serving", type=int, default=0, metavar="SCENES",
                     help="also run the serving mix: this many independent scenes (node count 500-8000, 10-500 "
                          "contacts) stepped through icr_server; 0 = skip")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="Poisson arrival rate (steps/s, all scenes); 0 = 70%% of the measured capacity")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
+                    help="length of each closed-loop window and of the Poisson run")
     ap.add_argument("--serving-slots", type=int, default=16,
                     help="server slots (streams) of the serving mix; HIP gets as many hardware queues (1..32)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
@@ -290,33 +294,40 @@ def main():
         f"{info['factor_flops']/1e9:.1f} GFLOP in {info['factor_ms']:.1f} ms")
     analysis = icr.analyze(sc["nodes"], sc["tets"])
 
-    def one_step():
-        return s.step(sc["obstacle"], nc, sc["n_newton"], args.sweeps, 0.0, sc["j_inner"], timing=True,
-                      graph=not args.no_graph)
+    def one_step(timing):
+        # timing = True: phase stamps and a report (synchronises the stream)
+        return s.step(sc["obstacle"], nc, sc["n_newton"], args.sweeps, 0.0, sc["j_inner"], timing=timing,
+                      report=timing, graph=args.graph and not args.no_graph)
 
     q0, v0, t_init = s.get_state()
     q0, v0 = q0.clone(), v0.clone()
     for i in range(args.warmup):
-        r = one_step()
+        r = one_step(True)
         log(f"[bench] warmup {i}: {r['ms_total']:.2f} ms")
-    torch.cuda.synchronize()
-    reps = []
-    wall = []
     traj = max(1, min(args.trajectory or sc["n_steps"], args.steps))
+    # timed region: the steps only (no phase stamps, no host synchronisation
+    # between steps); each step's device time from events on the stream
+    tstream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    evs[0].record(tstream)
     for i in range(args.steps):
         if i % traj == 0:
             s.set_state(q0, v0, t_init)   # restart the trajectory (also clears the warm start)
-        ts = time.perf_counter()
-        reps.append(one_step())      # report => stream synchronised at the end of each step
-        wall.append(time.perf_counter() - ts)
+        one_step(False)
+        evs[i + 1].record(tstream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    # phase breakdown: one more trajectory with stamps (outside the timed region)
+    s.set_state(q0, v0, t_init)
+    reps = [one_step(True) for _ in range(traj)]
+    torch.cuda.synchronize()
     res = s.step_results(nc)
     node_ids = res["node_ids"].cpu().numpy()
 
     steps_per_s = args.steps / elapsed
-    lat = np.array(wall) * 1e3
     ph = {k: float(np.mean([r[k] for r in reps])) for k in
           ("ms_total", "ms_free", "ms_contacts", "ms_build_WH", "ms_newton", "ms_update_W", "ms_pgs", "ms_corr",
            "ms_correct")}
@@ -362,6 +373,7 @@ def main():
                                f"{args.sweeps} PGS sweeps, FP64",
                    "dofs": 3 * len(sc["nodes"]), "contacts": nc, "newton": n_newton, "pgs_sweeps": args.sweeps,
                    "parallelism": "single GPU"},
+        "launch": "graph replay" if (args.graph and not args.no_graph) else "eager",
         "metric_scope_steps_per_s": 1e3 / metric_ms,
         "phases_ms": ph,
         "build_WH_gflop": wh_flops / 1e9,
@@ -399,7 +411,8 @@ def main():
         }
         s2.close()
     if args.serving > 0:
-        out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots)
+        out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots,
+                                     seconds=args.serving_seconds)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)...")
         out["cpu_baseline"] = cpu_baseline(sc, args.sweeps, args.cpu_cols)

@@ -62,6 +62,15 @@ const char *icr_last_error(const icr_scene *s);
 /* Rebind the scene to another stream (e.g. torch's current stream). */
 icr_status icr_set_stream(icr_scene *s, void *stream);
 
+/* enable = 1 (default): the multi-RHS solve of icr_build_WH / icr_step runs
+ * the W_H products of each elimination-tree level on a second stream of the
+ * scene, overlapping the next level's solve (joined before the call's later
+ * work).  enable = 0: everything on the scene's stream -- what many scenes
+ * stepped concurrently want, since every extra stream takes a place among
+ * the process's few hardware queues.  Same results either way.
+ * ICR_E_ARG unless enable is 0 or 1. */
+icr_status icr_set_overlap(icr_scene *s, int32_t enable);
+
 /*
  * Assemble the linear-elastic FE model (Sec. "Implicit time integration",
  * Eq. 4-5): per tetrahedron K_e = V B^T D B (isotropic D from E, nu), lumped
@@ -279,7 +288,8 @@ const char *icr_server_last_error(const icr_server *srv);
  * before its steps run on the slot streams).  ICR_E_OOM (nothing admitted)
  * when it would exceed the budget.  While admitted, the scene's stream is
  * the slot stream of its last request: set it back (icr_set_stream) before
- * calling the scene directly, after its requests have completed. */
+ * calling the scene directly, after its requests have completed.  Admission
+ * also turns the scene's second stream off (icr_set_overlap(scene, 0)). */
 icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id);
 /* Remove an idle scene (no request queued or in flight: else ICR_E_STATE);
  * its bytes return to the budget.  The scene itself is not destroyed. */

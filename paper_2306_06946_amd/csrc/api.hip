@@ -281,6 +281,17 @@ icr_status icr_set_stream(icr_scene *s, void *stream) {
   });
 }
 
+icr_status icr_set_overlap(icr_scene *s, int32_t enable) {
+  return guarded(s, [&] {
+    REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+    if (s->overlap != (enable == 1)) {
+      s->overlap = enable == 1;
+      s->epoch++;   // a captured step graph holds the other launch pattern
+    }
+    return ICR_OK;
+  });
+}
+
 icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int32_t *tets, int32_t T,
                         const double *E, const double *nu, double rho, double alpha, double beta, double h,
                         const double *gravity, const uint8_t *fixed) {

@@ -541,7 +541,7 @@ void launch_fill(icr_scene *s, double *x, long n, double v) {
 }
 
 void ensure_rhs_capacity(icr_scene *s, int nc) {
-  if (!s->side) {
+  if (s->overlap && !s->side) {
     ICR_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
     ICR_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     ICR_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
@@ -627,11 +627,14 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     // Z of this level is final: its W_H products go to the side stream (they
     // read Z and write Wp only, which nothing on the main stream touches
     // until the join)
-    ICR_HIP(hipEventRecord(s->ev_fork, st));
-    ICR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+    hipStream_t sy = st;
+    if (s->overlap) {
+      ICR_HIP(hipEventRecord(s->ev_fork, st));
+      ICR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+      sy = s->side;
+    }
     const int ct = cdiv(rmax, AccS::T);
-    k_rhs_syrk<AccS><<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, s->side>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m,
-                                                                           F.d_Wp);
+    k_rhs_syrk<AccS><<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, sy>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
     if (L.max_b3 > 0) {
       k_rhs_off<AccS><<<dim3(cdiv(L.max_b3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
@@ -639,8 +642,10 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
       ICR_LAUNCH_CHECK();
     }
   }
-  ICR_HIP(hipEventRecord(s->ev_join, s->side));
-  ICR_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  if (s->overlap) {
+    ICR_HIP(hipEventRecord(s->ev_join, s->side));
+    ICR_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  }
   {
     const int nt = cdiv(m, 64);
     k_wp_mirror<<<nt * (nt + 1) / 2, 256, 0, st>>>((int)m, F.d_Wp);

@@ -180,6 +180,7 @@ struct icr_scene {
   StepGraph sg;
   // second stream of the multi-RHS solve: the W_H products of a tree level
   // run there while the main stream goes on with the next level's solve
+  bool overlap = true;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };

@@ -164,6 +164,10 @@ icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id
       throw ServerError(ICR_E_OOM, "admission refused: " + std::to_string(info.device_bytes) + " bytes with " +
                                        std::to_string(srv->used) + " of " + std::to_string(srv->budget) +
                                        " in use");
+    // one stream per request: the scene's second stream would only contend
+    // with the slots for the hardware queues
+    const icr_status so = icr_set_overlap(scene, 0);
+    if (so != ICR_OK) throw ServerError(so, icr_last_error(scene));
     SceneEntry e;
     e.s = scene;
     e.bytes = info.device_bytes;

@@ -65,6 +65,7 @@ _SIGS = {
     "icr_destroy": (None, [_P]),
     "icr_last_error": (C.c_char_p, [_P]),
     "icr_set_stream": (C.c_int, [_P, _P]),
+    "icr_set_overlap": (C.c_int, [_P, C.c_int32]),
     "icr_assemble": (C.c_int, [_P, _P, _I, _P, _I, _P, _P, _D, _D, _D, _D, _P, _P]),
     "icr_factor": (C.c_int, [_P]),
     "icr_get_factor_info": (C.c_int, [_P, C.POINTER(FactorInfo)]),
@@ -181,6 +182,9 @@ class Scene:
 
     def set_stream(self, stream):
         self._check(self.L.icr_set_stream(self._h, C.c_void_p(stream)))
+
+    def set_overlap(self, enable):
+        self._check(self.L.icr_set_overlap(self._h, 1 if enable else 0))
 
     # -- model ---------------------------------------------------------------
     def assemble(self, scene):

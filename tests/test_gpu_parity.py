@@ -224,6 +224,34 @@ def test_step_medium_matches_oracle():
     _compare_step(sim, s, sc, 2, "medium")
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_overlap_off_equals_on(medium, graph):
+    """The second-stream overlap of the W_H products changes no bit (eager and
+    graph launches), and switching it between steps is honoured."""
+    sc, _ = medium
+    icr = _icr()
+    outs = []
+    for overlap in (True, False, True):
+        s = icr.scene_from_dict(sc)
+        s.set_overlap(overlap)
+        _say(f"[gpu] overlap={overlap} graph={graph}")
+        for _ in range(2):
+            s.step(sc["obstacle"], sc["n_contacts"], sc["n_newton"], 40, 0.0, sc["j_inner"], report=False,
+                   graph=graph)
+        WH = s.step_results(sc["n_contacts"], with_WH=True)["WH"]
+        q, v, _ = s.get_state()
+        outs.append((q.cpu(), v.cpu(), WH.cpu()))
+        s.close()
+    for run in outs[1:]:
+        for a, b in zip(outs[0], run):
+            assert torch.equal(a, b)
+    bad = icr.Scene()
+    with pytest.raises(icr.IcrError) as e:
+        bad._check(bad.L.icr_set_overlap(bad._h, 2))
+    assert e.value.code == icr.E_ARG
+    bad.close()
+
+
 def test_step_is_deterministic(medium):
     sc, _ = medium
     icr = _icr()
