@@ -247,6 +247,9 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=40)
     ap.add_argument("--standard-steps", type=int, default=20,
                     help="also time this many steps of the standard rebuild scheme (Algorithm 2); 0 = skip")
+    ap.add_argument("--per-sweep-steps", type=int, default=0,
+                    help="also time this many steps with the directions updated after every PGS sweep "
+                         "(n_newton x sweeps iterations of one sweep); 0 = skip")
     ap.add_argument("--graph", action="store_true",
                     help="replay the captured step graph instead of launching every step eagerly (eager is about "
                          "1%% faster here: the graph replay loses part of the overlap of the W_H products)")
@@ -410,6 +413,24 @@ def main():
             "metric_scope_speedup": sp["ms_newton"] / (fp["ms_build_WH"] + fp["ms_newton"]),
         }
         s2.close()
+    if args.per_sweep_steps > 0:
+        # variant of the results section: directions (and W) updated after
+        # every PGS sweep, i.e. n_newton x sweeps Newton iterations of one sweep
+        nps = min(args.per_sweep_steps, traj)
+        nk = n_newton * args.sweeps
+        log(f"[bench] directions updated every sweep: {nk} iterations x 1 sweep, {nps} steps...")
+        s.set_state(q0, v0, t_init)
+        pr = [s.step(sc["obstacle"], nc, nk, 1, 0.0, sc["j_inner"], timing=True) for _ in range(nps)]
+        keys = ("ms_total", "ms_build_WH", "ms_newton", "ms_update_W", "ms_pgs", "ms_corr")
+        pp = {k: float(np.mean([r[k] for r in pr])) for k in keys}
+        fp = {k: float(np.mean([r[k] for r in reps[:nps]])) for k in keys}
+        out["per_sweep_directions"] = {
+            "steps": nps, "newton_iterations": nk, "sweeps_per_iteration": 1,
+            "ms_per_step": pp["ms_total"], "metric_scope_ms": pp["ms_build_WH"] + pp["ms_newton"],
+            "ms_update_W": pp["ms_update_W"], "ms_pgs": pp["ms_pgs"], "ms_corr": pp["ms_corr"],
+            "fast_ms_per_step": fp["ms_total"], "fast_metric_scope_ms": fp["ms_build_WH"] + fp["ms_newton"],
+            "status_counts": [pr[-1]["n_separate"], pr[-1]["n_stick"], pr[-1]["n_slip"]],
+        }
     if args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots,
                                      seconds=args.serving_seconds)

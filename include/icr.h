@@ -179,7 +179,9 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
 
 typedef struct {
   int32_t n_contacts;   /* contacts kept per step (closest candidates) */
-  int32_t n_newton;     /* Newton iterations (Algorithm 3) */
+  int32_t n_newton;     /* Newton iterations (Algorithm 3), 1..256.  With max_sweeps = 1 the
+                           directions are updated after every PGS sweep (the per-sweep update
+                           the results section proposes) */
   int32_t max_sweeps;   /* PGS sweeps per Newton iteration */
   int32_t j_inner;      /* slip fixed-point passes */
   double tol;           /* PGS stopping tolerance */

@@ -83,8 +83,8 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.pgs.ctl = C.arena.alloc<int>(2);
   pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);
-  C.d_sweeps = C.arena.alloc<int>(64);
-  C.d_eps = C.arena.alloc<double>(64);
+  C.d_sweeps = C.arena.alloc<int>(kMaxNewton);
+  C.d_eps = C.arena.alloc<double>(kMaxNewton);
   C.nc_cap = nc;
 }
 
@@ -399,7 +399,7 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     S.prev_nc = 0;
     S.t = 0;
     S.d_ctx = B.alloc<StepCtx>(1);
-    S.d_stamps = B.alloc<unsigned long long>(6 + 4 * 64);
+    S.d_stamps = B.alloc<unsigned long long>(6 + 4 * kMaxNewton);
     S.obs_valid = false;
     {
       double t0 = 0.0;
@@ -609,7 +609,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     const int nc = opt->n_contacts;
     REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
     REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
-    REQUIRE(opt->n_newton >= 1 && opt->n_newton <= 64, "n_newton must be in [1, 64]");
+    REQUIRE(opt->n_newton >= 1 && opt->n_newton <= kMaxNewton, "n_newton must be in [1, 256]");
     REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
     REQUIRE(opt->scheme == 0 || opt->scheme == 1, "scheme must be 0 (fast) or 1 (standard)");
     REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");

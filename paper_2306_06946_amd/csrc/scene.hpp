@@ -216,6 +216,7 @@ void launch_advance_time(icr_scene *s);
 void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 4096;
+constexpr int kMaxNewton = 256;   // Newton iterations per step (per-iteration sweeps, eps, stamps)
 size_t pgs_wss_elems(int nc);   // doubles of the blocked coupling matrix of an active set (n_c contacts)
 size_t pgs_rec_elems(int nc);   // doubles of the prepared records (and gaps) of a first active set
 void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture

@@ -196,7 +196,7 @@ def _compare_step(sim, s, sc, steps, tag):
         assert _rel(res["q_free"].cpu().numpy() - sim.q_rest, out["q_free"] - sim.q_rest) <= 1e-10
         m = 3 * nc
         assert _rel(res["WH"].cpu().numpy().reshape(m, m), out["WH"]) <= 1e-10
-        assert rep["sweeps"] == [r["sweeps"] for r in rec]
+        assert rep["sweeps"] == [r["sweeps"] for r in rec][:16]   # the report holds the first 16
         assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
         assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
         assert _rel(res["p"].cpu().numpy() - out["p_free"], out["p"] - out["p_free"]) <= 1e-10
@@ -214,6 +214,18 @@ def test_step_tiny_matches_oracle(seed):
     s = _icr().scene_from_dict(sc)
     sim = O.Simulation(sc)
     _compare_step(sim, s, sc, 2, f"tiny seed={seed}")
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "medium"])
+def test_directions_updated_every_sweep_matches_oracle(cfg):
+    """Directions and W updated after every PGS sweep (results section): 30
+    Newton iterations of one sweep each, against the oracle's Algorithm 3
+    with the same counts."""
+    sc = make_scene(cfg, 0)
+    sc["n_newton"], sc["max_sweeps"] = 30, 1
+    s = _icr().scene_from_dict(sc)
+    sim = O.Simulation(sc)
+    _compare_step(sim, s, sc, 2, f"{cfg} per-sweep directions")
 
 
 def test_step_medium_matches_oracle():
