@@ -372,12 +372,18 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], int j_inne
   const double n10 = fma(d[0], mw12, -d[2] * mw01), n11 = fma(d[0], mm22, -d[2] * mw02);
   bool safe = rc[18] != 0.0;
   if (safe) {
-    for (int it = 0; it < j_inner; ++it) {
+    auto pass = [&]() {
       const double v0 = fma(n00, u0, fma(n01, u1, n0));
       const double v1 = fma(n10, u0, fma(n11, u1, n1));
       const double inv = frsqrt1(fma(v0, v0, v1 * v1));
       u0 = v0 * inv;
       u1 = v1 * inv;
+    };
+    if (j_inner == 8) {   // the default count: straight-line passes, no loop branch
+#pragma unroll
+      for (int it = 0; it < 8; ++it) pass();
+    } else {
+      for (int it = 0; it < j_inner; ++it) pass();
     }
     safe = (u0 == u0) && (u1 == u1);   // |v| = 0 (a NaN) takes the guarded pass below
   }
