@@ -321,6 +321,58 @@ __device__ inline double frsqrt1(double x) {
   return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
+// Guarded slip pass (rare: the record's den > 0 guarantee fails, or |v| = 0
+// occurred): den <= 0 replaced by w_nn as in the direct form, |v| = 0 keeps
+// the direction; restarts from the same initial direction.  Out of line, so
+// the chains' straight-line code keeps its registers.
+struct SlipIn {
+  double w00, w01, w02, mm11, mm22, mw12, mw01, mw02;   // record entries
+  double d0, d1, d2, lt1, lt2, nt2;                     // gap, stick trial
+  double n0, n1, n00, n01, n10, n11;                    // -v(u) = n + N u
+};
+__device__ __noinline__ double2 guarded_slip(const SlipIn a, int j_inner) {
+  const double w00 = a.w00, w01 = a.w01, w02 = a.w02, mm11 = a.mm11, mm22 = a.mm22, mw12 = a.mw12, mw01 = a.mw01,
+               mw02 = a.mw02;
+  const double d[3] = {a.d0, a.d1, a.d2};
+  const double lt1 = a.lt1, lt2 = a.lt2, nt2 = a.nt2;
+  const double n0 = a.n0, n1 = a.n1, n00 = a.n00, n01 = a.n01, n10 = a.n10, n11 = a.n11;
+  double u0, u1;
+  if (nt2 > 0.0) {
+    const double inv = frsqrt(nt2);
+    u0 = lt1 * inv;
+    u1 = lt2 * inv;
+  } else {
+    const double nd2 = d[1] * d[1] + d[2] * d[2];
+    if (nd2 > 0.0) {
+      const double inv = frsqrt(nd2);
+      u0 = -d[1] * inv;
+      u1 = -d[2] * inv;
+    } else {
+      u0 = 1.0;
+      u1 = 0.0;
+    }
+  }
+  for (int it = 0; it < j_inner; ++it) {
+    const double den = fma(mw01, u0, fma(mw02, u1, w00));
+    double v0, v1;
+    if (den > 0.0) {
+      v0 = fma(n00, u0, fma(n01, u1, n0));
+      v1 = fma(n10, u0, fma(n11, u1, n1));
+    } else {
+      const double e1 = fma(mm11, u0, fma(mw12, u1, w01)), e2 = fma(mw12, u0, fma(mm22, u1, w02));
+      v0 = fma(d[0], e1, -w00 * d[1]);
+      v1 = fma(d[0], e2, -w00 * d[2]);
+    }
+    const double s2 = v0 * v0 + v1 * v1;
+    if (s2 > 0.0) {
+      const double inv = frsqrt(s2);
+      u0 = v0 * inv;
+      u1 = v1 * inv;
+    }
+  }
+  return make_double2(u0, u1);
+}
+
 // Same branches and fixed point as local_solve, from the record: stick trial
 // by the precomputed inverse, refined reciprocals instead of divisions, and
 // the slip pass on the direction u alone.  With den(u) > 0 the tangential
@@ -388,41 +440,11 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], int j_inne
     safe = (u0 == u0) && (u1 == u1);   // |v| = 0 (a NaN) takes the guarded pass below
   }
   if (!safe) {
-    // guarded pass: den <= 0 replaced by w_nn as in the direct form, |v| = 0
-    // keeps the direction; restarts from the same initial direction
-    if (nt2 > 0.0) {
-      const double inv = frsqrt(nt2);
-      u0 = lt1 * inv;
-      u1 = lt2 * inv;
-    } else {
-      const double nd2 = d[1] * d[1] + d[2] * d[2];
-      if (nd2 > 0.0) {
-        const double inv = frsqrt(nd2);
-        u0 = -d[1] * inv;
-        u1 = -d[2] * inv;
-      } else {
-        u0 = 1.0;
-        u1 = 0.0;
-      }
-    }
-    for (int it = 0; it < j_inner; ++it) {
-      const double den = fma(mw01, u0, fma(mw02, u1, w00));
-      double v0, v1;
-      if (den > 0.0) {
-        v0 = fma(n00, u0, fma(n01, u1, n0));
-        v1 = fma(n10, u0, fma(n11, u1, n1));
-      } else {
-        const double e1 = fma(mm11, u0, fma(mw12, u1, w01)), e2 = fma(mw12, u0, fma(mm22, u1, w02));
-        v0 = fma(d[0], e1, -w00 * d[1]);
-        v1 = fma(d[0], e2, -w00 * d[2]);
-      }
-      const double s2 = v0 * v0 + v1 * v1;
-      if (s2 > 0.0) {
-        const double inv = frsqrt(s2);
-        u0 = v0 * inv;
-        u1 = v1 * inv;
-      }
-    }
+    const SlipIn a{w00, w01, w02, mm11, mm22, mw12, mw01, mw02, d[0], d[1], d[2], lt1, lt2, nt2,
+                   n0, n1, n00, n01, n10, n11};
+    const double2 u = guarded_slip(a, j_inner);
+    u0 = u.x;
+    u1 = u.y;
   }
   double den = fma(mw01, u0, fma(mw02, u1, w00));
   if (den <= 0.0) den = w00;
