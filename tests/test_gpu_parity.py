@@ -140,6 +140,66 @@ def test_solve_contacts_matches_oracle(nc, mu_zero, tiny):
     assert _rel(lam.cpu().numpy(), lam_ref) <= 1e-10
 
 
+def test_solve_contacts_at_the_contact_limit(tiny):
+    """4096 contacts (m = 12288), the largest PGS call: a low-rank-plus-diagonal
+    SPD W keeps the input cheap; most contacts stay active, so the sweeps run
+    in the large-set kernel with its gaps in dynamic LDS.  4097 is refused."""
+    icr = _icr()
+    _, s = tiny
+    nc = 4096
+    m = 3 * nc
+    rng = np.random.default_rng(4096)
+    G = rng.standard_normal((m, 24)) / np.sqrt(24.0)
+    W = G @ G.T
+    W = 0.5 * (W + W.T)
+    W[np.diag_indices(m)] += 1.0
+    W *= 50.0
+    d = rng.uniform(-1e-3, 1e-3, size=m)
+    mu = rng.uniform(0.1, 0.6, size=nc)
+    lam0 = np.zeros(m)
+    h = 0.01
+    lam_ref, st_ref, sw_ref, _ = O.pgs(W, d, mu, h, lam0, 3, 0.0, 8)
+    _say(f"[gpu] solve_contacts nc={nc}, {int(np.sum(st_ref != 0))} contacts with a force")
+    lam = _cuda(lam0)
+    status = torch.empty(nc, dtype=torch.int8, device="cuda")
+    sw, _ = s.solve_contacts(_cuda(W.ravel()), _cuda(d), _cuda(mu), h, lam, status, 3, 0.0, 8)
+    assert sw == sw_ref == 3
+    assert np.array_equal(status.cpu().numpy(), st_ref)
+    assert _rel(lam.cpu().numpy(), lam_ref) <= 1e-10
+    small = torch.zeros(16, dtype=torch.float64, device="cuda")
+    st8 = torch.zeros(16, dtype=torch.int8, device="cuda")
+    ptr = small.data_ptr()
+    code = s.L.icr_solve_contacts(s._h, nc + 1, ptr, ptr, ptr, h, ptr, st8.data_ptr(), 3, 0.0, 8, None, None)
+    assert code == icr.E_ARG
+
+
+def test_step_edge_cases(tiny):
+    """Degenerate and limit cases of one time step against the oracle: an
+    obstacle out of reach (every contact separate, the step is the free
+    motion) and the largest Newton count (256 iterations of one sweep); 257
+    iterations are refused."""
+    icr = _icr()
+    sc = make_scene("tiny", 3)
+    far = dict(sc["obstacle"])
+    far["c0"] = np.asarray(far["c0"]) - 1.0 * np.asarray(far["normal"])
+    sc_far = dict(sc, obstacle=far)
+    s = icr.scene_from_dict(sc_far)
+    sim = O.Simulation(sc_far)
+    _compare_step(sim, s, sc_far, 1, "tiny, obstacle out of reach")
+    res = s.step_results(sc["n_contacts"])
+    assert np.all(res["lam"].cpu().numpy() == 0.0)
+    assert np.all(res["status"].cpu().numpy() == 0)
+    s.close()
+    sc_n = dict(sc, n_newton=256, max_sweeps=1)
+    s = icr.scene_from_dict(sc_n)
+    sim = O.Simulation(sc_n)
+    _compare_step(sim, s, sc_n, 1, "tiny, 256 Newton iterations")
+    with pytest.raises(icr.IcrError) as e:
+        s.step(sc["obstacle"], sc["n_contacts"], 257, 1, 0.0, sc["j_inner"])
+    assert e.value.code == icr.E_ARG
+    s.close()
+
+
 def test_proximity_update_matches_formula(tiny):
     _, s = tiny
     rng = np.random.default_rng(3)
