@@ -186,7 +186,12 @@ typedef struct {
   int32_t j_inner;      /* slip fixed-point passes */
   double tol;           /* PGS stopping tolerance */
   int32_t timing;       /* 1: record per-phase device times in the report */
-  int32_t scheme;       /* 0: fast update (Algorithm 3); 1: standard rebuild (Algorithm 2) */
+  int32_t scheme;       /* 0: fast update (Algorithm 3); 1: standard rebuild (Algorithm 2);
+                           2: directions updated before every local solve (the per-constraint
+                           variant of the results section): each Newton iteration is one
+                           Gauss-Seidel call on world-frame forces in which contact a's frame,
+                           gap and block h^2 C_a W_H,aa C_a^T are taken at its current proximity
+                           p_a = p_free,a + h^2 (W_H f)_a, followed by Eq. 31 */
   int32_t graph;        /* 1: capture the step's launch sequence once (per options) as a HIP graph
                            and replay it; 0: launch every kernel eagerly.  Same results. */
 } icr_step_opts;

@@ -42,7 +42,15 @@ notes of the repository):
   R16 warm start across steps: a contact whose node was in contact at the end
       of the previous step starts from that node's world-frame force;
   R17 contacts = the K candidates with smallest signed distance at q_free
-      (ties by node id), then ordered by node id.
+      (ties by node id), then ordered by node id;
+  R18 directions updated before every local solve (the variant the results
+      section proposes, "after the resolution of each constraint"): Gauss-
+      Seidel on world-frame forces f; at contact a's turn its frame and gap
+      are taken at its current proximity p_a = p_free,a + h^2 sum_b W_H,ab f_b
+      and the local problem is R9 applied to that contact alone:
+      d_a = delta(p_a) - W~_aa C_a f_a with W~_aa = h^2 C_a W_H,aa C_a^T; the
+      stopping rule R7 is taken on f.  With a plane obstacle (constant frames,
+      affine gap) this is exactly the PGS of one Newton iteration.
 """
 from __future__ import annotations
 
@@ -456,6 +464,64 @@ def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_s
     return f, p, C, lam, info
 
 
+def pgs_per_constraint(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, max_sweeps, tol, j_inner=8):
+    """Gauss-Seidel with the directions updated before every local solve (R18).
+
+    Returns (f world force [nc,3], C last frames [nc,3,3], lambda [m] in those
+    frames, status [nc], sweeps, eps).
+    """
+    nc = len(p_free) // 3
+    WH = np.asarray(WH, dtype=np.float64)
+    f = np.array(f_init, dtype=np.float64).reshape(nc, 3)
+    C = np.zeros((nc, 3, 3))
+    lam = np.zeros(3 * nc)
+    status = np.zeros(nc, dtype=np.int8)
+    eps = math.inf
+    sweeps = 0
+    h2 = h * h
+    for sweep in range(max_sweeps):
+        prev = f.copy()
+        for a in range(nc):
+            r0, r1 = 3 * a, 3 * a + 3
+            pa = p_free[r0:r1] + h2 * (WH[r0:r1] @ f.ravel())          # current proximity of contact a
+            Ca, delta = directions(pa, p_start[r0:r1], obs, t0, t1)      # its frame and gap there
+            Ca = Ca[0]
+            Wl = h2 * (Ca @ WH[r0:r1, r0:r1] @ Ca.T)
+            da = delta - Wl @ (Ca @ f[a])                               # R9 for this contact alone
+            (l0, l1, l2), st = local_solve(Wl.tolist(), da.tolist(), float(mu[a]), j_inner)
+            la = np.array([l0, l1, l2])
+            f[a] = Ca.T @ la
+            C[a] = Ca
+            lam[r0:r1] = la
+            status[a] = st
+        sweeps = sweep + 1
+        diff = float(np.sqrt(np.sum((f - prev) ** 2)))
+        nf = float(np.sqrt(np.sum(f * f)))
+        eps = diff / nf if nf > 0.0 else (0.0 if diff == 0.0 else math.inf)
+        if eps <= tol:
+            break
+    return f, C, lam, status, sweeps, eps
+
+
+def newton_per_constraint(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_sweeps, tol, j_inner,
+                          record=None):
+    """Algorithm 3's loop with the per-constraint direction update (R18) in place
+    of steps 1-3: n_newton calls of max_sweeps sweeps, each followed by the
+    proximity update of Eq. 31."""
+    f = np.array(f_init, dtype=np.float64).reshape(-1, 3)
+    p = p_free + (h * h) * (WH @ f.ravel())
+    info = []
+    C = lam = None
+    for k in range(n_newton):
+        f, C, lam, status, sweeps, eps = pgs_per_constraint(WH, p_free, p_start, obs, t0, t1, mu, h, f, max_sweeps,
+                                                           tol, j_inner)
+        p = p_free + (h * h) * (WH @ f.ravel())
+        info.append(dict(sweeps=sweeps, eps=eps, status=status.copy()))
+        if record is not None:
+            record.append(dict(C=C, lam=lam.copy(), status=status.copy(), p=p.copy(), sweeps=sweeps, eps=eps))
+    return f, p, C, lam, info
+
+
 def newton_standard(factor, nodes_c, n, q_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_sweeps,
                     tol, j_inner, record=None):
     """Algorithm 2: re-linearise, rebuild W_k = J_k A^-1 J_k^T, PGS, correct, integrate, remap."""
@@ -503,7 +569,7 @@ class Simulation:
         self.mu_of_node = np.zeros(len(scene["nodes"]))
         self.mu_of_node[cand] = scene["cand_mu"]
 
-    def step(self, standard=False, record=None, max_sweeps=None, tol=None):
+    def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False):
         sc = self.scene
         h = sc["h"]
         t0, t1 = self.t, self.t + h
@@ -524,8 +590,9 @@ class Simulation:
         else:
             WH = build_WH(self.factor, nodes_c, self.n)
             out["WH"] = WH
-            f, p, C, lam, info = newton_fast(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h, f_init,
-                                             sc["n_newton"], ms, tl, sc["j_inner"], record)
+            newton = newton_per_constraint if per_constraint else newton_fast
+            f, p, C, lam, info = newton(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h, f_init,
+                                        sc["n_newton"], ms, tl, sc["j_inner"], record)
             out["info"] = info
         # corrective motion and integration (Eq. 20, Algorithm 1 last loop, R1)
         dv = dv_free + h * self.factor.solve(H.T @ f.ravel())

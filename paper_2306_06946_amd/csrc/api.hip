@@ -549,6 +549,7 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   const double h = s->mesh.h;
   const int nc = opt->n_contacts, nk = opt->n_newton;
   const bool standard = opt->scheme == 1;
+  const bool per_constraint = opt->scheme == 2;
   auto mark = [&](int base, int i) {
     if (opt->timing) launch_stamp(s, base + i);
   };
@@ -563,7 +564,19 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   mark(ev, 2);
   if (!standard) build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
   mark(ev, 3);
+  // directions updated before every local solve: proximity of the warm start
+  if (per_constraint) launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
   for (int k = 0; k < nk; ++k) {
+    if (per_constraint) {
+      mark(kev, 4 * k);
+      mark(kev, 4 * k + 1);
+      launch_pgs_per_constraint(st, nc, S.d_ctx, C.d_WH, C.d_p, C.d_pstart, C.d_mu, h, C.d_f, C.d_C, C.d_lam,
+                                C.d_status, opt->max_sweeps, opt->tol, opt->j_inner, C.d_sweeps + k, C.d_eps + k);
+      mark(kev, 4 * k + 2);
+      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+      mark(kev, 4 * k + 3);
+      continue;
+    }
     launch_directions(s, nc, k == 0);
     mark(kev, 4 * k);
     if (standard)
@@ -611,7 +624,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
     REQUIRE(opt->n_newton >= 1 && opt->n_newton <= kMaxNewton, "n_newton must be in [1, 256]");
     REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
-    REQUIRE(opt->scheme == 0 || opt->scheme == 1, "scheme must be 0 (fast) or 1 (standard)");
+    REQUIRE(opt->scheme >= 0 && opt->scheme <= 2, "scheme must be 0 (fast), 1 (standard) or 2 (per constraint)");
     REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");
     ensure_contact_buffers(s, nc);
     ensure_rhs_capacity(s, nc);

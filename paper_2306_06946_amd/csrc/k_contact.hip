@@ -111,17 +111,11 @@ __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restric
   }
 }
 
-// Frames C_k and gaps at p_{k-1}; d_k = delta - C_k (p - p_free); warm start
-// lambda = C_k f with f the previous world-frame force.
-__global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const double *__restrict__ p,
-                             const double *__restrict__ pfree, const double *__restrict__ pstart,
-                             const double *__restrict__ fprev, double *__restrict__ C, double *__restrict__ dk,
-                             double *__restrict__ lam) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  const icr_obstacle obs = ctx->obs;
-  const double t0 = ctx->t0, t1 = ctx->t0 + ctx->h;
-  double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
+// Frame (rows n, t1, t2: normal and axis-rule tangents) and gap delta of a
+// contact at proximity pc: normal gap = signed distance at t1, tangential gap
+// = relative tangential displacement over the step.
+__device__ inline void contact_frame(const icr_obstacle &obs, double t0, double t1, const double pc[3],
+                                     const double ps[3], double F[3][3], double delta[3]) {
   double n[3];
   double phi = signed_distance(obs, t1, pc, n);
   int ax = 0;
@@ -142,11 +136,32 @@ __global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const doub
   double rel[3];
   for (int a = 0; a < 3; ++a) {
     double uo = (obs.c0[a] + obs.vel[a] * t1) - (obs.c0[a] + obs.vel[a] * t0);
-    rel[a] = pc[a] - pstart[3 * c + a] - uo;
+    rel[a] = pc[a] - ps[a] - uo;
   }
-  double F[3][3] = {{n[0], n[1], n[2]}, {ta[0], ta[1], ta[2]}, {tb[0], tb[1], tb[2]}};
-  double delta[3] = {phi, ta[0] * rel[0] + ta[1] * rel[1] + ta[2] * rel[2],
-                     tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2]};
+  for (int a = 0; a < 3; ++a) {
+    F[0][a] = n[a];
+    F[1][a] = ta[a];
+    F[2][a] = tb[a];
+  }
+  delta[0] = phi;
+  delta[1] = ta[0] * rel[0] + ta[1] * rel[1] + ta[2] * rel[2];
+  delta[2] = tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2];
+}
+
+// Frames C_k and gaps at p_{k-1}; d_k = delta - C_k (p - p_free); warm start
+// lambda = C_k f with f the previous world-frame force.
+__global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const double *__restrict__ p,
+                             const double *__restrict__ pfree, const double *__restrict__ pstart,
+                             const double *__restrict__ fprev, double *__restrict__ C, double *__restrict__ dk,
+                             double *__restrict__ lam) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const icr_obstacle obs = ctx->obs;
+  const double t0 = ctx->t0, t1 = ctx->t0 + ctx->h;
+  double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
+  double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
+  double F[3][3], delta[3];
+  contact_frame(obs, t0, t1, pc, ps, F, delta);
   double dp[3] = {pc[0] - pfree[3 * c], pc[1] - pfree[3 * c + 1], pc[2] - pfree[3 * c + 2]};
   for (int r = 0; r < 3; ++r) {
     for (int a = 0; a < 3; ++a) C[9 * c + 3 * r + a] = F[r][a];
@@ -689,6 +704,146 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
     if (tid == 0) {
       double diff = sqrt(dsum), nl = sqrt(nl2);
       eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
+      stop = (eps <= tol) ? 1 : 0;
+    }
+    __syncthreads();
+    if (stop) {
+      ++sweep;
+      break;
+    }
+  }
+  if (tid == 0) {
+    *sweeps_out = sweep;
+    *eps_out = eps;
+  }
+}
+
+// Gauss-Seidel with the directions updated before every local solve (the
+// per-constraint variant of the results section), one workgroup.  The current
+// proximity P = p_free + h^2 W_H f of every contact (world frame) lives in
+// LDS.  At contact a's turn: frame C_a and gap delta at P_a, block
+// W~_aa = h^2 C_a W_H,aa C_a^T, gap without the own force
+// d = delta - W~_aa C_a f_a (the linearisation of Algorithm 3 at P_a), local
+// solve, f_a = C_a^T lambda_a, then P += h^2 W_H[:, a] (f_a - f_a^old) from
+// the rows of the exactly symmetric W_H.  A contact with no force and a
+// non-negative normal gap is a no-op; wave 0 finds the next contact that can
+// change 64 at a time and writes the frames of the skipped ones.
+__host__ __device__ inline size_t pgs_pc_lds(int nc) { return (size_t)nc * 3 * sizeof(double); }
+__global__ __launch_bounds__(1024) void k_pgs_pc(int nc, const StepCtx *__restrict__ ctx,
+                                                 const double *__restrict__ WH, const double *__restrict__ pin,
+                                                 const double *__restrict__ pstart, const double *__restrict__ mu,
+                                                 double h2, double *__restrict__ f, double *__restrict__ C,
+                                                 double *__restrict__ lam, int8_t *__restrict__ status,
+                                                 int max_sweeps, double tol, int j_inner, int *__restrict__ sweeps_out,
+                                                 double *__restrict__ eps_out) {
+  extern __shared__ double lds_P[];
+  double *P = lds_P;
+  __shared__ double bc[3];
+  __shared__ double red[16];
+  __shared__ int ctl_s;
+  __shared__ int stop;
+  const int m = 3 * nc;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const icr_obstacle obs = ctx->obs;
+  const double t0 = ctx->t0, t1 = ctx->t0 + ctx->h;
+  for (int i = tid; i < m; i += 1024) P[i] = pin[i];
+  if (tid == 0) stop = 0;
+  __syncthreads();
+  int sweep = 0;
+  double eps = 0.0, dsum = 0.0;
+  for (sweep = 0; sweep < max_sweeps; ++sweep) {
+    dsum = 0.0;
+    int a = 0;
+    while (true) {
+      if (wv == 0) {
+        int next = nc;
+        while (a < nc) {
+          const int c = a + ln;
+          bool active = false;
+          double Fc[3][3], dc[3];
+          if (c < nc) {
+            const double pc[3] = {P[3 * c], P[3 * c + 1], P[3 * c + 2]};
+            const double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
+            contact_frame(obs, t0, t1, pc, ps, Fc, dc);
+            active = f[3 * c] != 0.0 || f[3 * c + 1] != 0.0 || f[3 * c + 2] != 0.0 || dc[0] < 0.0;
+          }
+          const unsigned long long bal = __ballot(active);
+          const int first = bal ? __ffsll((long long)bal) - 1 : 64;
+          if (c < nc && ln < first) {   // skipped: separate, frame at its (unchanged) proximity
+            for (int r = 0; r < 3; ++r) {
+              for (int q = 0; q < 3; ++q) C[9L * c + 3 * r + q] = Fc[r][q];
+              lam[3 * c + r] = 0.0;
+            }
+            status[c] = (int8_t)ICR_SEPARATE;
+          }
+          if (bal == 0ull) {
+            a += 64;
+            continue;
+          }
+          next = a + first;
+          break;
+        }
+        if (next < nc) {
+          // every lane of wave 0 runs the local solve on the same data
+          const double pc[3] = {P[3 * next], P[3 * next + 1], P[3 * next + 2]};
+          const double ps[3] = {pstart[3 * next], pstart[3 * next + 1], pstart[3 * next + 2]};
+          double F[3][3], delta[3];
+          contact_frame(obs, t0, t1, pc, ps, F, delta);
+          double B[3][3];   // W_H,aa C_a^T
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+              const double *wr = WH + (3L * next + i) * m + 3L * next;
+              B[i][j] = wr[0] * F[j][0] + wr[1] * F[j][1] + wr[2] * F[j][2];
+            }
+          double w[3][3];
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) w[i][j] = h2 * (F[i][0] * B[0][j] + F[i][1] * B[1][j] + F[i][2] * B[2][j]);
+          for (int i = 0; i < 3; ++i)   // exactly symmetric block
+            for (int j = 0; j < i; ++j) w[j][i] = w[i][j];
+          const double fo[3] = {f[3 * next], f[3 * next + 1], f[3 * next + 2]};
+          double lr[3], dd[3];
+          for (int i = 0; i < 3; ++i) lr[i] = F[i][0] * fo[0] + F[i][1] * fo[1] + F[i][2] * fo[2];
+          for (int i = 0; i < 3; ++i) dd[i] = delta[i] - (w[i][0] * lr[0] + w[i][1] * lr[1] + w[i][2] * lr[2]);
+          double rec[PGS_RW];
+          make_record(w, mu[next], rec);
+          const Local r = local_solve_rec(rec, dd, j_inner);
+          double fn[3], df[3];
+          for (int q = 0; q < 3; ++q) {
+            fn[q] = F[0][q] * r.l[0] + F[1][q] * r.l[1] + F[2][q] * r.l[2];
+            df[q] = fn[q] - fo[q];
+            dsum += df[q] * df[q];
+          }
+          if (ln == 0) {
+            for (int q = 0; q < 3; ++q) {
+              bc[q] = df[q];
+              f[3 * next + q] = fn[q];
+              lam[3 * next + q] = r.l[q];
+              for (int k = 0; k < 3; ++k) C[9L * next + 3 * q + k] = F[q][k];
+            }
+            status[next] = (int8_t)r.st;
+          }
+        }
+        if (ln == 0) ctl_s = next;
+      }
+      __syncthreads();
+      const int cur = ctl_s;
+      if (cur >= nc) break;
+      const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
+      if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
+        const double *r0 = WH + (3L * cur) * m;
+        for (int i = tid; i < m; i += 1024) P[i] += h2 * (r0[i] * d0 + r0[m + i] * d1 + r0[2L * m + i] * d2);
+      }
+      __syncthreads();
+      a = cur + 1;
+    }
+    // eps = |f_i - f_{i-1}| / |f_i|
+    double part = 0.0;
+    __threadfence_block();
+    for (int i = tid; i < m; i += 1024) part += f[i] * f[i];
+    const double nf2 = block_sum(part, red);
+    if (tid == 0) {
+      const double diff = sqrt(dsum), nf = sqrt(nf2);
+      eps = nf > 0.0 ? diff / nf : (diff == 0.0 ? 0.0 : INFINITY);
       stop = (eps <= tol) ? 1 : 0;
     }
     __syncthreads();
@@ -1414,6 +1569,15 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   ICR_LAUNCH_CHECK();
 }
 
+void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
+                               const double *pstart, const double *mu, double h, double *f, double *Cm,
+                               double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
+                               double *eps_dev) {
+  k_pgs_pc<<<1, 1024, pgs_pc_lds(nc), st>>>(nc, ctx, WH, p, pstart, mu, h * h, f, Cm, lam, status, max_sweeps, tol,
+                                           j_inner, sweeps_dev, eps_dev);
+  ICR_LAUNCH_CHECK();
+}
+
 size_t pgs_rec_elems(int nc) { return (size_t)std::min(nc, PGS_WAVE_MAX) * PGS_RW; }
 
 size_t pgs_wss_elems(int nc) {
@@ -1428,6 +1592,8 @@ void pgs_prepare() {
                               (int)sizeof(PgsLds)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_single_lds(PGS_MAX_NC)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_pc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pgs_pc_lds(PGS_MAX_NC)));
   done = true;
 }
 

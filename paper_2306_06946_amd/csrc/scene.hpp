@@ -220,6 +220,10 @@ constexpr int kMaxNewton = 256;   // Newton iterations per step (per-iteration s
 size_t pgs_wss_elems(int nc);   // doubles of the blocked coupling matrix of an active set (n_c contacts)
 size_t pgs_rec_elems(int nc);   // doubles of the prepared records (and gaps) of a first active set
 void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture
+void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
+                               const double *pstart, const double *mu, double h, double *f, double *Cm,
+                               double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
+                               double *eps_dev);
 void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
                 double *eps_dev, const PgsWork &wk);

@@ -245,9 +245,10 @@ class Scene:
                                                 _dptr(p, t.float64)))
 
     def step(self, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, timing=False,
-             report=True, standard=False, graph=True):
+             report=True, standard=False, graph=True, per_constraint=False):
         ob = _obstacle(obstacle)
-        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, 1 if standard else 0,
+        scheme = 1 if standard else (2 if per_constraint else 0)
+        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, scheme,
                       1 if graph else 0)
         rep = StepReport()
         self._check(self.L.icr_step(self._h, C.byref(ob), C.byref(op), C.byref(rep) if report else None))

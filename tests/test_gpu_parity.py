@@ -288,6 +288,36 @@ def test_directions_updated_every_sweep_matches_oracle(cfg):
     _compare_step(sim, s, sc, 2, f"{cfg} per-sweep directions")
 
 
+@pytest.mark.parametrize("cfg,seed", [("tiny", 0), ("tiny", 2), ("medium", 0)])
+def test_per_constraint_directions_match_oracle(cfg, seed):
+    """Directions updated before every local solve (scheme 2) against the
+    oracle's per-constraint Gauss-Seidel: plane (tiny) and sphere (medium)."""
+    icr = _icr()
+    sc = make_scene(cfg, seed)
+    if cfg == "medium":
+        sc["max_sweeps"] = 60
+    nc = sc["n_contacts"]
+    s = icr.scene_from_dict(sc)
+    sim = O.Simulation(sc)
+    for k in range(2):
+        _say(f"[gpu] per-constraint directions {cfg} seed={seed} step {k}")
+        rep = s.step(sc["obstacle"], nc, sc["n_newton"], sc["max_sweeps"], sc["tol"], sc["j_inner"],
+                     per_constraint=True)
+        rec = []
+        out = sim.step(record=rec, per_constraint=True)
+        res = s.step_results(nc)
+        q, v, _ = s.get_state()
+        assert np.array_equal(res["node_ids"].cpu().numpy(), out["nodes_c"])
+        assert rep["sweeps"] == [r["sweeps"] for r in rec][:16]
+        assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+        assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+        assert _rel(res["C"].cpu().numpy().reshape(-1, 3, 3), rec[-1]["C"]) <= 1e-12
+        assert _rel(res["p"].cpu().numpy() - out["p_free"], out["p"] - out["p_free"]) <= 1e-10
+        assert _rel(q.cpu().numpy() - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+        assert _rel(v.cpu().numpy(), out["v"]) <= 1e-10
+    s.close()
+
+
 def test_step_medium_matches_oracle():
     sc = make_scene("medium", 0)
     sc["max_sweeps"] = 100

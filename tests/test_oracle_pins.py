@@ -385,6 +385,72 @@ def test_sphere_newton_final_proximity_matches_positions():
     assert np.abs(H @ out["q"] - out["p"]).max() <= 1e-12 * np.abs(out["p"]).max()
 
 
+def _step_inputs(sc):
+    sim = O.Simulation(sc)
+    h = sc["h"]
+    _, q_free, _ = O.free_motion(sim.asm, sim.factor, sc, sim.q, sim.v, sim.q_rest)
+    nodes = O.select_contacts(q_free, sc, h)
+    H = O.mapping_H(nodes, sim.n)
+    WH = O.build_WH(sim.factor, nodes, sim.n)
+    return dict(WH=WH, p_free=H @ q_free, p_start=H @ sim.q, mu=sim.mu_of_node[nodes], h=h, t0=0.0, t1=h,
+                obs=sc["obstacle"])
+
+
+def test_per_constraint_update_is_plain_pgs_on_a_plane():
+    """Plane obstacle: the frame is constant and the gap affine in p, so the
+    per-constraint direction update (R18) takes the same Gauss-Seidel steps as
+    the PGS of one Newton iteration, started from the same force."""
+    sc = make_scene("tiny", 1)
+    x = _step_inputs(sc)
+    nc = len(x["mu"])
+    rng = np.random.default_rng(5)
+    f0 = np.zeros((nc, 3))
+    f0[::3] = rng.uniform(0.0, 2.0, size=(len(f0[::3]), 3)) * np.array([-1.0, 0.1, 0.1])
+    f, C, lam, st, sw, eps = O.pgs_per_constraint(x["WH"], x["p_free"], x["p_start"], x["obs"], x["t0"], x["t1"],
+                                                  x["mu"], x["h"], f0, 40, 0.0)
+    C1, delta = O.directions(x["p_free"], x["p_start"], x["obs"], x["t0"], x["t1"])
+    W = np.einsum("aij,ajbk,blk->aibl", C1, x["WH"].reshape(nc, 3, nc, 3), C1).reshape(3 * nc, 3 * nc)
+    lam0 = np.einsum("aij,aj->ai", C1, f0).ravel()
+    lam_p, st_p, sw_p, _ = O.pgs(W, delta, x["mu"], x["h"], lam0, 40, 0.0)
+    assert sw == sw_p == 40
+    assert np.array_equal(st, st_p)
+    assert np.array_equal(C, C1)
+    f_p = np.einsum("aji,aj->ai", C1, lam_p.reshape(nc, 3))
+    assert np.linalg.norm(f - f_p) <= 1e-12 * np.linalg.norm(f_p)
+    assert set(st.tolist()) >= {O.SEPARATE, O.SLIP}
+
+
+def test_per_constraint_update_converges_to_the_nonlinear_contact_conditions():
+    """Sphere obstacle: at a fixed point of the per-constraint update every
+    contact satisfies Signorini and Coulomb in the frame and gap evaluated at
+    its own final proximity p = p_free + h^2 W_H f (computed afresh here)."""
+    sc = make_scene("medium", 0)
+    sc["n_contacts"] = 40
+    x = _step_inputs(sc)
+    nc = len(x["mu"])
+    f, C, lam, st, sw, eps = O.pgs_per_constraint(x["WH"], x["p_free"], x["p_start"], x["obs"], x["t0"], x["t1"],
+                                                  x["mu"], x["h"], np.zeros((nc, 3)), 5000, 1e-14)
+    assert eps <= 1e-14
+    p = x["p_free"] + x["h"] ** 2 * (x["WH"] @ f.ravel())
+    phi, nrm = O.signed_distance(p, x["obs"], x["t1"])
+    u = O.obstacle_point(x["obs"], x["t1"]) - O.obstacle_point(x["obs"], x["t0"])
+    rel = p.reshape(-1, 3) - x["p_start"].reshape(-1, 3) - u
+    scale_f = np.abs(f).max()
+    tau = 1e-9 * np.abs(phi).max()
+    for a in range(nc):
+        ln = f[a] @ nrm[a]                    # normal force along the final normal
+        ft = f[a] - ln * nrm[a]               # tangential force
+        dt = rel[a] - (rel[a] @ nrm[a]) * nrm[a]   # tangential gap in the tangent plane
+        assert ln >= -1e-12 * scale_f and phi[a] >= -tau
+        assert abs(ln * phi[a]) <= tau * max(scale_f, 1e-300)
+        assert np.linalg.norm(ft) <= x["mu"][a] * ln * (1 + 1e-10) + 1e-12 * scale_f
+        if st[a] == O.STICK:
+            assert np.linalg.norm(dt) <= tau
+        if st[a] == O.SLIP:
+            assert ft @ dt <= tau * max(np.linalg.norm(ft), 1e-300)
+    assert set(st.tolist()) >= {O.SEPARATE, O.STICK} or set(st.tolist()) >= {O.SEPARATE, O.SLIP}
+
+
 # ---------------------------------------------------------------------------
 # The paper's Table 1 bookkeeping, which fixes the scope of a "step"
 # ---------------------------------------------------------------------------
