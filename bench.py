@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--per-sweep-steps", type=int, default=0,
                     help="also time this many steps with the directions updated after every PGS sweep "
                          "(n_newton x sweeps iterations of one sweep); 0 = skip")
+    ap.add_argument("--per-constraint-steps", type=int, default=0,
+                    help="also time this many steps with the directions updated before every local solve; 0 = skip")
     ap.add_argument("--graph", action="store_true",
                     help="replay the captured step graph instead of launching every step eagerly (eager is about "
                          "1%% faster here: the graph replay loses part of the overlap of the W_H products)")
@@ -429,6 +431,23 @@ def main():
             "ms_per_step": pp["ms_total"], "metric_scope_ms": pp["ms_build_WH"] + pp["ms_newton"],
             "ms_update_W": pp["ms_update_W"], "ms_pgs": pp["ms_pgs"], "ms_corr": pp["ms_corr"],
             "fast_ms_per_step": fp["ms_total"], "fast_metric_scope_ms": fp["ms_build_WH"] + fp["ms_newton"],
+            "status_counts": [pr[-1]["n_separate"], pr[-1]["n_stick"], pr[-1]["n_slip"]],
+        }
+    if args.per_constraint_steps > 0:
+        # variant of the results section: directions updated before every
+        # local solve (one-workgroup Gauss-Seidel on world-frame forces), same
+        # Newton and sweep counts
+        npc = min(args.per_constraint_steps, traj)
+        log(f"[bench] directions updated before every local solve: {npc} steps...")
+        s.set_state(q0, v0, t_init)
+        pr = [s.step(sc["obstacle"], nc, n_newton, args.sweeps, 0.0, sc["j_inner"], timing=True,
+                     per_constraint=True, graph=False) for _ in range(npc)]
+        keys = ("ms_total", "ms_build_WH", "ms_newton", "ms_pgs", "ms_corr")
+        pp = {k: float(np.mean([r[k] for r in pr])) for k in keys}
+        out["per_constraint_directions"] = {
+            "steps": npc, "newton_iterations": n_newton, "sweeps_per_iteration": args.sweeps,
+            "ms_per_step": pp["ms_total"], "metric_scope_ms": pp["ms_build_WH"] + pp["ms_newton"],
+            "ms_pgs": pp["ms_pgs"], "ms_corr": pp["ms_corr"],
             "status_counts": [pr[-1]["n_separate"], pr[-1]["n_stick"], pr[-1]["n_slip"]],
         }
     if args.serving > 0:
