@@ -174,7 +174,8 @@ typedef struct {
 } icr_obstacle;
 
 /* Contact candidates (surface nodes) and their friction coefficients, host
- * arrays, copied.  Candidates must be distinct and not clamped. */
+ * arrays, copied.  count in [1, 4096]; candidates must be distinct, in range
+ * and not clamped, mu finite and >= 0 (else ICR_E_ARG). */
 icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu);
 
 typedef struct {
