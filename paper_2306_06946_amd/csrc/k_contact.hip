@@ -397,6 +397,8 @@ __device__ __noinline__ double2 guarded_slip(const SlipIn a, int j_inner) {
 // an affine map of u, so a pass is u <- -v / |v| (same iterates up to
 // rounding).  Every VALU instruction of the single issuing wave costs the
 // same whatever its dependences, so the pass is kept to 14 of them.
+// J = 8: the default pass count, straight-line; J = 0: j_inner passes in a loop.
+template <int J>
 __device__ Local local_solve_rec(const double *rc, const double d[3], int j_inner) {
   Local out;
   if (d[0] >= 0.0) {
@@ -446,7 +448,7 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], int j_inne
       u0 = v0 * inv;
       u1 = v1 * inv;
     };
-    if (j_inner == 8) {   // the default count: straight-line passes, no loop branch
+    if constexpr (J == 8) {   // the default count: straight-line passes, no loop branch
 #pragma unroll
       for (int it = 0; it < 8; ++it) pass();
     } else {
@@ -806,7 +808,7 @@ __global__ __launch_bounds__(1024) void k_pgs_pc(int nc, const StepCtx *__restri
           for (int i = 0; i < 3; ++i) dd[i] = delta[i] - (w[i][0] * lr[0] + w[i][1] * lr[1] + w[i][2] * lr[2]);
           double rec[PGS_RW];
           make_record(w, mu[next], rec);
-          const Local r = local_solve_rec(rec, dd, j_inner);
+          const Local r = j_inner == 8 ? local_solve_rec<8>(rec, dd, j_inner) : local_solve_rec<0>(rec, dd, j_inner);
           double fn[3], df[3];
           for (int q = 0; q < 3; ++q) {
             fn[q] = F[0][q] * r.l[0] + F[1][q] * r.l[1] + F[2][q] * r.l[2];
@@ -943,7 +945,7 @@ __device__ inline void chain_rec(ChainRec &c, const PgsLds &L, int i) {
 // W~(own rows, i) dlambda_i to its gaps.  Straight-line apart from the local
 // solve and the one-lane store, so loads in flight are waited for only where
 // they are used.
-template <int K, int NS>
+template <int K, int NS, int J>
 __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], const ChainRec &c,
                                   double (&g)[NS][3], PgsLds &L, int j_inner, int ln) {
   const int li = i & 63;
@@ -955,7 +957,7 @@ __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], co
   dd[0] = readlane_f64(g[K][0], li);
   dd[1] = readlane_f64(g[K][1], li);
   dd[2] = readlane_f64(g[K][2], li);
-  const Local rs = local_solve_rec(rc, dd, j_inner);
+  const Local rs = local_solve_rec<J>(rc, dd, j_inner);
   if (ln == 0) {
     double *lp = L.rec + PGS_RW * i + 19;
     lp[0] = rs.l[0];
@@ -976,18 +978,18 @@ __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], co
 // Contacts 64K .. 64K+63 of the sweep; blocks of the next two contacts and the
 // record of the next one are in flight while the current one is solved.
 // Loads past the end re-read the last contact (unused).
-template <int K, int NS>
+template <int K, int NS, int J>
 __device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln,
                                   double (&g)[NS][3], double2 (&A)[NS][PGS_BLK / 2], double2 (&B)[NS][PGS_BLK / 2],
                                   ChainRec &rA, ChainRec &rB) {
   const int last = nS - 1, end = min(nS, 64 * K + 64);
   for (int i = 64 * K; i < end; i += 2) {
     chain_rec(rB, L, min(i + 1, last));
-    chain_step<K, NS>(i, A, rA, g, L, j_inner, ln);
+    chain_step<K, NS, J>(i, A, rA, g, L, j_inner, ln);
     chain_load<NS>(A, Wb, min(i + 2, last), ln);
     if (i + 1 < end) {
       chain_rec(rA, L, min(i + 2, last));
-      chain_step<K, NS>(i + 1, B, rB, g, L, j_inner, ln);
+      chain_step<K, NS, J>(i + 1, B, rB, g, L, j_inner, ln);
     }
     chain_load<NS>(B, Wb, min(i + 3, last), ln);
   }
@@ -996,7 +998,7 @@ __device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds 
 // Sequential sweep over S by wave 0 alone: gaps of S (without own term) live
 // in the lanes' registers, forces, records and statuses in LDS; no barrier is
 // taken inside the sweep.
-template <int NS>
+template <int NS, int J>
 __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int ln = threadIdx.x & 63;
   double g[NS][3];
@@ -1012,8 +1014,8 @@ __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int
   chain_load<NS>(A, Wb, 0, ln);
   chain_load<NS>(B, Wb, min(1, last), ln);
   chain_rec(rA, L, 0);
-  chain_slot<0, NS>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
-  if constexpr (NS > 1) chain_slot<1, NS>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
+  chain_slot<0, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
+  if constexpr (NS > 1) chain_slot<1, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int c = ln + 64 * k;
@@ -1029,6 +1031,7 @@ __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int
 // slots.  Per contact the owning wave publishes e_i through LDS, one block
 // barrier follows, then every chain wave runs the same local solve and
 // updates its own rows (the other waves only take the barriers).
+template <int J>
 __device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const bool chain = w < Q;
@@ -1076,7 +1079,7 @@ __device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds
     for (int q = 0; q < 19; ++q) rc[q] = c[q];
     const double lo0 = c[19], lo1 = c[20], lo2 = c[21];
     double dd[3] = {L.ebuf[i & 1][0], L.ebuf[i & 1][1], L.ebuf[i & 1][2]};
-    const Local rs = local_solve_rec(rc, dd, j_inner);
+    const Local rs = local_solve_rec<J>(rc, dd, j_inner);
     if (w == 0 && ln == 0) {
       double *lp = L.rec + PGS_RW * i + 19;
       lp[0] = rs.l[0];
@@ -1395,13 +1398,23 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     if (nS > 0) {
       if (nS <= 128) {
         if (wv == 0) {
-          if (nsp == 64)
-            chain_wave<1>(nS, Wss, L, j_inner);
-          else
-            chain_wave<2>(nS, Wss, L, j_inner);
+          if (j_inner == 8) {
+            if (nsp == 64)
+              chain_wave<1, 8>(nS, Wss, L, j_inner);
+            else
+              chain_wave<2, 8>(nS, Wss, L, j_inner);
+          } else {
+            if (nsp == 64)
+              chain_wave<1, 0>(nS, Wss, L, j_inner);
+            else
+              chain_wave<2, 0>(nS, Wss, L, j_inner);
+          }
         }
       } else {
-        chain_multi(nS, (nS + 127) / 128, Wss, L, j_inner);
+        if (j_inner == 8)
+          chain_multi<8>(nS, (nS + 127) / 128, Wss, L, j_inner);
+        else
+          chain_multi<0>(nS, (nS + 127) / 128, Wss, L, j_inner);
       }
     }
     __syncthreads();
