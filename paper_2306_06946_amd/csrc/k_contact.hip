@@ -284,7 +284,7 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
 
 // Per-contact record of the active-set PGS, computed once per active set from
 // the symmetric 3x3 block w of h^2 W_aa and mu (kappa = (w11 + w22) / 2):
-//   0-5  w00 w01 w02 w11 w12 w22      6-11 the same entries of w^-1
+//   0-5  w00 w01 w02 w11 w12 w22      6-11 the same entries of -w^-1
 //   12   mu (w11 - kappa)   13 mu (w22 - kappa)   14 mu w12
 //   15   mu w01             16 mu w02             17 mu
 //   18   1 if w00 > mu |(w01, w02)| with margin (then den(u) > 0 on the unit
@@ -302,12 +302,12 @@ __device__ inline void make_record(const double w[3][3], double mu, double *rec)
   rec[3] = w11;
   rec[4] = w12;
   rec[5] = w22;
-  rec[6] = c00 * idet;
-  rec[7] = c01 * idet;
-  rec[8] = c02 * idet;
-  rec[9] = c11 * idet;
-  rec[10] = c12 * idet;
-  rec[11] = c22 * idet;
+  rec[6] = -(c00 * idet);
+  rec[7] = -(c01 * idet);
+  rec[8] = -(c02 * idet);
+  rec[9] = -(c11 * idet);
+  rec[10] = -(c12 * idet);
+  rec[11] = -(c22 * idet);
   rec[12] = mu * (w11 - kap);
   rec[13] = mu * (w22 - kap);
   rec[14] = mu * w12;
@@ -408,9 +408,10 @@ __device__ Local local_solve_rec(const double *rc, const double d[3], int j_inne
   }
   const double w00 = rc[0], w01 = rc[1], w02 = rc[2];
   const double mm11 = rc[12], mm22 = rc[13], mw12 = rc[14], mw01 = rc[15], mw02 = rc[16], mu = rc[17];
-  const double ln = -(rc[6] * d[0] + rc[7] * d[1] + rc[8] * d[2]);
-  const double lt1 = -(rc[7] * d[0] + rc[9] * d[1] + rc[10] * d[2]);
-  const double lt2 = -(rc[8] * d[0] + rc[10] * d[1] + rc[11] * d[2]);
+  // the record holds -w^-1: the stick trial lambda = -w^-1 d without a negation
+  const double ln = rc[6] * d[0] + rc[7] * d[1] + rc[8] * d[2];
+  const double lt1 = rc[7] * d[0] + rc[9] * d[1] + rc[10] * d[2];
+  const double lt2 = rc[8] * d[0] + rc[10] * d[1] + rc[11] * d[2];
   const double nt2 = lt1 * lt1 + lt2 * lt2;
   if (ln > 0.0 && nt2 <= (mu * ln) * (mu * ln)) {
     out.l[0] = ln;
