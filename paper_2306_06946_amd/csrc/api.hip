@@ -396,7 +396,8 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     S.d_node_force = B.alloc<double>(m.n);
     ICR_HIP(hipMemsetAsync(S.d_node_force, 0, sizeof(double) * m.n, st));
     S.d_prev_nodes = B.alloc<int>(N);
-    S.prev_nc = 0;
+    S.d_prev_nc = B.alloc<int>(1);
+    ICR_HIP(hipMemsetAsync(S.d_prev_nc, 0, sizeof(int), st));
     S.t = 0;
     S.d_ctx = B.alloc<StepCtx>(1);
     S.d_stamps = B.alloc<unsigned long long>(6 + 4 * kMaxNewton);
@@ -600,8 +601,7 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   // corrective motion and integration (Eq. 20)
   if (!standard) contact_force_solve(s, C.d_f, S.d_sol);             // A^-1 H^T f (last W_H's Z)
   launch_integrate(s);
-  launch_store_forces(s, nc);
-  launch_advance_time(s);
+  launch_store_forces(s, nc);   // and the time advance
   if (standard) launch_fill(s, C.d_WH, 9L * nc * nc, 0.0);           // no W_H in this scheme
   mark(ev, 5);
 }

@@ -1500,12 +1500,29 @@ __global__ void k_zero(long n, double *__restrict__ x) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = 0.0;
 }
 
-__global__ void k_scatter_force(int nc, const int *__restrict__ nodes, const double *__restrict__ f,
-                                double *__restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  int v = nodes[c];
-  for (int a = 0; a < 3; ++a) out[3 * v + a] = f[3 * c + a];
+// Warm start of the next step (one workgroup): clear the forces of the
+// previous step's contact nodes (count and ids on the device), store this
+// step's world-frame forces on their nodes, keep their ids, advance the time.
+__global__ __launch_bounds__(1024) void k_store_forces(int nc, const int *__restrict__ nodes,
+                                                       const double *__restrict__ f, double *__restrict__ node_force,
+                                                       int *__restrict__ prev_nodes, int *__restrict__ prev_nc,
+                                                       StepCtx *__restrict__ ctx) {
+  const int pn = *prev_nc;
+  for (int c = threadIdx.x; c < pn; c += blockDim.x) {
+    const int v = prev_nodes[c];
+    for (int a = 0; a < 3; ++a) node_force[3 * v + a] = 0.0;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int v = nodes[c];
+    for (int a = 0; a < 3; ++a) node_force[3 * v + a] = f[3 * c + a];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) prev_nodes[c] = nodes[c];
+  if (threadIdx.x == 0) {
+    *prev_nc = nc;
+    ctx->t0 = ctx->t0 + ctx->h;
+  }
 }
 
 // p = H q_k with q_k = q_free + h^2 A^-1 J^T lambda (Algorithm 2, steps 4-6).
@@ -1523,21 +1540,8 @@ __global__ void k_set_ctx(StepCtx *ctx, icr_obstacle obs, int set_obs, double t0
   ctx->h = h;
 }
 
-__global__ void k_advance_time(StepCtx *ctx) { ctx->t0 = ctx->t0 + ctx->h; }
-
 __global__ void k_stamp(unsigned long long *ts, int slot) { ts[slot] = wall_clock64(); }
 
-__global__ void k_copy_int(int n, const int *__restrict__ a, int *__restrict__ b) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
-}
-
-__global__ void k_clear_nodes(int nc, const int *__restrict__ nodes, double *__restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  int v = nodes[c];
-  for (int a = 0; a < 3; ++a) out[3 * v + a] = 0.0;
-}
 
 }  // namespace
 
@@ -1636,11 +1640,6 @@ void launch_stamp(icr_scene *s, int slot) {
   ICR_LAUNCH_CHECK();
 }
 
-void launch_advance_time(icr_scene *s) {
-  k_advance_time<<<1, 1, 0, s->stream>>>(s->st.d_ctx);
-  ICR_LAUNCH_CHECK();
-}
-
 void launch_standard_proximity(icr_scene *s, int nc) {
   const double h = s->mesh.h;
   k_std_proximity<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->st.d_qfree, s->st.d_sol, h * h,
@@ -1650,15 +1649,9 @@ void launch_standard_proximity(icr_scene *s, int nc) {
 
 void launch_store_forces(icr_scene *s, int nc) {
   auto &S = s->st;
-  if (S.prev_nc > 0) {
-    k_clear_nodes<<<cdiv(S.prev_nc, 128), 128, 0, s->stream>>>(S.prev_nc, S.d_prev_nodes, S.d_node_force);
-    ICR_LAUNCH_CHECK();
-  }
-  k_scatter_force<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, S.d_node_force);
+  k_store_forces<<<1, 1024, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, S.d_node_force, S.d_prev_nodes,
+                                            S.d_prev_nc, S.d_ctx);
   ICR_LAUNCH_CHECK();
-  k_copy_int<<<cdiv(nc, 256), 256, 0, s->stream>>>(nc, s->con.d_nodes_c, S.d_prev_nodes);
-  ICR_LAUNCH_CHECK();
-  S.prev_nc = nc;
 }
 
 }  // namespace icr

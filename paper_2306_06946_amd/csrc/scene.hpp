@@ -140,7 +140,7 @@ struct State {
   double *d_b = nullptr, *d_dvfree = nullptr, *d_qfree = nullptr, *d_sol = nullptr;
   double *d_node_force = nullptr;   // world-frame force per node from the previous step
   int *d_prev_nodes = nullptr;
-  int prev_nc = 0;
+  int *d_prev_nc = nullptr;   // contacts of the previous step (device: a captured step graph reads it)
   double t = 0;
 };
 
@@ -212,7 +212,6 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
 void launch_select_contacts(icr_scene *s, int nc);
 void launch_directions(icr_scene *s, int nc, bool first);
 void launch_set_ctx(icr_scene *s, const icr_obstacle *obs, const double *t0);
-void launch_advance_time(icr_scene *s);
 void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 4096;
@@ -230,6 +229,8 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
 void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
 void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
                       double *p);
+// World-frame forces of this step's contacts become the next step's warm
+// start (previous contacts cleared), then the step time advances.
 void launch_store_forces(icr_scene *s, int nc);
 void launch_standard_proximity(icr_scene *s, int nc);
 

@@ -326,6 +326,45 @@ def test_step_medium_matches_oracle():
     _compare_step(sim, s, sc, 2, "medium")
 
 
+def test_warm_start_after_contacts_leave_and_return():
+    """Obstacle under the left half, then the right half, then the left half
+    again: the left contacts leave and come back, and must come back with no
+    stored force (R16).  Graph replay (captured on the scene's first step),
+    eager launches and the oracle agree step by step."""
+    icr = _icr()
+    sc = make_scene("medium", 0)
+    sc["max_sweeps"] = 100
+    width = (sc["grid"][0] - 1) * sc["spacing"]
+    base = dict(sc["obstacle"], vel=np.zeros(3))
+    left = dict(base, c0=np.asarray(base["c0"]) - np.array([0.3 * width, 0.0, 0.0]))
+    right = dict(base, c0=np.asarray(base["c0"]) + np.array([0.3 * width, 0.0, 0.0]))
+    seq = [left, right, left, right]
+    nc = sc["n_contacts"]
+    runs = []
+    for graph in (False, True):
+        s = icr.scene_from_dict(sc)
+        sim = O.Simulation(sc) if not graph else None
+        out = []
+        for k, ob in enumerate(seq):
+            _say(f"[gpu] warm start, graph={graph}, step {k}")
+            s.step(ob, nc, sc["n_newton"], sc["max_sweeps"], sc["tol"], sc["j_inner"], graph=graph)
+            res = s.step_results(nc)
+            q, v, _ = s.get_state()
+            out.append((res["node_ids"].cpu(), res["lam"].cpu(), q.cpu(), v.cpu()))
+            if sim is not None:
+                sim.scene["obstacle"] = ob
+                ref = sim.step()
+                assert np.array_equal(res["node_ids"].cpu().numpy(), ref["nodes_c"])
+                assert _rel(q.cpu().numpy() - sim.q_rest, ref["q"] - sim.q_rest) <= 1e-10
+        ids = [set(o[0].numpy().tolist()) for o in out]
+        assert len((ids[0] & ids[2]) - ids[1]) > 0   # some contacts left and came back
+        runs.append(out)
+        s.close()
+    for a, b in zip(runs[0], runs[1]):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_overlap_off_equals_on(medium, graph):
     """The second-stream overlap of the W_H products changes no bit (eager and
