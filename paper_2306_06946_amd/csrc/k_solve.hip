@@ -278,25 +278,6 @@ __global__ __launch_bounds__(256) void k_wh_unpermute(int nc, const int *__restr
 
 // ---- single RHS -------------------------------------------------------------
 
-__global__ void k_fwd1_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                const int *__restrict__ child, const int *__restrict__ invmap_off,
-                                const int *__restrict__ invmap, const int *__restrict__ perm,
-                                const double *__restrict__ b, double *__restrict__ x1) {
-  const SupDev S = sup[level_sup[blockIdx.y]];
-  const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < f; i += gridDim.x * blockDim.x) {
-    double v = (i < n3) ? b[3 * perm[S.col0 + i / 3] + i % 3] : 0.0;
-    for (int c = 0; c < S.nchild; ++c) {
-      const int ii = invmap[invmap_off[S.child_off + c] + i / 3];
-      if (ii >= 0) {
-        const SupDev C = sup[child[S.child_off + c]];
-        v += x1[C.x1_off + 3 * C.ncol + 3 * ii + i % 3];
-      }
-    }
-    x1[S.x1_off + i] = v;
-  }
-}
-
 // Single-RHS products, 1024 threads per block.  Column-major A times x: lane
 // = row (64 rows, coalesced), wave = k-phase (16 phases), four independent
 // accumulators per thread, phases summed in a fixed order through LDS.
@@ -332,25 +313,60 @@ __device__ inline double phase_sum(double v, double (*part)[GV_R + 1]) {
   return t;
 }
 
-// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]
+// Entry i of the single-RHS front of supernode S (Eq. 12 forward half): the
+// permuted right-hand side on its own columns plus the children's update
+// entries mapped onto row i (extend-add), children in order.
+__device__ inline double fwd1_front(const SupDev &S, int i, const SupDev *__restrict__ sup,
+                                    const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                    const int *__restrict__ invmap, const int *__restrict__ perm,
+                                    const double *__restrict__ b, const double *__restrict__ x1) {
+  const int n3 = 3 * S.ncol;
+  double v = (i < n3) ? b[3 * perm[S.col0 + i / 3] + i % 3] : 0.0;
+  for (int c = 0; c < S.nchild; ++c) {
+    const int ii = invmap[invmap_off[S.child_off + c] + i / 3];
+    if (ii >= 0) {
+      const SupDev C = sup[child[S.child_off + c]];
+      v += x1[C.x1_off + 3 * C.ncol + 3 * ii + i % 3];
+    }
+  }
+  return v;
+}
+
+// y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]; the front entries it needs
+// are assembled on the fly into LDS (GV_X at a time)
 __global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                    const int *__restrict__ child,
+                                                    const int *__restrict__ invmap_off, const int *__restrict__ invmap,
+                                                    const int *__restrict__ perm, const double *__restrict__ b,
                                                     const double *__restrict__ linv, const double *__restrict__ x1,
                                                     double *__restrict__ y) {
   __shared__ double part[GV_P][GV_R + 1];
+  __shared__ double xs[GV_X];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
   const int i0 = GV_R * blockIdx.x;
   if (i0 >= n3) return;   // uniform over the block
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
-  const double v = gemv_part(linv + S.linv_off, n3, x1 + S.x1_off, i, n3, 0, min(n3, i0 + GV_R), ph);
+  const int kend = min(n3, i0 + GV_R);
+  double v = 0.0;
+  for (int kk = 0; kk < kend; kk += GV_X) {
+    const int kn = min(kend, kk + GV_X);
+    __syncthreads();
+    for (int k = kk + threadIdx.x; k < kn; k += 1024)
+      xs[k - kk] = fwd1_front(S, k, sup, child, invmap_off, invmap, perm, b, x1);
+    __syncthreads();
+    v += gemv_part(linv + S.linv_off, n3, xs - kk, i, n3, kk, kn, ph);
+  }
   const double t = phase_sum(v, part);
   if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
 }
 
-// x1_s[n_s + i] -= sum_k L21(i, k) y_s[k]
+// x1_s[n_s + i] = front(n_s + i) - sum_k L21(i, k) y_s[k]
 __global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                   const double *__restrict__ front, const double *__restrict__ y,
-                                                   double *__restrict__ x1) {
+                                                   const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                                   const int *__restrict__ invmap, const int *__restrict__ perm,
+                                                   const double *__restrict__ b, const double *__restrict__ front,
+                                                   const double *__restrict__ y, double *__restrict__ x1) {
   __shared__ double part[GV_P][GV_R + 1];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
@@ -359,7 +375,8 @@ __global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ su
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
   const double v = gemv_part(front + S.front_off + n3, f, y + 3 * S.col0, i, b3, 0, n3, ph);
   const double t = phase_sum(v, part);
-  if (ph == 0 && i < b3) x1[S.x1_off + n3 + i] -= t;
+  if (ph == 0 && i < b3)
+    x1[S.x1_off + n3 + i] = fwd1_front(S, n3 + i, sup, child, invmap_off, invmap, perm, b, x1) - t;
 }
 
 // y_s[j] -= sum_i L21(i, j) x[below row i]
@@ -510,13 +527,13 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
     const LevelInfo &L = F.levels[l];
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
-    k_fwd1_assemble<<<dim3(cdiv(L.max_f3, 256), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
-                                                                          F.d_invmap, F.d_perm, b, F.d_x1);
-    ICR_LAUNCH_CHECK();
-    k_fwd1_diag<<<dim3(cdiv(L.max_n3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_linv, F.d_x1, y);
+    k_fwd1_diag<<<dim3(cdiv(L.max_n3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
+                                                                       F.d_invmap, F.d_perm, b, F.d_linv, F.d_x1, y);
     ICR_LAUNCH_CHECK();
     if (L.max_b3 > 0) {
-      k_fwd1_off<<<dim3(cdiv(L.max_b3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_front, y, F.d_x1);
+      k_fwd1_off<<<dim3(cdiv(L.max_b3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
+                                                                        F.d_invmap, F.d_perm, b, F.d_front, y,
+                                                                        F.d_x1);
       ICR_LAUNCH_CHECK();
     }
   }
