@@ -588,12 +588,12 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
     launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
                C.d_sweeps + k, C.d_eps + k, C.pgs);
     mark(kev, 4 * k + 2);
-    launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
     if (standard) {
+      launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
       contact_force_solve(s, C.d_lam, S.d_sol);                      // A^-1 J_k^T lambda_k
       launch_standard_proximity(s, nc);                               // p_k = H (q_free + h^2 sol)
     } else {
-      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+      launch_world_force_proximity(st, nc, C.d_C, C.d_lam, C.d_f, C.d_WH, C.d_pfree, h, C.d_p);  // Eq. 31
     }
     mark(kev, 4 * k + 3);
   }

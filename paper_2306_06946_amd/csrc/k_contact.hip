@@ -534,29 +534,44 @@ __device__ double block_min(double v, double *red) {
 // the dense product.  Every block compacts the non-zero contacts (ascending,
 // SG_CHUNK at a time) into LDS, then its waves split that list over the same
 // 64 outputs and add their partial sums in a fixed order.
+// World-frame force of contact c from its frame rows and force components.
+__device__ inline double world_force(const double *__restrict__ C, const double *__restrict__ lam, long c, int a) {
+  const double *R = C + 9 * c;
+  return R[a] * lam[3 * c] + R[3 + a] * lam[3 * c + 1] + R[6 + a] * lam[3 * c + 2];
+}
+
 constexpr int SG_NT = 512;
 constexpr int SG_NW = SG_NT / 64;
-constexpr int SG_CHUNK = 4096;
+constexpr int SG_CHUNK = 2048;
 __device__ inline bool block_nonzero(const double *__restrict__ v, long c) {
   return (v[3 * c] != 0.0) | (v[3 * c + 1] != 0.0) | (v[3 * c + 2] != 0.0);
 }
+// With C given, the vector is the world-frame force f = C^T lambda of the
+// contacts (v is then ignored): every block forms the entries it needs from
+// C and lambda, and block 0 also writes f for all contacts to fout.
 __global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double *__restrict__ M,
                                                            const double *__restrict__ x0,
                                                            const double *__restrict__ v, double h2,
-                                                           double *__restrict__ y) {
+                                                           double *__restrict__ y, const double *__restrict__ C,
+                                                           const double *__restrict__ lam,
+                                                           double *__restrict__ fout) {
   __shared__ int list[SG_CHUNK];
+  __shared__ double fl[3 * SG_CHUNK];   // world forces of the listed contacts (with C)
   __shared__ int wsum[SG_NW];
   __shared__ double part[SG_NW][64];
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const long m = 3L * nc;
   const long i = (long)blockIdx.x * 64 + ln;
+  const double *nzv = C ? lam : v;   // same zero blocks: C is a rotation
+  if (C && blockIdx.x == 0)
+    for (long e = tid; e < m; e += SG_NT) fout[e] = world_force(C, lam, e / 3, (int)(e % 3));
   double s = 0.0;
   for (int c0 = 0; c0 < nc; c0 += SG_CHUNK) {
     const int cn = min(SG_CHUNK, nc - c0);
     const int per = (cn + SG_NT - 1) / SG_NT;   // contiguous contacts per thread
     const int lo = c0 + min(cn, tid * per), hi = c0 + min(cn, (tid + 1) * per);
     int cnt = 0;
-    for (int c = lo; c < hi; ++c) cnt += block_nonzero(v, c) ? 1 : 0;
+    for (int c = lo; c < hi; ++c) cnt += block_nonzero(nzv, c) ? 1 : 0;
     int incl = cnt;   // inclusive scan over the wave, then over the waves
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(incl, o, 64);
@@ -570,15 +585,20 @@ __global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double 
       total += wsum[w];
     }
     for (int c = lo; c < hi; ++c)
-      if (block_nonzero(v, c)) list[pos++] = c;
+      if (block_nonzero(nzv, c)) list[pos++] = c;
     __syncthreads();
+    if (C) {
+      for (int e = tid; e < 3 * total; e += SG_NT) fl[e] = world_force(C, lam, list[e / 3], e % 3);
+      __syncthreads();
+    }
     if (i < m) {
 #pragma unroll 4
       for (int q = wv; q < total; q += SG_NW) {
         const long r = 3L * list[q];
-        s = fma(M[r * m + i], v[r], s);
-        s = fma(M[(r + 1) * m + i], v[r + 1], s);
-        s = fma(M[(r + 2) * m + i], v[r + 2], s);
+        const double v0 = C ? fl[3 * q] : v[r], v1 = C ? fl[3 * q + 1] : v[r + 1], v2 = C ? fl[3 * q + 2] : v[r + 2];
+        s = fma(M[r * m + i], v0, s);
+        s = fma(M[(r + 1) * m + i], v1, s);
+        s = fma(M[(r + 2) * m + i], v2, s);
       }
     }
     __syncthreads();   // list and wsum are rewritten by the next chunk
@@ -1489,11 +1509,9 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
 
 __global__ void k_world_force(int nc, const double *__restrict__ C, const double *__restrict__ lam,
                               double *__restrict__ f) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  const double *R = C + 9L * c;
-  for (int a = 0; a < 3; ++a)
-    f[3 * c + a] = R[a] * lam[3 * c] + R[3 + a] * lam[3 * c + 1] + R[6 + a] * lam[3 * c + 2];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * nc) return;
+  f[e] = world_force(C, lam, e / 3, e % 3);
 }
 
 __global__ void k_zero(long n, double *__restrict__ x) {
@@ -1571,7 +1589,7 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
                 const PgsWork &wk) {
   const int m = 3 * nc;
   // g0 = d + W~ lambda over the contacts with a warm-start force
-  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g);
+  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g, nullptr, nullptr, nullptr);
   ICR_LAUNCH_CHECK();
   k_pgs_set<<<1, 1024, 0, st>>>(nc, W, wk.g, lam, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn);
   ICR_LAUNCH_CHECK();
@@ -1616,7 +1634,15 @@ void pgs_prepare() {
 }
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {
-  k_world_force<<<cdiv(nc, 128), 128, 0, st>>>(nc, Cm, lam, f);
+  k_world_force<<<cdiv(3 * nc, 256), 256, 0, st>>>(nc, Cm, lam, f);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_world_force_proximity(hipStream_t st, int nc, const double *Cm, const double *lam, double *f,
+                                  const double *WH, const double *p_free, double h, double *p) {
+  const int m = 3 * nc;
+  // f = C^T lambda and p = p_free + h^2 W_H f in one launch
+  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, nullptr, h * h, p, Cm, lam, f);
   ICR_LAUNCH_CHECK();
 }
 
@@ -1624,7 +1650,7 @@ void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_
                       double *p) {
   const int m = 3 * nc;
   // p = p_free + h^2 W_H f; f is zero at separated contacts
-  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, f, h * h, p);
+  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, f, h * h, p, nullptr, nullptr, nullptr);
   ICR_LAUNCH_CHECK();
 }
 

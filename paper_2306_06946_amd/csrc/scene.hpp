@@ -227,6 +227,9 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
                 double *eps_dev, const PgsWork &wk);
 void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
+// f = C^T lambda and the proximity update p = p_free + h^2 W_H f (Eq. 31) in one launch
+void launch_world_force_proximity(hipStream_t st, int nc, const double *Cm, const double *lam, double *f,
+                                  const double *WH, const double *p_free, double h, double *p);
 void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
                       double *p);
 // World-frame forces of this step's contacts become the next step's warm
