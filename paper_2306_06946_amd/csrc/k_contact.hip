@@ -1141,28 +1141,38 @@ __device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds
 }
 
 // The active set of the first sweep, its compact couplings and records are
-// prepared by wide kernels before the sequential kernel starts (a set that
+// prepared by a wide kernel before the sequential kernel starts (a set that
 // grows later is rebuilt inside k_pgs_active).
-// k_pgs_set: S = {c : lambda_c != 0 or g0_n(c) < 0} in ascending order,
-// the normal gaps at the set's start and sqrt(W~_nn) of every contact.
-__global__ __launch_bounds__(1024) void k_pgs_set(int nc, const double *__restrict__ W, const double *__restrict__ g0,
-                                                  const double *__restrict__ lam, double h2, int *__restrict__ Sidx,
-                                                  int *__restrict__ nS_out, double *__restrict__ gnSet,
-                                                  double *__restrict__ swn) {
+// k_pgs_gather (any grid): the normal gaps at the set's start and sqrt(W~_nn)
+// of every contact; every block forms the set S = {c : lambda_c != 0 or
+// g0_n(c) < 0} in ascending order (64-contact ballots, window prefix) and
+// block 0 writes S and |S|.  For a set of at most PGS_WAVE_MAX contacts the blocks then
+// write the blocked W~_SS with zero diagonal blocks, the per-contact records
+// and the gaps without the own term, e = g0 - W~_cc lambda_c.
+__global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__restrict__ W,
+                                                    const double *__restrict__ g0, const double *__restrict__ lam,
+                                                    const double *__restrict__ mu, double h2,
+                                                    int *__restrict__ Sidx_out, int *__restrict__ nS_out,
+                                                    double *__restrict__ gnSet, double *__restrict__ swn,
+                                                    double *__restrict__ Wss, double *__restrict__ rec,
+                                                    double *__restrict__ gS) {
+  __shared__ int Sidx[PGS_MAX_NC];
   __shared__ int wcount[PGS_MAX_NC / 64 + 1];
+  __shared__ int nS_s;
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int nwin = (nc + 63) / 64;
+  const long stride = (long)gridDim.x * blockDim.x, t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long c = t0; c < nc; c += stride) {
+    gnSet[c] = g0[3 * c];
+    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
+  }
   auto in_set = [&](int c) {
     return c < nc && (lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0 || g0[3 * c] < 0.0);
   };
-  for (int w = wv; w < nwin; w += 16) {
+  for (int w = wv; w < nwin; w += 4) {
     const unsigned long long bal = __ballot(in_set(64 * w + ln));
     if (ln == 0) wcount[w] = __popcll(bal);
-  }
-  for (int c = tid; c < nc; c += 1024) {
-    gnSet[c] = g0[3 * c];
-    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
   }
   __syncthreads();
   if (tid == 0) {
@@ -1172,30 +1182,23 @@ __global__ __launch_bounds__(1024) void k_pgs_set(int nc, const double *__restri
       wcount[w] = acc;
       acc += t;
     }
-    *nS_out = acc;
+    nS_s = acc;
   }
   __syncthreads();
-  for (int w = wv; w < nwin; w += 16) {
+  for (int w = wv; w < nwin; w += 4) {
     const int c = 64 * w + ln;
     const bool in = in_set(c);
     const unsigned long long bal = __ballot(in);
     if (in) Sidx[wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
   }
-}
-
-// k_pgs_gather (any grid): for a set of at most PGS_WAVE_MAX contacts, the
-// blocked W~_SS with zero diagonal blocks, the per-contact records and the
-// gaps without the own term, e = g0 - W~_cc lambda_c.
-__global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__restrict__ W,
-                                                    const double *__restrict__ g0, const double *__restrict__ lam,
-                                                    const double *__restrict__ mu, double h2,
-                                                    const int *__restrict__ Sidx, const int *__restrict__ nS_in,
-                                                    double *__restrict__ Wss, double *__restrict__ rec,
-                                                    double *__restrict__ gS) {
-  const int nS = *nS_in;
+  __syncthreads();
+  const int nS = nS_s;
+  if (blockIdx.x == 0) {
+    for (int q = tid; q < nS; q += 256) Sidx_out[q] = Sidx[q];
+    if (tid == 0) *nS_out = nS;
+  }
   if (nS == 0 || nS > PGS_WAVE_MAX) return;
-  const int m = 3 * nc, nsp = pgs_wave_pad(nS);
-  const long stride = (long)gridDim.x * blockDim.x, t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsp = pgs_wave_pad(nS);
   const long nel = (long)nS * nsp * PGS_BLK;
   for (long e = t0; e < nel; e += stride) {
     const int j = (int)(e % PGS_BLK);
@@ -1242,7 +1245,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
     L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
   }
-  const int npre = *preN;   // set prepared by k_pgs_set / k_pgs_gather
+  const int npre = *preN;   // set prepared by k_pgs_gather
   if (tid == 0) {
     L.stop = 0;
     L.zflag = 0;
@@ -1591,9 +1594,8 @@ void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const 
   // g0 = d + W~ lambda over the contacts with a warm-start force
   k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g, nullptr, nullptr, nullptr);
   ICR_LAUNCH_CHECK();
-  k_pgs_set<<<1, 1024, 0, st>>>(nc, W, wk.g, lam, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn);
-  ICR_LAUNCH_CHECK();
-  k_pgs_gather<<<512, 256, 0, st>>>(nc, W, wk.g, lam, mu, h * h, wk.Sidx, wk.nS, wk.Wss, wk.rec, wk.gS);
+  k_pgs_gather<<<512, 256, 0, st>>>(nc, W, wk.g, lam, mu, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn, wk.Wss, wk.rec,
+                                    wk.gS);
   ICR_LAUNCH_CHECK();
   k_pgs_active<<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
                                                 sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl, wk.Sidx,
