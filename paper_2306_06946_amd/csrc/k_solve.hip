@@ -91,37 +91,161 @@ __device__ inline int lower_bound_i(const int *a, int n, int x) {
   return lo;
 }
 
-__global__ void k_ranges(int nsup, int nc, const SupDev *__restrict__ sup, const int *__restrict__ keys,
-                         int *__restrict__ lohi) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsup) return;
-  int lo = lower_bound_i(keys, nc, sup[s].first_desc);
-  int own = lower_bound_i(keys, nc, s);
-  int hi = lower_bound_i(keys, nc, s + 1);
-  if (3 * (hi - lo) > sup[s].rmax) own = hi = lo;   // only reachable with duplicate ids (flagged)
-  lohi[3 * s + 0] = lo;
-  lohi[3 * s + 1] = own;
-  lohi[3 * s + 2] = hi;
+constexpr int RHS_T = AccS::T;   // tile order of the multi-RHS products
+enum { RT_ASM = 0, RT_DIAG = 1, RT_SYRK = 2, RT_OFF = 3, RHS_KINDS = 4 };
+
+// Tasks of the multi-RHS products of one supernode with r RHS columns, n3
+// DOF columns and b3 below rows (tiles of RHS_T): assemble (4 columns per
+// task), L_ss^{-1} X (row tile x column tile), Z^T Z (lower column-tile
+// pairs), L_21 Z (below-row tile x column tile).  The host evaluates the same
+// counts at r = rmax for the list capacities.
+__host__ __device__ inline void rhs_task_counts(int r, int n3, int b3, int c[RHS_KINDS]) {
+  if (r <= 0) {
+    c[RT_ASM] = c[RT_DIAG] = c[RT_SYRK] = c[RT_OFF] = 0;
+    return;
+  }
+  const int tr = (r + RHS_T - 1) / RHS_T;
+  c[RT_ASM] = (r + 3) / 4;
+  c[RT_DIAG] = ((n3 + RHS_T - 1) / RHS_T) * tr;
+  c[RT_SYRK] = tr * (tr + 1) / 2;
+  c[RT_OFF] = ((b3 + RHS_T - 1) / RHS_T) * tr;
+}
+
+// k_rhs_plan (one block per height level): the contact range [lo, own, hi)
+// of every supernode of the level (contacts are sorted by supernode; a range
+// over the supernode's capacity, reachable only with duplicate ids, which are
+// flagged, is emptied), then the level's task lists: one entry (supernode,
+// tile row << 16 | tile column) per tile that has work, in supernode order,
+// and the list lengths.  The products launch one workgroup per entry of the
+// list's capacity; those past its length return after one uniform load (a
+// grid laid out by supernode and static column capacity would have most of
+// its workgroups find no columns, each after three dependent loads).
+constexpr int PLAN_NT = 1024;     // threads
+constexpr int PLAN_CHUNK = 256;   // supernodes per chunk (levels with more take several)
+constexpr int PLAN_KEYS = 4096;
+__global__ __launch_bounds__(PLAN_NT) void k_rhs_plan(int nc, const int *__restrict__ level_first,
+                                                      const int *__restrict__ level_sup,
+                                                      const SupDev *__restrict__ sup, const int *__restrict__ keys,
+                                                      int *__restrict__ lohi, const int *__restrict__ task_off,
+                                                      int *__restrict__ task_cnt, int2 *__restrict__ tasks) {
+  __shared__ int pre[RHS_KINDS][PLAN_CHUNK];
+  __shared__ int wsum[RHS_KINDS][PLAN_CHUNK / 64];
+  __shared__ int wtot[RHS_KINDS];
+  __shared__ int ssup[PLAN_CHUNK], sn3t[PLAN_CHUNK], sb3t[PLAN_CHUNK];
+  __shared__ int skeys[PLAN_KEYS];
+  const int l = blockIdx.x, tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  const int first = level_first[l], last = level_first[l + 1];
+  // the sorted keys are searched in LDS when they fit
+  const int *kp = keys;
+  if (nc <= PLAN_KEYS) {
+    for (int i = tid; i < nc; i += PLAN_NT) skeys[i] = keys[i];
+    __syncthreads();
+    kp = skeys;
+  }
+  int run[RHS_KINDS] = {0, 0, 0, 0};
+  for (int base = first; base < last; base += PLAN_CHUNK) {
+    // ranges, task counts and their exclusive prefix over the chunk (waves
+    // 0 .. PLAN_CHUNK / 64 - 1)
+    const int q = base + tid;
+    int c[RHS_KINDS] = {0, 0, 0, 0};
+    if (tid < PLAN_CHUNK && q < last) {
+      const int sn = level_sup[q];
+      const SupDev &S = sup[sn];
+      const int lo = lower_bound_i(kp, nc, S.first_desc);
+      int own = lower_bound_i(kp, nc, sn);
+      int hi = lower_bound_i(kp, nc, sn + 1);
+      if (3 * (hi - lo) > S.rmax) own = hi = lo;
+      lohi[3 * sn + 0] = lo;
+      lohi[3 * sn + 1] = own;
+      lohi[3 * sn + 2] = hi;
+      const int n3 = 3 * S.ncol, b3 = 3 * S.nb;
+      rhs_task_counts(3 * (hi - lo), n3, b3, c);
+      ssup[tid] = sn;
+      sn3t[tid] = (n3 + RHS_T - 1) / RHS_T;
+      sb3t[tid] = (b3 + RHS_T - 1) / RHS_T;
+    }
+    int v[RHS_KINDS];
+#pragma unroll
+    for (int k = 0; k < RHS_KINDS; ++k) v[k] = c[k];
+    if (tid < PLAN_CHUNK) {
+      for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < RHS_KINDS; ++k) {
+          const int t = __shfl_up(v[k], o, 64);
+          if (ln >= o) v[k] += t;
+        }
+      }
+      if (ln == 63) {
+#pragma unroll
+        for (int k = 0; k < RHS_KINDS; ++k) wsum[k][wv] = v[k];
+      }
+    }
+    __syncthreads();
+    if (tid < RHS_KINDS) {
+      int acc = 0;
+      for (int w = 0; w < PLAN_CHUNK / 64; ++w) {
+        const int t = wsum[tid][w];
+        wsum[tid][w] = acc;
+        acc += t;
+      }
+      wtot[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < PLAN_CHUNK) {
+#pragma unroll
+      for (int k = 0; k < RHS_KINDS; ++k) pre[k][tid] = wsum[k][wv] + v[k] - c[k];
+    }
+    __syncthreads();
+    // the chunk's tasks, all threads
+    const int nq = min(PLAN_CHUNK, last - base);
+    for (int k = 0; k < RHS_KINDS; ++k) {
+      const int tot = wtot[k];
+      int2 *out = tasks + task_off[RHS_KINDS * l + k] + run[k];
+      for (int t = tid; t < tot; t += PLAN_NT) {
+        int a = 0, b = nq;   // first q with pre > t; the task's supernode is the one before
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (pre[k][mid] <= t)
+            a = mid + 1;
+          else
+            b = mid;
+        }
+        const int qq = a - 1, u = t - pre[k][qq];
+        int ti = u, tj = 0;
+        if (k == RT_DIAG) {
+          ti = u % sn3t[qq];
+          tj = u / sn3t[qq];
+        } else if (k == RT_SYRK) {
+          tri_index(u, ti, tj);
+        } else if (k == RT_OFF) {
+          ti = u % sb3t[qq];
+          tj = u / sb3t[qq];
+        }
+        out[t] = make_int2(ssup[qq], (ti << 16) | tj);
+      }
+      run[k] += tot;
+    }
+    __syncthreads();
+  }
+  if (tid < RHS_KINDS) task_cnt[RHS_KINDS * l + tid] = run[tid];
 }
 
 // ---- multi-RHS forward ------------------------------------------------------
 
-// X_s column by column (one wave per column, 4 columns per block): a column
+// X_s column by column (one wave per column, 4 columns per task): a column
 // of an own contact is a unit vector of H^T (or a column of J^T = H^T C^T
 // when frames are given); a column of a contact below a child is the child's
 // below-row part extended into the front rows (extend-add through invmap).
 // Everything that identifies the column is uniform over the wave.
-__global__ __launch_bounds__(256) void k_rhs_assemble(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                      const int *__restrict__ child, const int *__restrict__ invmap_off,
-                                                      const int *__restrict__ invmap, const int *__restrict__ lohi,
-                                                      const int *__restrict__ order, const int *__restrict__ node_ids,
-                                                      const int *__restrict__ iperm, const double *__restrict__ frames,
-                                                      double *__restrict__ X) {
-  const int s = level_sup[blockIdx.y];
+__device__ inline void rhs_assemble_column(const SupDev *__restrict__ sup, int s, int jc, int l,
+                                           const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                           const int *__restrict__ invmap, const int *__restrict__ lohi,
+                                           const int *__restrict__ order, const int *__restrict__ node_ids,
+                                           const int *__restrict__ iperm, const double *__restrict__ frames,
+                                           double *__restrict__ X) {
   const SupDev S = sup[s];
   const int lo = lohi[3 * s], own = lohi[3 * s + 1], hi = lohi[3 * s + 2];
   const int r = 3 * (hi - lo);
-  const int jc = 4 * blockIdx.x + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (jc >= r) return;
   const int f = 3 * (S.ncol + S.nb);
   double *Xc = X + S.x_off + (long)jc * f;
@@ -162,71 +286,94 @@ __global__ __launch_bounds__(256) void k_rhs_assemble(const SupDev *__restrict__
   }
 }
 
-// Z_s = L_ss^{-1} X_s[:n_s]; grid (row tile, col tile, supernode)
+// The product kernels take task blockIdx.x of their level's list; the grid is
+// the list's capacity and the workgroups past its length return after one
+// uniform load.
+__global__ __launch_bounds__(256) void k_rhs_assemble(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
+                                                      const int *__restrict__ ntask, const int *__restrict__ child,
+                                                      const int *__restrict__ invmap_off,
+                                                      const int *__restrict__ invmap, const int *__restrict__ lohi,
+                                                      const int *__restrict__ order, const int *__restrict__ node_ids,
+                                                      const int *__restrict__ iperm, const double *__restrict__ frames,
+                                                      double *__restrict__ X) {
+  if ((int)blockIdx.x >= *ntask) return;
+  const int2 tk = tasks[blockIdx.x];
+  rhs_assemble_column(sup, tk.x, 4 * (tk.y >> 16) + (threadIdx.x >> 6), threadIdx.x & 63, child, invmap_off, invmap,
+                      lohi, order, node_ids, iperm, frames, X);
+}
+
+// Z_s = L_ss^{-1} X_s[:n_s], one 64x64 tile per task
 template <class Ac>
-__global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                  const int *__restrict__ lohi, const double *__restrict__ linv,
-                                                  const double *__restrict__ X, double *__restrict__ Z) {
+__global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
+                                                  const int *__restrict__ ntask, const int *__restrict__ lohi,
+                                                  const double *__restrict__ linv, const double *__restrict__ X,
+                                                  double *__restrict__ Z) {
   constexpr int T = Ac::T;
   __shared__ double lds[Ac::LDS];
-  const int s = level_sup[blockIdx.z];
+  if ((int)blockIdx.x >= *ntask) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int s = tk.x;
   const SupDev S = sup[s];
   const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
   const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
-  const int i0 = T * blockIdx.x, j0 = T * blockIdx.y;
+  const int i0 = T * (tk.y >> 16), j0 = T * (tk.y & 0xffff);
   if (i0 >= n3 || j0 >= r) return;
   const int M = min(T, n3 - i0), N = min(T, r - j0);
   const int kend = min(n3, i0 + T);
   Ac acc;
   acc.zero();
-  acc.template acc<true, false>(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend, lds);
+  acc.template acc<true, false>(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend,
+                                lds);
   double *Zs = Z + S.z_off;
   acc.for_each([&](int i, int j, double v) {
     if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = v;
   });
 }
 
-// X_s[n_s:] -= L_21 Z_s
+// X_s[n_s:] -= L_21 Z_s, one tile per task
 template <class Ac>
-__global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                 const int *__restrict__ lohi, const double *__restrict__ front,
-                                                 const double *__restrict__ Z, double *__restrict__ X) {
+__global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
+                                                 const int *__restrict__ ntask, const int *__restrict__ lohi,
+                                                 const double *__restrict__ front, const double *__restrict__ Z,
+                                                 double *__restrict__ X) {
   constexpr int T = Ac::T;
   __shared__ double lds[Ac::LDS];
-  const int s = level_sup[blockIdx.z];
+  if ((int)blockIdx.x >= *ntask) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int s = tk.x;
   const SupDev S = sup[s];
   const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int i0 = T * blockIdx.x, j0 = T * blockIdx.y;
+  const int i0 = T * (tk.y >> 16), j0 = T * (tk.y & 0xffff);
   if (i0 >= b3 || j0 >= r) return;
   const int M = min(T, b3 - i0), N = min(T, r - j0);
   Ac acc;
   acc.zero();
-  acc.template acc<true, false>(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0, n3,
-                               lds);
+  acc.template acc<true, false>(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0,
+                                n3, lds);
   double *Xs = X + S.x_off;
   acc.for_each([&](int i, int j, double v) {
     if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= v;
   });
 }
 
-// Wp[3lo + i][3lo + j] += sum_k Z(k, i) Z(k, j), lower tiles of the r x r block
+// Wp[3lo + i][3lo + j] += sum_k Z(k, i) Z(k, j), one lower tile of the r x r
+// block per task
 template <class Ac>
-__global__ __launch_bounds__(256) void k_rhs_syrk(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                  const int *__restrict__ lohi, const double *__restrict__ Z, int m,
-                                                  double *__restrict__ Wp) {
+__global__ __launch_bounds__(256) void k_rhs_syrk(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
+                                                  const int *__restrict__ ntask, const int *__restrict__ lohi,
+                                                  const double *__restrict__ Z, int m, double *__restrict__ Wp) {
   constexpr int T = Ac::T;
   __shared__ double lds[Ac::LDS];
-  const int s = level_sup[blockIdx.y];
+  if ((int)blockIdx.x >= *ntask) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int s = tk.x;
   const SupDev S = sup[s];
   const int lo = lohi[3 * s];
   const int r = 3 * (lohi[3 * s + 2] - lo);
-  const int nt = (r + T - 1) / T;
-  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
-  int I, J;
-  tri_index(blockIdx.x, I, J);
+  const int i0 = T * (tk.y >> 16), j0 = T * (tk.y & 0xffff);
+  if (i0 >= r || j0 > i0) return;
   const int n3 = 3 * S.ncol;
-  const int i0 = T * I, j0 = T * J;
   const int M = min(T, r - i0), N = min(T, r - j0);
   const double *Zs = Z + S.z_off;
   Ac acc;
@@ -580,6 +727,38 @@ void ensure_rhs_capacity(icr_scene *s, int nc) {
   }
   F.d_X = F.rhs_arena.alloc<double>(xo);
   F.d_Z = F.rhs_arena.alloc<double>(zo);
+  {
+    // task-list capacities per (level, kind): the counts at r = rmax
+    const int nlev = (int)F.levels.size();
+    F.rhs_cap.assign(RHS_KINDS * nlev, 0);
+    F.rhs_off.assign(RHS_KINDS * nlev, 0);
+    std::vector<int> level_first(nlev + 1, 0);
+    long long tot = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const LevelInfo &L = F.levels[l];
+      level_first[l] = L.first;
+      level_first[l + 1] = L.first + L.count;
+      for (int q = 0; q < L.count; ++q) {
+        const SupDev &d = F.sup[F.sym.level_sup[L.first + q]];
+        int c[RHS_KINDS];
+        rhs_task_counts(d.rmax, 3 * d.ncol, 3 * d.nb, c);
+        for (int k = 0; k < RHS_KINDS; ++k) F.rhs_cap[RHS_KINDS * l + k] += c[k];
+      }
+      for (int k = 0; k < RHS_KINDS; ++k) {
+        F.rhs_off[RHS_KINDS * l + k] = (int)tot;
+        tot += F.rhs_cap[RHS_KINDS * l + k];
+      }
+    }
+    if (tot > INT32_MAX) throw std::runtime_error("multi-RHS task lists exceed 2^31 entries");
+    F.d_rhs_tasks = F.rhs_arena.alloc<int2>(std::max<long long>(1, tot));
+    F.d_rhs_off = F.rhs_arena.alloc<int>(F.rhs_off.size());
+    F.d_rhs_cnt = F.rhs_arena.alloc<int>(F.rhs_off.size());
+    F.d_level_first = F.rhs_arena.alloc<int>(level_first.size());
+    ICR_HIP(hipMemcpyAsync(F.d_rhs_off, F.rhs_off.data(), F.rhs_off.size() * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream));
+    ICR_HIP(hipMemcpyAsync(F.d_level_first, level_first.data(), level_first.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s->stream));
+  }
   const long long m = 3LL * nc;
   F.d_Wp = F.rhs_arena.alloc<double>(m * m);
   F.d_keys = F.rhs_arena.alloc<int>(nc);
@@ -624,22 +803,25 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
   k_sort_contacts<<<1, 1024, 0, st>>>(nc, s->mesh.N, nsup, node_ids, F.d_sup_of_node, s->mesh.d_fixed, F.d_keys,
                                       F.d_order, F.d_pos, F.d_cerr);
   ICR_LAUNCH_CHECK();
-  k_ranges<<<cdiv(nsup, 256), 256, 0, st>>>(nsup, nc, F.d_sup, F.d_keys, F.d_lohi);
+  const int nlev = (int)F.levels.size();
+  k_rhs_plan<<<nlev, PLAN_NT, 0, st>>>(nc, F.d_level_first, F.d_level_sup, F.d_sup, F.d_keys, F.d_lohi, F.d_rhs_off,
+                                      F.d_rhs_cnt, F.d_rhs_tasks);
   ICR_LAUNCH_CHECK();
   k_fill<<<1024, 256, 0, st>>>(m * m, 0.0, F.d_Wp);
   ICR_LAUNCH_CHECK();
-  for (size_t l = 0; l < F.levels.size(); ++l) {
-    const LevelInfo &L = F.levels[l];
-    if (!L.count) continue;
-    const int *ls = F.d_level_sup + L.first;
-    int rmax = 0;
-    for (int q = 0; q < L.count; ++q) rmax = std::max(rmax, F.sup[F.sym.level_sup[L.first + q]].rmax);
-    if (rmax == 0) continue;
-    k_rhs_assemble<<<dim3(cdiv(rmax, 4), L.count), 256, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap,
-                                                      F.d_lohi, F.d_order, node_ids, F.d_iperm, frames, F.d_X);
+  // grid of a product launch: its list's capacity (one workgroup per task;
+  // the hardware keeps scheduling workgroups of both streams' launches)
+  auto grid = [&](int l, int k) { return (unsigned)std::max(1, F.rhs_cap[RHS_KINDS * l + k]); };
+  auto list = [&](int l, int k) { return F.d_rhs_tasks + F.rhs_off[RHS_KINDS * l + k]; };
+  auto count = [&](int l, int k) { return F.d_rhs_cnt + RHS_KINDS * l + k; };
+  for (int l = 0; l < nlev; ++l) {
+    if (F.rhs_cap[RHS_KINDS * l + RT_ASM] == 0) continue;   // no supernode of the level can hold a contact column
+    k_rhs_assemble<<<grid(l, RT_ASM), 256, 0, st>>>(F.d_sup, list(l, RT_ASM), count(l, RT_ASM), F.d_child,
+                                                    F.d_invmap_off, F.d_invmap, F.d_lohi, F.d_order, node_ids,
+                                                    F.d_iperm, frames, F.d_X);
     ICR_LAUNCH_CHECK();
-    k_rhs_diag<AccS><<<dim3(cdiv(L.max_n3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
-        F.d_sup, ls, F.d_lohi, F.d_linv, F.d_X, F.d_Z);
+    k_rhs_diag<AccS><<<grid(l, RT_DIAG), 256, 0, st>>>(F.d_sup, list(l, RT_DIAG), count(l, RT_DIAG), F.d_lohi,
+                                                       F.d_linv, F.d_X, F.d_Z);
     ICR_LAUNCH_CHECK();
     // Z of this level is final: its W_H products go to the side stream (they
     // read Z and write Wp only, which nothing on the main stream touches
@@ -650,12 +832,12 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
       ICR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
       sy = s->side;
     }
-    const int ct = cdiv(rmax, AccS::T);
-    k_rhs_syrk<AccS><<<dim3(ct * (ct + 1) / 2, L.count), 256, 0, sy>>>(F.d_sup, ls, F.d_lohi, F.d_Z, (int)m, F.d_Wp);
+    k_rhs_syrk<AccS><<<grid(l, RT_SYRK), 256, 0, sy>>>(F.d_sup, list(l, RT_SYRK), count(l, RT_SYRK), F.d_lohi,
+                                                       F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
-    if (L.max_b3 > 0) {
-      k_rhs_off<AccS><<<dim3(cdiv(L.max_b3, AccS::T), cdiv(rmax, AccS::T), L.count), 256, 0, st>>>(
-          F.d_sup, ls, F.d_lohi, F.d_front, F.d_Z, F.d_X);
+    if (F.rhs_cap[RHS_KINDS * l + RT_OFF] > 0) {
+      k_rhs_off<AccS><<<grid(l, RT_OFF), 256, 0, st>>>(F.d_sup, list(l, RT_OFF), count(l, RT_OFF), F.d_lohi,
+                                                       F.d_front, F.d_Z, F.d_X);
       ICR_LAUNCH_CHECK();
     }
   }

@@ -88,6 +88,11 @@ struct Factor {
   double *d_X = nullptr, *d_Z = nullptr, *d_Wp = nullptr, *d_fpos = nullptr;
   int *d_keys = nullptr, *d_order = nullptr, *d_pos = nullptr, *d_lohi = nullptr, *d_cerr = nullptr;
   // Z f in column chunks: tasks (supernode, first row, first column, partial offset)
+  // multi-RHS product tasks per (height level, kind), built on the device
+  // from the contact ranges: (supernode, tile row << 16 | tile column)
+  int2 *d_rhs_tasks = nullptr;
+  int *d_rhs_off = nullptr, *d_rhs_cnt = nullptr, *d_level_first = nullptr;
+  std::vector<int> rhs_off, rhs_cap;   // first entry and capacity of each list
   int4 *d_zf_tasks = nullptr;
   int n_zf_tasks = 0, n_zf_sum_tasks = 0;   // the first n_zf_sum_tasks tasks have chunk 0
   double *d_zf_part = nullptr;
