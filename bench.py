@@ -61,7 +61,8 @@ def profiled_traffic(kernel):
     The summary (profiles/hbm_traffic_precision.md) holds a line
     `traffic_bytes_per_launch <kernel> <bytes> <source hash>`; the value is
     used only while the kernel source hash matches the current source, else
-    the traffic is unknown (None).
+    the traffic is unknown (None).  The caller applies it only to the
+    workload the counters were taken on.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_precision.md")
@@ -256,6 +257,8 @@ def main():
                     help="replay the captured step graph instead of launching every step eagerly (eager is about "
                          "1%% faster here: the graph replay loses part of the overlap of the W_H products)")
     ap.add_argument("--no-graph", action="store_true", help="eager launches (the default; kept for old commands)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the W_H products of a tree level on the scene's own stream instead of a second one")
     ap.add_argument("--serving", type=int, default=0, metavar="SCENES",
                     help="also run the serving mix: this many independent scenes (node count 500-8000, 10-500 "
                          "contacts) stepped through icr_server; 0 = skip")
@@ -294,6 +297,8 @@ def main():
     log(f"[bench] config={args.config} nodes={len(sc['nodes'])} dofs={3 * len(sc['nodes'])} contacts={nc}")
     stream = torch.cuda.current_stream().cuda_stream
     s = icr.scene_from_dict(sc, stream)
+    if args.no_overlap:
+        s.set_overlap(False)
     info = s.factor_info()
     log(f"[bench] factor: {info['n_supernodes']} supernodes, nnz(L)={info['nnz_L']/1e6:.1f}M, "
         f"{info['factor_flops']/1e9:.1f} GFLOP in {info['factor_ms']:.1f} ms")
@@ -354,7 +359,9 @@ def main():
     roof = dict(cand[dom][1])
     roof["kernel"] = {"pgs": "k_pgs_active", "build_WH": "k_rhs_*", "update_W": "k_update_W"}[dom]
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = profiled_traffic(roof["kernel"])
+    # the counters were taken on the precision workload at the default sweep count
+    roof["traffic"] = (profiled_traffic(roof["kernel"]) if args.config == "precision" and args.sweeps == 30
+                       else None)
     out = {
         "metric": ("time-steps/sec (W_H build + Newton W updates) at "
                    + ("60k" if args.config == "precision" else f"{3 * len(sc['nodes']) / 1000:.1f}k")

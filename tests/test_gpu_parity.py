@@ -469,6 +469,12 @@ def test_full_size_config_sampled_against_oracle(cfg):
     _say(f"[gpu] {cfg}: oracle W_H columns")
     ref = O.build_WH(fac, nodes, asm["n"], columns=cols)
     assert _rel(WH[:, cols], ref) <= 1e-10
+    # every entry at once: W_H x = H A^{-1} H^T x for seeded random x (one
+    # oracle solve each); an error in any block row or column of W_H shows
+    _say(f"[gpu] {cfg}: W_H times random vectors against oracle solves")
+    H = O.mapping_H(nodes, asm["n"])
+    xs = np.random.default_rng(7).standard_normal((m, 2))
+    assert _rel(WH @ xs, H @ fac.solve(H.T @ xs)) <= 1e-10
     lam = res["lam"].cpu().numpy().reshape(-1, 3)
     st = res["status"].cpu().numpy()
     mu = sc["cand_mu"][np.searchsorted(sc["candidates"], nodes)]
