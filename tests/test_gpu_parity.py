@@ -96,6 +96,44 @@ def test_build_WH_unsorted_ids_and_repeat(medium):
     assert _rel(W1.cpu().numpy().reshape(111, 111), ref) <= 1e-10
 
 
+def test_build_WH_at_the_contact_limit():
+    """8192 contacts (the limit of one build), in random order, on the 61k-DOF
+    mesh: more contacts than the task planner keeps in LDS (its range search
+    then reads the sorted keys from global memory) and than the PGS limit.
+    Every entry is checked at once against oracle solves, W_H x = H A^-1 H^T x
+    for seeded random x; 8193 contacts are refused."""
+    sc = make_scene("precision", 0)
+    icr = _icr()
+    _say("[gpu] build_WH precision nc=8192: assemble+factor")
+    s = icr.Scene()
+    s.assemble(sc)
+    s.factor()
+    rng = np.random.default_rng(13)
+    free = np.nonzero(sc["fixed"] == 0)[0]
+    nc = 8192
+    nodes_c = rng.choice(free, size=nc, replace=False).astype(np.int32)
+    m = 3 * nc
+    WH = torch.empty(m * m, dtype=torch.float64, device="cuda")
+    _say("[gpu] build_WH precision nc=8192")
+    s.build_WH(_cuda(nodes_c), WH)
+    torch.cuda.synchronize()
+    got = WH.cpu().numpy().reshape(m, m)
+    del WH
+    assert np.array_equal(got, got.T)
+    _say("[gpu] build_WH precision nc=8192: oracle solves")
+    asm = O.assemble(sc)
+    fac = O.CholeskyFactor(asm["A"])
+    H = O.mapping_H(nodes_c, asm["n"])
+    xs = np.random.default_rng(14).standard_normal((m, 2))
+    assert _rel(got @ xs, H @ fac.solve(H.T @ xs)) <= 1e-10
+    ref = O.build_WH(fac, nodes_c, asm["n"], columns=[0, m - 1])
+    assert _rel(got[:, [0, m - 1]], ref) <= 1e-10
+    # the count is checked before any pointer is used (no 4.8 GB output needed)
+    more = _cuda(rng.choice(free, size=nc + 1, replace=False).astype(np.int32))
+    import ctypes
+    assert s.L.icr_build_WH(s._h, nc + 1, ctypes.c_void_p(more.data_ptr()), None) == icr.E_ARG
+
+
 def test_build_WH_rejects_clamped_node(medium):
     sc, s = medium
     bad = np.array([int(np.nonzero(sc["fixed"])[0][0])], dtype=np.int32)
