@@ -212,8 +212,8 @@ __global__ __launch_bounds__(PLAN_NT) void k_rhs_plan(int nc, const int *__restr
         }
         const int qq = a - 1, u = t - pre[k][qq];
         int ti = u, tj = 0;
-        if (k == RT_DIAG) {
-          ti = u % sn3t[qq];
+        if (k == RT_DIAG) {   // deepest row tiles first (their product runs over k < i0 + 64)
+          ti = sn3t[qq] - 1 - u % sn3t[qq];
           tj = u / sn3t[qq];
         } else if (k == RT_SYRK) {
           tri_index(u, ti, tj);
