@@ -284,7 +284,6 @@ __device__ inline void AccM::acc(const double *A, long ars, long acs, const doub
 // is staged in LDS as [k][i] / [k][j] rows padded to T + 1 doubles (no bank
 // conflicts for either staging order or the MFMA operand reads), the next
 // chunk is prefetched into registers while the MFMAs of the current one run.
-// WB = 4 (128 x 128) halves the operand traffic per flop of the 64 x 64 tile.
 template <int WB, int KC = KT>
 struct AccMT {
   static constexpr int T = 32 * WB;
@@ -373,7 +372,6 @@ struct AccMT {
   }
 };
 typedef AccMT<2, 32> AccS;   // 64 x 64, K-chunk 32
-typedef AccMT<4> AccL;   // 128 x 128
 
 // The tile accumulator used by the dense kernels.
 #ifndef ICR_TILE_MFMA
