@@ -525,7 +525,9 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
     }
     auto &C = s->con;
     C.count = count;
+    // ascending node id: the selection kernel places its contacts in list order
     C.nodes.assign(nodes, nodes + count);
+    std::sort(C.nodes.begin(), C.nodes.end());
     auto &B = s->state_arena;
     s->epoch++;
     C.d_cand = B.upload(C.nodes, s->stream);

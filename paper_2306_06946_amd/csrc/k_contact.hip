@@ -33,8 +33,39 @@ __device__ double signed_distance(const icr_obstacle &o, double t, const double 
   return r0 * o.normal[0] + r1 * o.normal[1] + r2 * o.normal[2];
 }
 
-// Keep the K candidates with smallest (distance, node id) at q_free, then order
-// them by node id; gather mu, p_free = H q_free, p_start = H q, warm start.
+// Exclusive prefix sum of one int per thread over a 1024-thread block.
+__device__ int block_excl_scan_1024(int v, int *wsum) {
+  const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(x, o, 64);
+    if (ln >= o) x += t;
+  }
+  if (ln == 63) wsum[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int t = wsum[w];
+      wsum[w] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  const int r = wsum[wv] + x - v;
+  __syncthreads();
+  return r;
+}
+
+// Keep the K candidates with smallest (distance, node id) at q_free, in
+// ascending node id; gather mu, p_free = H q_free, p_start = H q, warm start.
+// The candidate list is ascending by node id (sorted when it is set).  The
+// K-th smallest distance key T is found by an MSB-first radix select (8 bits
+// per pass, 256-bin histograms in LDS); the contacts are the candidates with
+// key < T and the lowest-id ones with key == T, placed by an exclusive scan
+// of the selection flags in list order.  Thread t holds list entries
+// 4t .. 4t + 3.
+constexpr int SEL_PER = 4;   // 4096 candidates at most
 __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restrict__ cand,
                                                  const double *__restrict__ qf, const double *__restrict__ q,
                                                  const StepCtx *__restrict__ ctx, int K,
@@ -42,65 +73,85 @@ __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restric
                                                  const double *__restrict__ node_force, int *__restrict__ nodes_c,
                                                  double *__restrict__ mu_c, double *__restrict__ pfree,
                                                  double *__restrict__ pstart, double *__restrict__ finit) {
-  __shared__ unsigned long long key[4096];
-  __shared__ int nid[4096];
+  __shared__ unsigned long long key[1024 * SEL_PER];
+  __shared__ int hist[256];
+  __shared__ int wsum[16];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_rank;
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
   const icr_obstacle obs = ctx->obs;
   const double t1 = ctx->t0 + ctx->h;
-  int n2 = 1;
-  while (n2 < ncand) n2 <<= 1;
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+#pragma unroll
+  for (int e = 0; e < SEL_PER; ++e) {
+    const int i = SEL_PER * tid + e;
+    unsigned long long kv = ~0ull;
     if (i < ncand) {
-      int v = cand[i];
+      const int v = cand[i];
       double p[3] = {qf[3 * v], qf[3 * v + 1], qf[3 * v + 2]}, nrm[3];
-      key[i] = sortable(signed_distance(obs, t1, p, nrm));
-      nid[i] = v;
-    } else {
-      key[i] = ~0ull;
-      nid[i] = 0x7fffffff;
+      kv = sortable(signed_distance(obs, t1, p, nrm));
     }
+    key[i] = kv;
   }
-  __syncthreads();
-  for (int k = 2; k <= n2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        int l = i ^ j;
-        if (l > i) {
-          unsigned long long a = key[i], b = key[l];
-          int na = nid[i], nb = nid[l];
-          bool gt = (a > b) || (a == b && na > nb);
-          bool up = ((i & k) == 0);
-          if (gt == up) {
-            key[i] = b;
-            key[l] = a;
-            nid[i] = nb;
-            nid[l] = na;
-          }
-        }
-      }
-      __syncthreads();
+  if (tid == 0) {
+    s_prefix = 0ull;
+    s_rank = K;   // rank (1-based) of the sought key among those matching the prefix
+  }
+  unsigned long long mask = 0ull;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int b = tid; b < 256; b += 1024) hist[b] = 0;
+    __syncthreads();
+    const unsigned long long prefix = s_prefix;
+#pragma unroll
+    for (int e = 0; e < SEL_PER; ++e) {
+      const int i = SEL_PER * tid + e;
+      if (i < ncand && (key[i] & mask) == prefix) atomicAdd(&hist[(int)((key[i] >> shift) & 255ull)], 1);
     }
-  // order the first K by node id
-  int k2 = 1;
-  while (k2 < K) k2 <<= 1;
-  for (int i = K + threadIdx.x; i < k2; i += blockDim.x) nid[i] = 0x7fffffff;
-  __syncthreads();
-  for (int k = 2; k <= k2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < k2; i += blockDim.x) {
-        int l = i ^ j;
-        if (l > i) {
-          int a = nid[i], b = nid[l];
-          bool up = ((i & k) == 0);
-          if ((a > b) == up) {
-            nid[i] = b;
-            nid[l] = a;
-          }
-        }
+    __syncthreads();
+    if (wv == 0) {
+      const int c0 = hist[4 * ln], c1 = hist[4 * ln + 1], c2 = hist[4 * ln + 2], c3 = hist[4 * ln + 3];
+      const int tot = c0 + c1 + c2 + c3;
+      int incl = tot;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (ln >= o) incl += t;
       }
-      __syncthreads();
+      const int rank = s_rank;
+      int run = incl - tot;
+      const int c[4] = {c0, c1, c2, c3};
+      for (int qd = 0; qd < 4; ++qd) {
+        if (run < rank && rank <= run + c[qd]) {   // exactly one bin of the wave
+          s_prefix = prefix | ((unsigned long long)(4 * ln + qd) << shift);
+          s_rank = rank - run;
+        }
+        run += c[qd];
+      }
     }
-  for (int c = threadIdx.x; c < K; c += blockDim.x) {
-    int v = nid[c];
+    __syncthreads();
+    mask |= 0xffull << shift;
+  }
+  const unsigned long long T = s_prefix;
+  const int need = s_rank;   // candidates with key == T to keep, lowest ids first
+  int tf[SEL_PER], tsum = 0;
+#pragma unroll
+  for (int e = 0; e < SEL_PER; ++e) {
+    const int i = SEL_PER * tid + e;
+    tf[e] = (i < ncand && key[i] == T) ? 1 : 0;
+    tsum += tf[e];
+  }
+  int tr = block_excl_scan_1024(tsum, wsum);
+  int sf[SEL_PER], ssum = 0;
+#pragma unroll
+  for (int e = 0; e < SEL_PER; ++e) {
+    const int i = SEL_PER * tid + e;
+    sf[e] = (i < ncand && (key[i] < T || (tf[e] && tr < need))) ? 1 : 0;
+    tr += tf[e];
+    ssum += sf[e];
+  }
+  int c = block_excl_scan_1024(ssum, wsum);
+#pragma unroll
+  for (int e = 0; e < SEL_PER; ++e) {
+    if (!sf[e]) continue;
+    const int v = cand[SEL_PER * tid + e];
     nodes_c[c] = v;
     mu_c[c] = mu_node[v];
     for (int a = 0; a < 3; ++a) {
@@ -108,6 +159,7 @@ __global__ __launch_bounds__(1024) void k_select(int ncand, const int *__restric
       pstart[3 * c + a] = q[3 * v + a];
       finit[3 * c + a] = node_force[3 * v + a];
     }
+    ++c;
   }
 }
 

@@ -306,6 +306,25 @@ def _compare_step(sim, s, sc, steps, tag):
     return icr
 
 
+def test_contact_selection_ties_by_node_id():
+    """Exact distance ties: zero gravity from rest (q_free = q bit for bit), the
+    unjittered top layer of the tiny mesh and a horizontal plane put all 16
+    candidates at one signed distance; 6 contacts are kept, the lowest node
+    ids.  The candidates are passed in descending order (the selection does
+    not depend on their order)."""
+    icr = _icr()
+    sc = make_scene("tiny", 0)
+    obs = dict(sc["obstacle"], normal=np.array([0.0, 0.0, -1.0]))
+    sc = dict(sc, obstacle=obs, gravity=np.zeros(3), n_contacts=6)
+    sc_rev = dict(sc, candidates=sc["candidates"][::-1].copy(), cand_mu=sc["cand_mu"][::-1].copy())
+    s = icr.scene_from_dict(sc_rev)
+    sim = O.Simulation(sc)
+    _compare_step(sim, s, sc, 1, "tiny, tied distances")
+    res = s.step_results(6)
+    assert np.array_equal(res["node_ids"].cpu().numpy(), np.sort(sc["candidates"])[:6])
+    s.close()
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_step_tiny_matches_oracle(seed):
     sc = make_scene("tiny", seed)
