@@ -175,7 +175,9 @@ typedef struct {
 
 /* Contact candidates (surface nodes) and their friction coefficients, host
  * arrays, copied.  count in [1, 4096]; candidates must be distinct, in range
- * and not clamped, mu finite and >= 0 (else ICR_E_ARG). */
+ * and not clamped, mu finite and >= 0 (else ICR_E_ARG).  Their order is
+ * irrelevant: each step keeps the n_contacts candidates with the smallest
+ * (signed distance, node id) and numbers its contacts by ascending node id. */
 icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu);
 
 typedef struct {
