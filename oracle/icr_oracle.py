@@ -232,7 +232,12 @@ def select_contacts(q_free, scene, t1):
 
 
 def contact_margin(q_free, scene, t1):
-    """Gap between the K-th and (K+1)-th signed distances (selection robustness)."""
+    """Gap between the K-th and (K+1)-th smallest signed distances at q_free.
+
+    The selection of R17 is decided by this difference: 0 means a tie that the
+    node-id rule breaks; a tiny positive value means a near-tie that rounding
+    on another machine could flip.
+    """
     cand = scene["candidates"]
     phi, _ = signed_distance(q_free.reshape(-1, 3)[cand], scene["obstacle"], t1)
     s = np.sort(phi)
@@ -240,25 +245,48 @@ def contact_margin(q_free, scene, t1):
     return float(s[K] - s[K - 1]) if K < len(s) else math.inf
 
 
-def mapping_H(nodes_c, n):
-    """H: the geometric-mapping Jacobian of nodal contacts (Eq. 6), m x n sparse selection."""
-    nc = len(nodes_c)
-    rows = np.arange(3 * nc)
-    cols = (3 * np.asarray(nodes_c)[:, None] + np.arange(3)[None, :]).ravel()
-    return sp.csr_matrix((np.ones(3 * nc), (rows, cols)), shape=(3 * nc, n))
+def mapping_H(nodes_c, n, weights=None):
+    """H: the geometric-mapping Jacobian of the contact points (Eq. 6), m x n sparse.
+
+    Nodal contacts (``weights`` None): contact c selects the three DOFs of node
+    nodes_c[c].  Mapped contacts: nodes_c and weights are [n_c, S]; the point
+    of contact c is sum_s weights[c, s] x(nodes_c[c, s]) (barycentric weights
+    of a surface point), slots with node -1 are unused, and a negative weight
+    marks a node of the second body, so that H = [H_1, -H_2] and H q is the
+    relative position x_1 - x_2 of the pair (Eq. 6, 16-17; R19).
+    """
+    nodes_c = np.asarray(nodes_c)
+    if weights is None:
+        nc = len(nodes_c)
+        rows = np.arange(3 * nc)
+        cols = (3 * nodes_c[:, None] + np.arange(3)[None, :]).ravel()
+        return sp.csr_matrix((np.ones(3 * nc), (rows, cols)), shape=(3 * nc, n))
+    weights = np.asarray(weights, dtype=np.float64)
+    nc, S = nodes_c.shape
+    rows, cols, vals = [], [], []
+    for c in range(nc):
+        for k in range(S):
+            if nodes_c[c, k] < 0:
+                continue
+            for a in range(3):
+                rows.append(3 * c + a)
+                cols.append(3 * nodes_c[c, k] + a)
+                vals.append(weights[c, k])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(3 * nc, n))
 
 
 # ---------------------------------------------------------------------------
 # Mapping compliance W_H = H A^-1 H^T (Eq. 28) and the Delassus operator
 # ---------------------------------------------------------------------------
 
-def build_WH(factor, nodes_c, n, columns=None):
+def build_WH(factor, nodes_c, n, columns=None, weights=None):
     """W_H = H A^{-1} H^T, symmetrised (Eq. 28, R15).
 
     With ``columns`` given, return only those columns of the unsymmetrised
-    H A^{-1} H^T (used at sizes where all m solves are too slow).
+    H A^{-1} H^T (used at sizes where all m solves are too slow).  ``weights``
+    as in ``mapping_H``.
     """
-    H = mapping_H(nodes_c, n)
+    H = mapping_H(nodes_c, n, weights)
     if columns is None:
         Y = factor.solve(H.T.toarray())
         WH = H @ Y
@@ -286,9 +314,9 @@ def update_W(WH, C):
     return W.reshape(3 * nc, 3 * nc)
 
 
-def jacobian(C, nodes_c, n):
+def jacobian(C, nodes_c, n, weights=None):
     """Contact Jacobian J = C H (Eq. 27)."""
-    H = mapping_H(nodes_c, n)
+    H = mapping_H(nodes_c, n, weights)
     Cbd = sp.block_diag([C[a] for a in range(C.shape[0])], format="csr")
     return Cbd @ H
 
@@ -405,10 +433,34 @@ def local_solve(Wl, d, mu, j_inner):
     return force(u0, u1), SLIP
 
 
-def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8):
+def decision_margins(Wl, d, mu):
+    """Relative margins of the two decisions ``local_solve`` takes for one contact.
+
+    sep:  |d_n| / |d|, how far the gap is from the separate/contact switch;
+    cone: |mu lam*_n - |lam*_t|| / (mu lam*_n) for the stick trial lam* of a
+          contact that is not separate (the stick/slip switch); inf when the
+          trial has lam*_n <= 0 or mu = 0 (no cone test is taken then).
+    A margin below about 1e-8 marks a decision that rounding on another
+    machine could flip (the classification parity of Eq. 8-9).
+    """
+    nd = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+    sep = abs(d[0]) / nd if nd > 0.0 else math.inf
+    if d[0] >= 0.0:
+        return sep, math.inf
+    x = chol3_solve(chol3(Wl), d)
+    ln, nt = -x[0], math.sqrt(x[1] * x[1] + x[2] * x[2])
+    if ln <= 0.0 or mu == 0.0:
+        return sep, math.inf
+    return sep, abs(mu * ln - nt) / (mu * ln)
+
+
+def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8, margins=None):
     """Projected Gauss-Seidel on delta = d + h^2 W lambda (Eq. 18-19, Algorithm 1; R2, R6, R7).
 
     Returns lambda [m], status [nc] (branch of the last sweep), sweeps, eps.
+    With ``margins`` a list, the decision margins (``decision_margins``) of
+    every contact's visit in the last sweep are appended to it as an
+    [nc, 2] array (columns sep, cone).
     """
     Wt = (h * h) * np.asarray(W, dtype=np.float64)
     d = np.asarray(d, dtype=np.float64)
@@ -418,12 +470,15 @@ def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8):
     eps = math.inf
     sweeps = 0
     diag = [Wt[3 * a:3 * a + 3, 3 * a:3 * a + 3].tolist() for a in range(nc)]
+    marg = np.full((nc, 2), math.inf) if margins is not None else None
     for sweep in range(max_sweeps):
         prev = lam.copy()
         for a in range(nc):
             r0, r1 = 3 * a, 3 * a + 3
             rows = Wt[r0:r1]
             da = d[r0:r1] + rows[:, :r0] @ lam[:r0] + rows[:, r1:] @ lam[r1:]
+            if marg is not None:
+                marg[a] = decision_margins(diag[a], da.tolist(), float(mu[a]))
             (l0, l1, l2), st = local_solve(diag[a], da.tolist(), float(mu[a]), j_inner)
             lam[r0], lam[r0 + 1], lam[r0 + 2] = l0, l1, l2
             status[a] = st
@@ -433,6 +488,8 @@ def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8):
         eps = diff / nl if nl > 0.0 else (0.0 if diff == 0.0 else math.inf)
         if eps <= tol:
             break
+    if margins is not None:
+        margins.append(marg)
     return lam, status, sweeps, eps
 
 
@@ -441,8 +498,12 @@ def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8):
 # ---------------------------------------------------------------------------
 
 def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_sweeps, tol, j_inner,
-                record=None):
-    """Algorithm 3 with readings R8-R10.  Returns (f world force [nc,3], p, last C, lambda, info)."""
+                record=None, margins=False):
+    """Algorithm 3 with readings R8-R10.  Returns (f world force [nc,3], p, last C, lambda, info).
+
+    With ``margins``, each entry of ``info`` also holds the decision margins of
+    that iteration's last PGS sweep (``pgs``).
+    """
     nc = len(p_free) // 3
     p = p_free.copy()
     f = f_init.reshape(-1, 3).copy()
@@ -454,10 +515,13 @@ def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_s
         W = update_W(WH, C)                                            # step 2
         dk = delta - rotation_blocks_apply(C, p - p_free)              # R9
         lam0 = rotation_blocks_apply(C, f.ravel())                     # R8 warm start
-        lam, status, sweeps, eps = pgs(W, dk, mu, h, lam0, max_sweeps, tol, j_inner)   # step 3
+        marg = [] if margins else None
+        lam, status, sweeps, eps = pgs(W, dk, mu, h, lam0, max_sweeps, tol, j_inner, marg)   # step 3
         f = rotation_blocks_apply_T(C, lam).reshape(-1, 3)
         p = p_free + (h * h) * (WH @ f.ravel())                        # step 4 (Eq. 31)
         info.append(dict(sweeps=sweeps, eps=eps, status=status.copy()))
+        if margins:
+            info[-1]["margins"] = marg[0]
         if record is not None:
             record.append(dict(C=C, W=W, d=dk, lam0=lam0, lam=lam.copy(), status=status.copy(), p=p.copy(),
                                sweeps=sweeps, eps=eps))
@@ -569,7 +633,7 @@ class Simulation:
         self.mu_of_node = np.zeros(len(scene["nodes"]))
         self.mu_of_node[cand] = scene["cand_mu"]
 
-    def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False):
+    def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False, margins=False):
         sc = self.scene
         h = sc["h"]
         t0, t1 = self.t, self.t + h
@@ -590,10 +654,14 @@ class Simulation:
         else:
             WH = build_WH(self.factor, nodes_c, self.n)
             out["WH"] = WH
-            newton = newton_per_constraint if per_constraint else newton_fast
-            f, p, C, lam, info = newton(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h, f_init,
-                                        sc["n_newton"], ms, tl, sc["j_inner"], record)
+            if per_constraint:
+                f, p, C, lam, info = newton_per_constraint(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h,
+                                                           f_init, sc["n_newton"], ms, tl, sc["j_inner"], record)
+            else:
+                f, p, C, lam, info = newton_fast(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h, f_init,
+                                                 sc["n_newton"], ms, tl, sc["j_inner"], record, margins)
             out["info"] = info
+            out["C"] = C
         # corrective motion and integration (Eq. 20, Algorithm 1 last loop, R1)
         dv = dv_free + h * self.factor.solve(H.T @ f.ravel())
         self.v = self.v + dv

@@ -462,3 +462,182 @@ def test_table1_phase_accounting():
         rebuild, pgs_t, corr, newton, total = map(float, r[4:9])
         assert abs(rebuild + pgs_t + corr - newton) <= 0.011
         assert abs(build + 5 * newton - total) <= 0.05
+
+
+# ---------------------------------------------------------------------------
+# Free motion by vibration modes (Eq. 5): pins A's stiffness coefficient and
+# both stiffness terms of the right-hand side
+# ---------------------------------------------------------------------------
+
+def _modal_free_motion_error(free_motion, assemble):
+    """Largest relative error of dv_free against the modal closed forms.
+
+    For K phi = w^2 M phi (phi zero on clamped DOFs, no gravity) the system
+    matrix A = M + h(alpha M + beta K) + h^2 K acts on phi as
+    a(w) M with a(w) = 1 + h alpha + (h beta + h^2) w^2, so
+      deformed at rest  (q = q_rest + phi, v = 0):   dv = -h w^2 phi / a(w)
+      moving undeformed (q = q_rest, v = phi):       dv = -h (alpha + beta w^2 + h w^2) phi / a(w)
+    """
+    import scipy.linalg as sla
+    sc = make_scene("tiny", 0)
+    sc["gravity"] = np.zeros(3)
+    asm = assemble(sc)
+    fac = O.CholeskyFactor(asm["A"])
+    n = asm["n"]
+    free = np.setdiff1d(np.arange(n), asm["fixed_dofs"])
+    Kff = asm["K"].toarray()[np.ix_(free, free)]
+    w2, Phi = sla.eigh(Kff, np.diag(asm["Mdiag"][free]))
+    h, al, be = sc["h"], sc["alpha"], sc["beta"]
+    q0 = sc["nodes"].ravel().copy()
+    worst = 0.0
+    for k in (0, 3, 40, 300, len(free) - 1):
+        phi = np.zeros(n)
+        phi[free] = Phi[:, k] / np.abs(Phi[:, k]).max() * 1e-3
+        a = 1.0 + h * al + (h * be + h * h) * w2[k]
+        dv, _, _ = free_motion(asm, fac, sc, q0 + phi, np.zeros(n), q0)
+        exp = -h * w2[k] * phi / a
+        worst = max(worst, np.linalg.norm(dv - exp) / np.linalg.norm(exp))
+        dv, _, _ = free_motion(asm, fac, sc, q0, phi, q0)
+        exp = -h * (al + be * w2[k] + h * w2[k]) * phi / a
+        worst = max(worst, np.linalg.norm(dv - exp) / np.linalg.norm(exp))
+    return worst
+
+
+def test_free_motion_modal_closed_form():
+    assert _modal_free_motion_error(O.free_motion, O.assemble) <= 1e-9
+
+
+def _mutated(fn, old, new):
+    """A copy of oracle function ``fn`` with one source fragment replaced (a planted mistake)."""
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert src.count(old) == 1, f"fragment {old!r} not found once in {fn.__name__}"
+    ns = dict(vars(O))
+    exec(compile(src.replace(old, new), f"<mutated {fn.__name__}>", "exec"), ns)
+    return ns[fn.__name__]
+
+
+@pytest.mark.parametrize("which,old,new", [
+    ("assemble", "(h * h) * K", "h * K"),                         # wrong power of h on K in A
+    ("assemble", "M + h * Bd + (h * h) * K", "M + Bd + (h * h) * K"),   # damping without h
+    ("free_motion", " - (h * h) * (K @ v)", ""),                  # dropped h^2 K v
+    ("free_motion", "K @ (q - q_rest) + ", ""),                   # dropped elastic force
+    ("free_motion", "- h * f_t", "+ h * f_t"),                    # sign of the internal force
+])
+def test_modal_pin_rejects_planted_mistakes(which, old, new):
+    fm, asm = O.free_motion, O.assemble
+    if which == "assemble":
+        asm = _mutated(O.assemble, old, new)
+    else:
+        fm = _mutated(O.free_motion, old, new)
+    assert _modal_free_motion_error(fm, asm) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Contact selection (Sec. "Contact generation"; R17) on a geometry whose
+# answer is known row by row
+# ---------------------------------------------------------------------------
+
+def _end_face_scene(theta_deg, K):
+    """Tiny beam, unjittered, end face z = 15 s; plane through the face centre,
+    tilted about x so that the signed distance of an end-face node is
+    sin(theta) (y - y_c): row j of the face (4 nodes) is nearer than row j+1."""
+    sc = make_scene("tiny", 0)
+    th = math.radians(theta_deg)
+    obs = dict(sc["obstacle"], normal=np.array([0.0, math.sin(th), -math.cos(th)]), vel=np.zeros(3))
+    return dict(sc, obstacle=obs, n_contacts=K)
+
+
+def _end_face_id(i, j):
+    return i + 4 * (j + 4 * 15)      # node id = i + nx (j + ny k), k = 15
+
+
+def test_select_contacts_rows_of_a_tilted_plane():
+    rng = np.random.default_rng(3)
+    for K, rows in ((4, [0]), (8, [0, 1]), (12, [0, 1, 2])):
+        sc = _end_face_scene(10.0, K)
+        sc["candidates"] = rng.permutation(sc["candidates"]).astype(np.int32)   # order is irrelevant
+        got = O.select_contacts(sc["nodes"].ravel(), sc, 0.0)
+        expect = sorted(_end_face_id(i, j) for j in rows for i in range(4))
+        assert got.tolist() == expect
+        assert math.isclose(O.contact_margin(sc["nodes"].ravel(), sc, 0.0), math.sin(math.radians(10.0)) * 0.01,
+                            rel_tol=1e-9)
+
+
+def test_select_contacts_ties_broken_by_node_id():
+    """K = 6 cuts row 1 (four equal distances): its two lowest node ids are kept; a
+    horizontal plane ties all 16 and keeps the 6 lowest ids.  Margin 0 at a tie."""
+    sc = _end_face_scene(10.0, 6)
+    got = O.select_contacts(sc["nodes"].ravel(), sc, 0.0)
+    expect = sorted([_end_face_id(i, 0) for i in range(4)] + [_end_face_id(0, 1), _end_face_id(1, 1)])
+    assert got.tolist() == expect
+    assert O.contact_margin(sc["nodes"].ravel(), sc, 0.0) == 0.0
+    flat = _end_face_scene(0.0, 6)
+    got = O.select_contacts(flat["nodes"].ravel(), flat, 0.0)
+    assert got.tolist() == sorted(flat["candidates"].tolist())[:6]
+
+
+def test_decision_margins_of_constructed_contacts():
+    """A stick trial placed at a known relative distance from the cone boundary,
+    and a gap at a known angle from the separate/contact switch."""
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        Wl = np.array(_block(rng))
+        mu = rng.uniform(0.1, 0.6)
+        rel = 10.0 ** rng.uniform(-6, -1) * rng.choice([-1.0, 1.0])
+        ang = rng.uniform(0, 2 * math.pi)
+        ln = rng.uniform(0.5, 2.0)
+        lam = np.array([ln, math.cos(ang), math.sin(ang)]) * np.array([1.0, mu * ln * (1 - rel), mu * ln * (1 - rel)])
+        d = -(Wl @ lam)
+        sep, cone = O.decision_margins(Wl.tolist(), d.tolist(), mu)
+        assert math.isclose(cone, abs(rel), rel_tol=1e-6)
+        assert math.isclose(sep, abs(d[0]) / np.linalg.norm(d), rel_tol=1e-14)
+    sep, cone = O.decision_margins(np.eye(3).tolist(), [3.0, 4.0, 0.0], 0.3)   # separate: 3/5, no cone test
+    assert sep == 0.6 and cone == math.inf
+
+
+# ---------------------------------------------------------------------------
+# Mapped (barycentric, two-body) contacts: Eq. 6, 16-17, 27-28
+# ---------------------------------------------------------------------------
+
+def test_barycentric_mapping_reproduces_affine_fields(tiny_sim):
+    """H q for barycentric points of tetrahedra: barycentric interpolation
+    reproduces any affine field u(x) = G x + c exactly, with the weights found
+    by solving [1; x] w = [1; p] for a point p chosen inside the element."""
+    sc = tiny_sim.scene
+    rng = np.random.default_rng(21)
+    tets = sc["tets"][rng.choice(len(sc["tets"]), 10, replace=False)]
+    pts, W = [], []
+    for t in tets:
+        X = sc["nodes"][t]
+        b = rng.dirichlet(np.ones(4))
+        p = b @ X
+        P = np.vstack([np.ones(4), X.T])
+        W.append(np.linalg.solve(P, np.concatenate([[1.0], p])))
+        pts.append(p)
+    H = O.mapping_H(tets, tiny_sim.n, np.array(W))
+    G, c = rng.standard_normal((3, 3)), rng.standard_normal(3)
+    field = (sc["nodes"] @ G.T + c).ravel()
+    assert np.allclose(H @ field, (np.array(pts) @ G.T + c).ravel(), rtol=1e-13, atol=1e-15)
+
+
+def test_mapped_WH_equals_dense_inverse(tiny_sim):
+    """W_H = H A^-1 H^T with multi-node rows and unused slots, against a dense
+    H filled entry by entry and numpy's inverse of A."""
+    rng = np.random.default_rng(22)
+    free = np.nonzero(tiny_sim.scene["fixed"] == 0)[0]
+    nc, S = 7, 4
+    ids = rng.choice(free, size=(nc, S), replace=True)
+    w = rng.uniform(-1.0, 1.0, size=(nc, S))
+    ids[2, 3] = -1
+    ids[5, 1:] = -1
+    WH = O.build_WH(tiny_sim.factor, ids, tiny_sim.n, weights=w)
+    Hd = np.zeros((3 * nc, tiny_sim.n))
+    for c in range(nc):
+        for k in range(S):
+            if ids[c, k] >= 0:
+                for a in range(3):
+                    Hd[3 * c + a, 3 * ids[c, k] + a] += w[c, k]
+    ref = Hd @ np.linalg.inv(tiny_sim.asm["A"].toarray()) @ Hd.T
+    assert np.linalg.norm(WH - ref) <= 1e-12 * np.linalg.norm(ref)
