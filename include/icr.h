@@ -140,9 +140,13 @@ icr_status icr_update_W(icr_scene *s, int32_t n_c, const double *WH, const doubl
  * tangential gap) by j_inner passes of a shifted fixed point.  After every
  * sweep eps = |lam_i - lam_{i-1}|_2 / |lam_i|_2; stop when eps <= tol or after
  * max_sweeps sweeps.
- *   W [m*m] device, exactly symmetric (as icr_update_W writes it: rows are
- *   read in place of columns); d [m], mu [n_c] device; lambda [m] device
- *   in/out (warm start);
+ *   W [m*m] device, exactly symmetric and positive semidefinite with
+ *   positive definite 3x3 diagonal blocks, as icr_update_W writes it from a
+ *   W_H of icr_build_WH (rows are read in place of columns, and contacts that
+ *   cannot change in a sweep are settled by the Cauchy-Schwarz bound
+ *   |W_cq| <= sqrt(W_cc W_qq) of a PSD matrix; an indefinite W gives iterates
+ *   that may differ from the sequential sweep); d [m], mu [n_c] device;
+ *   lambda [m] device in/out (warm start);
  *   status [n_c] device int8 (branch of the last sweep)
  *   sweeps_out, eps_out: host, may be NULL (then the call does not synchronise)
  * Returns ICR_WARN_NOT_CONVERGED (when eps_out/sweeps_out are given and
@@ -158,6 +162,7 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
  *   WH [m*m] device, exactly symmetric (as icr_build_WH writes it: rows are
  *   read in place of columns, and only those of contacts with a non-zero
  *   force); p_free [m], f [m] device; p [m] device output.
+ * ICR_E_ARG on n_c < 1 or a non-finite or non-positive h.
  */
 icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, const double *p_free,
                                 const double *f, double h, double *p);

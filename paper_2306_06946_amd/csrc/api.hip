@@ -502,6 +502,7 @@ icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, con
                                 double h, double *p) {
   return guarded(s, [&] {
     REQUIRE(n_c >= 1, "n_c must be >= 1");
+    REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
     REQUIRE(WH && p_free && f && p, "NULL device pointer");
     launch_proximity(s->stream, n_c, WH, p_free, f, h, p);
     return ICR_OK;

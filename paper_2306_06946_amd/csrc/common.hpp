@@ -29,97 +29,10 @@ struct HipError : std::runtime_error {
 constexpr int TILE = 64;   // output tile edge of the FP64 GEMM tiles
 constexpr int KT = 16;     // K-chunk staged in LDS per iteration
 
-// Accumulate a 64x64 tile:  acc += A(i, k) * B(k, j) for i in [0, M), j in
-// [0, N) (tile-local), k in [k0, k1).  A(i, k) = A[i*ars + k*acs],
-// B(k, j) = B[k*brs + j*bcs].  256 threads; thread (tx, ty) = (tid % 16,
-// tid / 16) owns rows ty + 16*ii and columns tx + 16*jj (ii, jj < 4).
-// Staging is coalesced along whichever stride is 1.  sA, sB: LDS [KT*TILE].
-__device__ inline void tile_gemm_acc(double acc[4][4], const double *__restrict__ A, long ars, long acs,
-                                     const double *__restrict__ B, long brs, long bcs, int M, int N, int k0,
-                                     int k1, double *sA, double *sB) {
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const bool a_rowfast = (ars == 1);
-  const bool b_colfast = (bcs == 1);
-  for (int kb = k0; kb < k1; kb += KT) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
-      int i, k;
-      if (a_rowfast) {
-        i = e & 63;
-        k = e >> 6;
-      } else {
-        k = e & 15;
-        i = e >> 4;
-      }
-      int kk = kb + k;
-      double v = 0.0;
-      if (i < M && kk < k1) v = A[(long)i * ars + (long)kk * acs];
-      sA[k * TILE + i] = v;
-      int j;
-      if (b_colfast) {
-        j = e & 63;
-        k = e >> 6;
-      } else {
-        k = e & 15;
-        j = e >> 4;
-      }
-      kk = kb + k;
-      v = 0.0;
-      if (j < N && kk < k1) v = B[(long)kk * brs + (long)j * bcs];
-      sB[k * TILE + j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) a[ii] = sA[k * TILE + ty + 16 * ii];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) b[jj] = sB[k * TILE + tx + 16 * jj];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = fma(a[ii], b[jj], acc[ii][jj]);
-    }
-    __syncthreads();
-  }
-}
-
-__device__ inline void tile_zero(double acc[4][4]) {
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = 0.0;
-}
-
 // ---------------------------------------------------------------------------
-// 64x64 FP64 tile accumulators.  Both expose for_each(f) visiting the tile-local
-// (i, j) of every value the calling thread owns.
+// 64x64 FP64 MFMA tile accumulators.  Each exposes for_each(f) visiting the
+// tile-local (i, j) of every value the calling thread owns.
 // ---------------------------------------------------------------------------
-
-// VALU layout: thread (tx, ty) owns (ty + 16 ii, tx + 16 jj).
-struct AccV {
-  double c[4][4];
-  __device__ void zero() { tile_zero_impl(); }
-  __device__ void tile_zero_impl() {
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) c[ii][jj] = 0.0;
-  }
-  __device__ void acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M, int N, int k0,
-                      int k1, double *sA, double *sB);
-  template <class F>
-  __device__ void for_each(F &&f) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) f(ty + 16 * ii, tx + 16 * jj, c[ii][jj]);
-  }
-};
 
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
@@ -149,47 +62,6 @@ struct AccM {
         for (int t = 0; t < 4; ++t) f(r0 + 16 * a + 4 * t + (l >> 4), c0 + 16 * b + (l & 15), c[a][b][t]);
   }
 };
-
-// Stage one K-chunk of A (64 x KT) and B (KT x 64) into LDS as [k][i] / [k][j].
-__device__ inline void stage_chunk(const double *__restrict__ A, long ars, long acs, const double *__restrict__ B,
-                                   long brs, long bcs, int M, int N, int kb, int k1, double *sA, double *sB) {
-  const int tid = threadIdx.x;
-  const bool a_rowfast = (ars == 1);
-  const bool b_colfast = (bcs == 1);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q;
-    int i, k;
-    if (a_rowfast) {
-      i = e & 63;
-      k = e >> 6;
-    } else {
-      k = e & 15;
-      i = e >> 4;
-    }
-    int kk = kb + k;
-    double v = 0.0;
-    if (i < M && kk < k1) v = A[(long)i * ars + (long)kk * acs];
-    sA[k * TILE + i] = v;
-    int j;
-    if (b_colfast) {
-      j = e & 63;
-      k = e >> 6;
-    } else {
-      k = e & 15;
-      j = e >> 4;
-    }
-    kk = kb + k;
-    v = 0.0;
-    if (j < N && kk < k1) v = B[(long)kk * brs + (long)j * bcs];
-    sB[k * TILE + j] = v;
-  }
-}
-
-__device__ inline void AccV::acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M,
-                                 int N, int k0, int k1, double *sA, double *sB) {
-  tile_gemm_acc(c, A, ars, acs, B, brs, bcs, M, N, k0, k1, sA, sB);
-}
 
 // Register-prefetched staging: the next K-chunk is fetched from global memory
 // into registers while the MFMAs of the current chunk run from LDS.
@@ -373,15 +245,8 @@ struct AccMT {
 };
 typedef AccMT<2, 32> AccS;   // 64 x 64, K-chunk 32
 
-// The tile accumulator used by the dense kernels.
-#ifndef ICR_TILE_MFMA
-#define ICR_TILE_MFMA 1
-#endif
-#if ICR_TILE_MFMA
+// The tile accumulator of the factor kernels.
 typedef AccM Acc;
-#else
-typedef AccV Acc;
-#endif
 
 
 // Lower-triangle tile index x -> (I, J), I >= J, row-major over the triangle.
