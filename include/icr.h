@@ -157,6 +157,23 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
                               int32_t j_inner, int32_t *sweeps_out, double *eps_out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * icr_solve_contacts without a scene.  Same arguments, kernels and results;
+ * the call allocates nothing and enqueues its work on `stream` (hipStream_t
+ * as void*, NULL = the null stream) of the current device.  Its work buffers
+ * live in one static device array of the library, about 21 MB per GPU, held
+ * until the process ends; every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other host threads) race.
+ * n_c <= 1024.  Errors are return codes only (no scene holds a message):
+ * ICR_E_ARG on n_c outside [1, 1024], max_sweeps < 1, j_inner < 0,
+ * h <= 0 or non-finite, a NULL device pointer; ICR_E_HIP on a runtime error.
+ */
+icr_status icr_solve_contacts_noalloc(void *stream, int32_t n_c, const double *W, const double *d, const double *mu,
+                                      double h, double *lambda, int8_t *status, int32_t max_sweeps, double tol,
+                                      int32_t j_inner, int32_t *sweeps_out, double *eps_out);
+
+/*
  * Proximity update p = p_free + h^2 W_H f (Eq. 31 with the total force
  * f = C_k^T lambda_k in world frame, one 3-vector per contact).
  *   WH [m*m] device, exactly symmetric (as icr_build_WH writes it: rows are

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libicr.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["analysis.cpp", "k_fem.hip", "k_factor.hip", "k_solve.hip", "k_contact.hip", "api.hip", "server.cpp"]
+SOURCES = ["analysis.cpp", "k_fem.hip", "k_factor.hip", "k_solve.hip", "k_contact.hip", "api.hip", "noalloc.hip",
+           "server.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 HIP_FLAGS = ["--offload-arch=gfx950", "-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -4,6 +4,7 @@
 // projected Gauss-Seidel (Eq. 18-19, Algorithm 1), and the proximity update
 // p_k = p_free + h^2 W_H C_k^T lambda_k (Eq. 31).
 #include <algorithm>
+#include <mutex>
 
 #include "scene.hpp"
 
@@ -341,7 +342,7 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
 //   15   mu w01             16 mu w02             17 mu
 //   18   1 if w00 > mu |(w01, w02)| with margin (then den(u) > 0 on the unit
 //        circle and the slip pass needs no fallback), else 0
-constexpr int PGS_RW = 22;   // record width: 19 entries, then the contact's current force (chain)
+constexpr int PGS_RW = kPgsRecWidth;   // record width: 19 entries, then the contact's current force (chain)
 __device__ inline void make_record(const double w[3][3], double mu, double *rec) {
   const double w00 = w[0][0], w01 = w[0][1], w02 = w[0][2], w11 = w[1][1], w12 = w[1][2], w22 = w[2][2];
   const double c00 = w11 * w22 - w12 * w12, c01 = w02 * w12 - w01 * w22, c02 = w01 * w12 - w02 * w11;
@@ -955,8 +956,8 @@ constexpr int PGS_SMAX = 512;
 constexpr int PGS_S3 = 3 * PGS_SMAX;
 constexpr int PGS_NT = 512;   // threads of the active-set kernel
 constexpr int PGS_NW = PGS_NT / 64;
-constexpr int PGS_WAVE_MAX = 512;   // largest set swept by the register chains (= PGS_SMAX)
-constexpr int PGS_BLK = 10;         // doubles per 3x3 block of the blocked W~_SS (9 used, 16-byte aligned)
+constexpr int PGS_WAVE_MAX = kPgsWaveMax;   // largest set swept by the register chains (= PGS_SMAX)
+constexpr int PGS_BLK = kPgsBlk;            // doubles per 3x3 block of the blocked W~_SS (9 used, 16-byte aligned)
 struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
@@ -975,9 +976,6 @@ struct PgsLds {
 static_assert(sizeof(PgsLds) <= 160 * 1024, "active-set PGS state must fit one CU's LDS");
 static_assert(3 * PGS_MAX_NC * sizeof(double) + PGS_MAX_NC + 512 <= 160 * 1024, "k_pgs_single LDS");
 
-// Padded contact count of the blocked layout: 64 contacts per register slot,
-// two slots per chain wave beyond 64 contacts.
-__host__ __device__ inline int pgs_wave_pad(int nS) { return nS <= 64 ? 64 : 128 * ((nS + 127) / 128); }
 
 __device__ inline double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
@@ -1668,23 +1666,22 @@ void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const
   ICR_LAUNCH_CHECK();
 }
 
-size_t pgs_rec_elems(int nc) { return (size_t)std::min(nc, PGS_WAVE_MAX) * PGS_RW; }
-
-size_t pgs_wss_elems(int nc) {
-  const int n = std::min(nc, PGS_WAVE_MAX);
-  return (size_t)n * pgs_wave_pad(n) * PGS_BLK;
-}
-
 void pgs_prepare() {
-  static bool done = false;
-  if (done) return;
+  // kernel attributes are set once per device
+  static std::mutex mtx;
+  static unsigned long long done = 0;
+  int dev = 0;
+  ICR_HIP(hipGetDevice(&dev));
+  const unsigned long long bit = 1ull << (dev & 63);
+  std::lock_guard<std::mutex> lock(mtx);
+  if (done & bit) return;
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_single_lds(PGS_MAX_NC)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_pc, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_pc_lds(PGS_MAX_NC)));
-  done = true;
+  done |= bit;
 }
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {

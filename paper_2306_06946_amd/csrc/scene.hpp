@@ -221,9 +221,21 @@ void launch_stamp(icr_scene *s, int slot);
 void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
 constexpr int kPgsMaxContacts = 4096;
 constexpr int kMaxNewton = 256;   // Newton iterations per step (per-iteration sweeps, eps, stamps)
-size_t pgs_wss_elems(int nc);   // doubles of the blocked coupling matrix of an active set (n_c contacts)
-size_t pgs_rec_elems(int nc);   // doubles of the prepared records (and gaps) of a first active set
-void pgs_prepare();   // one-time kernel attributes (dynamic LDS); call outside graph capture
+// Layout of the PGS work buffers: per-contact records of kPgsRecWidth
+// doubles, the blocked coupling matrix of an active set of up to kPgsWaveMax
+// contacts in 3x3 blocks of kPgsBlk doubles, padded to pgs_wave_pad contacts.
+constexpr int kPgsRecWidth = 22;
+constexpr int kPgsWaveMax = 512;
+constexpr int kPgsBlk = 10;
+// 64 contacts per register slot, two slots per chain wave beyond 64 contacts
+__host__ __device__ constexpr inline int pgs_wave_pad(int nS) { return nS <= 64 ? 64 : 128 * ((nS + 127) / 128); }
+// doubles of the blocked coupling matrix of an active set (n_c contacts)
+constexpr inline size_t pgs_wss_elems(int nc) {
+  return (size_t)(nc < kPgsWaveMax ? nc : kPgsWaveMax) * pgs_wave_pad(nc < kPgsWaveMax ? nc : kPgsWaveMax) * kPgsBlk;
+}
+// doubles of the prepared records (and gaps) of a first active set
+constexpr inline size_t pgs_rec_elems(int nc) { return (size_t)(nc < kPgsWaveMax ? nc : kPgsWaveMax) * kPgsRecWidth; }
+void pgs_prepare();   // kernel attributes (dynamic LDS), once per device; call outside graph capture
 void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
                                const double *pstart, const double *mu, double h, double *f, double *Cm,
                                double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,

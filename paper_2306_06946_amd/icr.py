@@ -73,6 +73,8 @@ _SIGS = {
     "icr_update_W": (C.c_int, [_P, _I, _P, _P, _P]),
     "icr_solve_contacts": (C.c_int, [_P, _I, _P, _P, _P, _D, _P, _P, _I, _D, _I, C.POINTER(_I),
                                      C.POINTER(_D)]),
+    "icr_solve_contacts_noalloc": (C.c_int, [_P, _I, _P, _P, _P, _D, _P, _P, _I, _D, _I, C.POINTER(_I),
+                                             C.POINTER(_D)]),
     "icr_proximity_update": (C.c_int, [_P, _I, _P, _P, _P, _D, _P]),
     "icr_set_candidates": (C.c_int, [_P, _I, _P, _P]),
     "icr_step": (C.c_int, [_P, C.POINTER(Obstacle), C.POINTER(StepOpts), C.POINTER(StepReport)]),
