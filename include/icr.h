@@ -21,9 +21,10 @@
  *   - Device work is enqueued on the scene's stream (icr_create).  Calls that
  *     return host values (sweeps, eps, reports) synchronise that stream.
  *   - Arrays are row-major, float64 unless stated; node ids are int32,
- *     DOF index = 3 * node + axis.  A contact is a mesh node (nodal mapping H:
- *     the three DOFs of that node, Eq. 6) with a frame of three rows
- *     (normal, tangent 1, tangent 2; Eq. 26) and three force components.
+ *     DOF index = 3 * node + axis.  A contact is a point mapped from mesh
+ *     nodes (Eq. 6: a node, or a weighted sum of up to four nodes in
+ *     icr_build_WH) with a frame of three rows (normal, tangent 1,
+ *     tangent 2; Eq. 26) and three force components.
  */
 #ifndef ICR_H
 #define ICR_H
@@ -110,18 +111,29 @@ typedef struct {
 icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out);
 
 /*
- * Mapping compliance W_H = H A^{-1} H^T (Eq. 28) for n_c nodal contacts.
- * Computed as W_H = Z^T Z with Z = L^{-1} P H^T: a sparse-RHS supernodal
- * forward solve (each contact's three columns live only on the path from its
- * node's supernode to the root) followed by per-supernode SYRK updates.  The
- * result is exactly symmetric.
- *   node_ids [n_c] device int32, distinct, not clamped
- *   WH       [m*m] device, m = 3 n_c, row-major; row 3c+a = contact c, axis a
- * Errors: ICR_E_STATE before icr_factor; ICR_E_ARG if n_c < 1 or n_c exceeds
- * the limit set by the mesh.  Ids are validated on the device; an invalid id
- * makes the call return ICR_E_ARG (this synchronises the stream).
+ * Mapping compliance W_H = H A^{-1} H^T (Eq. 28), H the Jacobian of the
+ * geometric mapping of the contact points (Eq. 6).  Computed as W_H = Z^T Z
+ * with Z = L^{-1} P H^T: a sparse-RHS supernodal forward solve (each node's
+ * three columns live only on the path from its supernode to the root)
+ * followed by per-supernode SYRK updates.  The result is exactly symmetric.
+ *   weights == NULL: nodal contacts, H selects the three DOFs of a node:
+ *     node_ids [n_c] device int32, distinct, not clamped.
+ *   weights != NULL: mapped contacts, point c = sum_k weights[4c+k] x(node_ids[4c+k]):
+ *     node_ids [n_c*4] device int32, -1 marks an unused slot; weights
+ *     [n_c*4] device, finite and non-zero on used slots.  A node may be
+ *     shared by several contacts; a negative weight puts the node on the
+ *     other side of the pair, so that with the nodes of body 1 weighted +w
+ *     and those of body 2 -w, H = [H_1, -H_2] and H q = x_1 - x_2 (the two-
+ *     body mapping of Eq. 16-17 on the block-diagonal A of two meshes).
+ *     Computed from the nodal W_N of the distinct nodes (at most 8192):
+ *     W_H = H_w W_N H_w^T, H_w the n_c x nodes weight matrix.
+ *   WH [m*m] device, m = 3 n_c, row-major; row 3c+a = contact c, axis a
+ * Errors: ICR_E_STATE before icr_factor; ICR_E_ARG if n_c < 1, n_c > 8192
+ * or more distinct nodes than that, or a bad id or weight.  Nodal ids are
+ * validated on the device, mapped ones on the host; the call synchronises
+ * the stream.
  */
-icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, double *WH);
+icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, const double *weights, double *WH);
 
 /*
  * Fast update of the compliance matrix (Eq. 28, Algorithm 3 step 2):

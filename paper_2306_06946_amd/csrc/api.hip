@@ -265,6 +265,7 @@ void icr_destroy(icr_scene *s) {
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->side) (void)hipStreamDestroy(s->side);
   s->con.arena.release();
+  s->map_arena.release();
   s->fac.rhs_arena.release();
   s->fac_arena.release();
   s->mesh_arena.release();
@@ -312,6 +313,8 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     s->assembled = s->factored = s->has_candidates = s->stepped = false;
     s->con.arena.release();
     s->con.nc_cap = 0;
+    s->map_arena.release();
+    s->map_nc_cap = s->map_nu_cap = 0;
     s->fac.rhs_arena.release();
     s->fac.nc_cap = 0;
     s->fac_arena.release();
@@ -440,24 +443,77 @@ icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out) {
     out->factor_flops = s->fac.flops;
     out->factor_ms = s->fac.ms;
     out->device_bytes = (int64_t)(s->mesh_arena.bytes + s->fac_arena.bytes + s->fac.rhs_arena.bytes +
-                                  s->state_arena.bytes + s->con.arena.bytes);
+                                  s->state_arena.bytes + s->con.arena.bytes + s->map_arena.bytes);
     return ICR_OK;
   });
 }
 
-icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, double *WH) {
+icr_status icr_build_WH(icr_scene *s, int32_t n_c, const int32_t *node_ids, const double *weights, double *WH) {
   return guarded(s, [&] {
     if (!s->factored) throw StateError("icr_build_WH before icr_factor");
     REQUIRE(n_c >= 1 && n_c <= 8192, "n_c must be in [1, 8192]");
-    REQUIRE(n_c <= s->mesh.N, "more contacts than nodes");
     REQUIRE(node_ids && WH, "NULL device pointer");
-    ensure_rhs_capacity(s, n_c);
-    build_WH_device(s, n_c, node_ids, WH, true);
-    int bad = 0;
-    ICR_HIP(hipMemcpyAsync(&bad, s->fac.d_cerr, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    ICR_HIP(hipStreamSynchronize(s->stream));
-    if (bad == 1) throw ArgError("a contact node id is out of range or clamped");
-    if (bad) throw ArgError("duplicate contact node ids");
+    hipStream_t st = s->stream;
+    auto device_check = [&] {
+      int bad = 0;
+      ICR_HIP(hipMemcpyAsync(&bad, s->fac.d_cerr, sizeof(int), hipMemcpyDeviceToHost, st));
+      ICR_HIP(hipStreamSynchronize(st));
+      if (bad == 1) throw ArgError("a contact node id is out of range or clamped");
+      if (bad) throw ArgError("duplicate contact node ids");
+    };
+    if (!weights) {   // nodal contacts
+      REQUIRE(n_c <= s->mesh.N, "more contacts than nodes");
+      ensure_rhs_capacity(s, n_c);
+      build_WH_device(s, n_c, node_ids, WH, true);
+      device_check();
+      return ICR_OK;
+    }
+    // mapped contacts: W_N of the distinct nodes, then the weighted expansion
+    std::vector<int> ids(4L * n_c);
+    std::vector<double> w(4L * n_c);
+    ICR_HIP(hipMemcpyAsync(ids.data(), node_ids, sizeof(int) * ids.size(), hipMemcpyDeviceToHost, st));
+    ICR_HIP(hipMemcpyAsync(w.data(), weights, sizeof(double) * w.size(), hipMemcpyDeviceToHost, st));
+    ICR_HIP(hipStreamSynchronize(st));
+    const auto &mesh = s->mesh;
+    std::vector<int> nodes;
+    nodes.reserve(ids.size());
+    for (int c = 0; c < n_c; ++c) {
+      int used = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int v = ids[4 * c + k];
+        if (v == -1) continue;
+        REQUIRE(v >= 0 && v < mesh.N, "contact " + std::to_string(c) + ": node id out of range");
+        REQUIRE(!mesh.fixed[v], "contact " + std::to_string(c) + ": node is clamped");
+        REQUIRE(std::isfinite(w[4 * c + k]) && w[4 * c + k] != 0.0,
+                "contact " + std::to_string(c) + ": weights of used slots must be finite and non-zero");
+        for (int l = 0; l < k; ++l) REQUIRE(ids[4 * c + l] != v, "contact " + std::to_string(c) + ": repeated node");
+        nodes.push_back(v);
+        ++used;
+      }
+      REQUIRE(used > 0, "contact " + std::to_string(c) + " has no node");
+    }
+    std::sort(nodes.begin(), nodes.end());
+    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+    const int nu = (int)nodes.size();
+    REQUIRE(nu <= 8192, "the contacts reference more than 8192 distinct nodes");
+    std::vector<int> idx(4L * n_c, -1);
+    for (long e = 0; e < 4L * n_c; ++e)
+      if (ids[e] >= 0) idx[e] = (int)(std::lower_bound(nodes.begin(), nodes.end(), ids[e]) - nodes.begin());
+    if (n_c > s->map_nc_cap || nu > s->map_nu_cap) {
+      ICR_HIP(hipStreamSynchronize(st));
+      s->map_arena.release();
+      s->map_nc_cap = std::max(n_c, s->map_nc_cap);
+      s->map_nu_cap = std::max(nu, s->map_nu_cap);
+      s->d_map_nodes = s->map_arena.alloc<int>(s->map_nu_cap);
+      s->d_map_idx = s->map_arena.alloc<int>(4L * s->map_nc_cap);
+      s->d_map_WN = s->map_arena.alloc<double>(9L * s->map_nu_cap * s->map_nu_cap);
+    }
+    ICR_HIP(hipMemcpyAsync(s->d_map_nodes, nodes.data(), sizeof(int) * nu, hipMemcpyHostToDevice, st));
+    ICR_HIP(hipMemcpyAsync(s->d_map_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+    ensure_rhs_capacity(s, nu);
+    build_WH_device(s, nu, s->d_map_nodes, s->d_map_WN, true);
+    launch_wh_expand(st, n_c, nu, s->d_map_idx, weights, s->d_map_WN, WH);
+    device_check();   // also keeps the host arrays alive until the copies are done
     return ICR_OK;
   });
 }

@@ -423,6 +423,57 @@ __global__ __launch_bounds__(256) void k_wh_unpermute(int nc, const int *__restr
   for (int j = threadIdx.x; j < m; j += 256) dst[j] = src[3 * pos[j / 3] + j % 3];
 }
 
+// Mapped contacts (Eq. 6): contact a is the point sum_k w_ak x(u_ak) over up
+// to four slots (unused slots: index -1), so H = Hw Hn with Hn the nodal
+// selection of the distinct nodes and
+//   W_H[3a+i][3b+j] = sum_{k,l} w_ak w_bl W_N[3 u_ak + i][3 u_bl + j],
+// W_N = Hn A^-1 Hn^T (built by the nodal path).  One block per contact row
+// a, threads over b.  The sixteen terms are summed in an order that is the
+// same for (a, b) and (b, a) -- diagonal slot pairs, then each off-diagonal
+// pair (k, l) as t_kl + t_lk -- with products and sums rounded separately
+// (no contraction), so W_H is exactly symmetric like W_N.
+__global__ __launch_bounds__(256) void k_wh_expand(int nc, int nu3, const int *__restrict__ idx,
+                                                   const double *__restrict__ wts, const double *__restrict__ WN,
+                                                   double *__restrict__ WH) {
+  const int a = blockIdx.x;
+  int ua[4];
+  double wa[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ua[k] = idx[4 * a + k];
+    wa[k] = ua[k] >= 0 ? wts[4 * a + k] : 0.0;
+  }
+  const long m = 3L * nc;
+  for (int b = threadIdx.x; b < nc; b += blockDim.x) {
+    int ub[4];
+    double wb[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      ub[l] = idx[4 * b + l];
+      wb[l] = ub[l] >= 0 ? wts[4 * b + l] : 0.0;
+    }
+    // t(k, l)[i][j] = (w_ak w_bl) W_N[3 u_ak + i][3 u_bl + j], 0 for an unused slot
+    auto term = [&](int k, int l, int i, int j) -> double {
+      if (ua[k] < 0 || ub[l] < 0) return 0.0;
+      return __dmul_rn(__dmul_rn(wa[k], wb[l]), WN[(long)(3 * ua[k] + i) * nu3 + 3 * ub[l] + j]);
+    };
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double acc = term(0, 0, i, j);
+#pragma unroll
+        for (int k = 1; k < 4; ++k) acc = __dadd_rn(acc, term(k, k, i, j));
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int l = k + 1; l < 4; ++l) acc = __dadd_rn(acc, __dadd_rn(term(k, l, i, j), term(l, k, i, j)));
+        WH[(3L * a + i) * m + 3L * b + j] = acc;
+      }
+    }
+  }
+}
+
 // ---- single RHS -------------------------------------------------------------
 
 // Single-RHS products, 1024 threads per block.  Column-major A times x: lane
@@ -697,6 +748,11 @@ void contact_force_solve(icr_scene *s, const double *f, double *x) {
   k_zf_sum<<<F.n_zf_sum_tasks, GV_R, 0, s->stream>>>(F.d_zf_tasks, F.d_sup, F.d_lohi, F.d_zf_part, F.d_y);
   ICR_LAUNCH_CHECK();
   backward_solve(s, x);
+}
+
+void launch_wh_expand(hipStream_t st, int nc, int nu, const int *idx, const double *w, const double *WN, double *WH) {
+  k_wh_expand<<<nc, 256, 0, st>>>(nc, 3 * nu, idx, w, WN, WH);
+  ICR_LAUNCH_CHECK();
 }
 
 void launch_fill(icr_scene *s, double *x, long n, double v) {

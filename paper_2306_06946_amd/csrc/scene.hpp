@@ -178,6 +178,11 @@ struct icr_scene {
   icr::Contacts con;
   icr::State st;
   icr::Arena mesh_arena, fac_arena, state_arena;
+  // mapped contacts of icr_build_WH: distinct nodes, slot indices, nodal W_N
+  icr::Arena map_arena;
+  int map_nc_cap = 0, map_nu_cap = 0;
+  int *d_map_nodes = nullptr, *d_map_idx = nullptr;
+  double *d_map_WN = nullptr;
   int last_nc = 0;
   int last_build_nc = 0;   // contact count of the last multi-RHS forward solve (Z valid for it)
   long epoch = 0;          // bumped whenever device buffers are (re)allocated
@@ -212,6 +217,9 @@ void launch_fill(icr_scene *s, double *x, long n, double v);
 // [nc*9] are given (the standard rebuild of Algorithm 2).
 void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate,
                      const double *frames = nullptr);
+// W_H of mapped contacts from the nodal W_N of their distinct nodes:
+// idx [nc*4] slot -> index into those nodes (-1 unused), w [nc*4] weights.
+void launch_wh_expand(hipStream_t st, int nc, int nu, const int *idx, const double *w, const double *WN, double *WH);
 
 // k_contact.hip
 void launch_select_contacts(icr_scene *s, int nc);

@@ -69,7 +69,7 @@ _SIGS = {
     "icr_assemble": (C.c_int, [_P, _P, _I, _P, _I, _P, _P, _D, _D, _D, _D, _P, _P]),
     "icr_factor": (C.c_int, [_P]),
     "icr_get_factor_info": (C.c_int, [_P, C.POINTER(FactorInfo)]),
-    "icr_build_WH": (C.c_int, [_P, _I, _P, _P]),
+    "icr_build_WH": (C.c_int, [_P, _I, _P, _P, _P]),
     "icr_update_W": (C.c_int, [_P, _I, _P, _P, _P]),
     "icr_solve_contacts": (C.c_int, [_P, _I, _P, _P, _P, _D, _P, _P, _I, _D, _I, C.POINTER(_I),
                                      C.POINTER(_D)]),
@@ -216,10 +216,19 @@ class Scene:
         self._check(self.L.icr_set_candidates(self._h, len(nodes), _np_ptr(nodes), _np_ptr(mu)))
 
     # -- hot-path calls ------------------------------------------------------
-    def build_WH(self, node_ids, WH):
+    def build_WH(self, node_ids, WH, weights=None):
+        """Nodal contacts (node_ids [n_c]) or, with weights, mapped contacts
+        (node_ids and weights [n_c, 4], -1 = unused slot)."""
         t = self._torch
-        nc = node_ids.numel()
-        self._check(self.L.icr_build_WH(self._h, nc, _dptr(node_ids, t.int32),
+        if weights is None:
+            nc = node_ids.numel()
+            wp = None
+        else:
+            nc = node_ids.numel() // 4
+            if weights.numel() != 4 * nc or node_ids.numel() != 4 * nc:
+                raise ValueError("mapped contacts need node_ids and weights of 4 entries per contact")
+            wp = _dptr(weights, t.float64)
+        self._check(self.L.icr_build_WH(self._h, nc, _dptr(node_ids, t.int32), wp,
                                         _dptr(WH, t.float64, 9 * nc * nc)))
 
     def update_W(self, WH, Cm, W):

@@ -72,6 +72,61 @@ def box_grid(nx: int, ny: int, nz: int, s: float, jitter: float, rng: np.random.
     return nodes, tets, ijk
 
 
+def stacked_grids(nx: int, ny: int, nz_low: int, nz_up: int, s: float, jitter: float, rng: np.random.Generator):
+    """Two bodies stacked along z, each a jittered Kuhn-split node grid.
+
+    The lower body occupies z in [0, (nz_low - 1) s]; the upper body starts at
+    its top face.  The two interface layers hold separate nodes at identical
+    positions (the upper body's bottom layer copies the lower body's top layer,
+    whose jitter is in-face only), so the two meshes touch without sharing a
+    node and A is block diagonal.  Returns (nodes, tets, ijk, body, pairs):
+    ``body`` is 0 for the lower and 1 for the upper body; ``pairs[i]`` =
+    (lower node, upper node) at the same interface position, in grid order.
+    """
+    lo_nodes, lo_tets, lo_ijk = box_grid(nx, ny, nz_low, s, jitter, rng)
+    up_nodes, up_tets, up_ijk = box_grid(nx, ny, nz_up, s, jitter, rng)
+    up_nodes = up_nodes + np.array([0.0, 0.0, (nz_low - 1) * s])
+    top = np.nonzero(lo_ijk[:, 2] == nz_low - 1)[0]
+    bottom = np.nonzero(up_ijk[:, 2] == 0)[0]   # same (i, j) order as ``top``
+    up_nodes[bottom] = lo_nodes[top]
+    nl = len(lo_nodes)
+    nodes = np.concatenate([lo_nodes, up_nodes])
+    tets = np.concatenate([lo_tets, up_tets + nl]).astype(np.int32)
+    up_ijk = up_ijk + np.array([0, 0, nz_low - 1], dtype=np.int32)
+    ijk = np.concatenate([lo_ijk, up_ijk])
+    body = np.concatenate([np.zeros(nl, dtype=np.int32), np.ones(len(up_nodes), dtype=np.int32)])
+    pairs = np.stack([top, bottom + nl], axis=1).astype(np.int32)
+    return nodes, tets, ijk, body, pairs
+
+
+def interface_edge_points(nx: int, ny: int, pairs: np.ndarray, count: int, rng: np.random.Generator):
+    """``count`` points on edges of the interface triangulation (grid edges
+    along i and j and the cell diagonals of the Kuhn split), each given on
+    both bodies: slots (upper a, upper b, lower a, lower b) with weights
+    (w, 1 - w, -w, -(1 - w)), w ~ U[0.1, 0.9].  A point pairs the upper
+    body's position with the lower body's, x_1 - x_2 (the upper body is body
+    1).  Edges are drawn without replacement while they last, then again."""
+    edges = []
+    for j in range(ny):
+        for i in range(nx):
+            a = i + nx * j
+            if i + 1 < nx:
+                edges.append((a, a + 1))
+            if j + 1 < ny:
+                edges.append((a, a + nx))
+            if i + 1 < nx and j + 1 < ny:
+                edges.append((a, a + 1 + nx))
+    edges = np.array(edges, dtype=np.int64)
+    picks = []
+    while len(picks) < count:
+        picks.extend(rng.permutation(len(edges))[: count - len(picks)].tolist())
+    e = edges[np.array(picks)]
+    w = rng.uniform(0.1, 0.9, size=count)
+    ids = np.stack([pairs[e[:, 0], 1], pairs[e[:, 1], 1], pairs[e[:, 0], 0], pairs[e[:, 1], 0]], axis=1)
+    wts = np.stack([w, 1.0 - w, -w, -(1.0 - w)], axis=1)
+    return np.ascontiguousarray(ids.astype(np.int32)), np.ascontiguousarray(wts)
+
+
 def _signed_volumes(nodes, tets):
     x0 = nodes[tets[:, 0]]
     e = np.stack([nodes[tets[:, 1]] - x0, nodes[tets[:, 2]] - x0, nodes[tets[:, 3]] - x0], axis=2)

@@ -131,7 +131,7 @@ def test_build_WH_at_the_contact_limit():
     # the count is checked before any pointer is used (no 4.8 GB output needed)
     more = _cuda(rng.choice(free, size=nc + 1, replace=False).astype(np.int32))
     import ctypes
-    assert s.L.icr_build_WH(s._h, nc + 1, ctypes.c_void_p(more.data_ptr()), None) == icr.E_ARG
+    assert s.L.icr_build_WH(s._h, nc + 1, ctypes.c_void_p(more.data_ptr()), None, None) == icr.E_ARG
 
 
 def test_build_WH_rejects_clamped_node(medium):
@@ -141,6 +141,121 @@ def test_build_WH_rejects_clamped_node(medium):
     with pytest.raises(_icr().IcrError) as e:
         s.build_WH(_cuda(bad), WH)
     assert e.value.code == _icr().E_ARG
+
+
+def _stacked_scene(seed, nx=8, ny=8, nzl=5, nzu=5):
+    """Two bodies stacked along z (the lower one clamped at its bottom) as one
+    mesh of two components: A is block diagonal."""
+    from paper_2306_06946_amd.scenes import stacked_grids
+    rng = np.random.default_rng(seed)
+    nodes, tets, ijk, body, pairs = stacked_grids(nx, ny, nzl, nzu, 0.01, 0.2, rng)
+    return dict(nodes=nodes, tets=tets, E=np.full(len(tets), 1.0e4), nu_e=np.full(len(tets), 0.45), rho=1.0e3,
+                alpha=0.1, beta=0.1, h=0.01, gravity=np.array([0.0, 0.0, -9.81]),
+                fixed=((ijk[:, 2] == 0) & (body == 0)).astype(np.uint8), body=body, pairs=pairs, grid=(nx, ny))
+
+
+def _random_mapped_contacts(sc, nc, rng):
+    """nc points, each on 1-4 distinct nodes of a random tetrahedron with no
+    clamped node, weights of either sign; some slots left unused (-1)."""
+    free_tets = np.nonzero(np.all(sc["fixed"][sc["tets"]] == 0, axis=1))[0]
+    ids = np.full((nc, 4), -1, dtype=np.int32)
+    w = np.zeros((nc, 4))
+    for c in range(nc):
+        t = sc["tets"][rng.choice(free_tets)]
+        k = int(rng.integers(1, 5))
+        slots = rng.permutation(4)[:k]
+        ids[c, slots] = rng.permutation(t)[:k]
+        w[c, slots] = rng.dirichlet(np.ones(k)) * rng.choice([-1.0, 1.0])
+    return ids, w
+
+
+def test_build_WH_mapped_matches_oracle(medium):
+    """Points mapped from 1-4 nodes (Eq. 6), nodes shared between points,
+    weights of both signs: W_H = H A^-1 H^T at 1e-10, exactly symmetric."""
+    sc, s = medium
+    rng = np.random.default_rng(31)
+    nc = 150
+    ids, w = _random_mapped_contacts(sc, nc, rng)
+    _say(f"[gpu] build_WH mapped medium nc={nc}")
+    WH = torch.empty(9 * nc * nc, dtype=torch.float64, device="cuda")
+    s.build_WH(_cuda(ids.ravel()), WH, weights=_cuda(w.ravel()))
+    torch.cuda.synchronize()
+    got = WH.cpu().numpy().reshape(3 * nc, 3 * nc)
+    asm = O.assemble(sc)
+    ref = O.build_WH(O.CholeskyFactor(asm["A"]), ids, asm["n"], weights=w)
+    assert _rel(got, ref) <= 1e-10
+    assert np.array_equal(got, got.T)
+
+
+def test_build_WH_mapped_single_slots_equal_nodal(medium):
+    """One used slot of weight 1 per contact is the nodal mapping: the same
+    W_H bit for bit as the nodal call."""
+    sc, s = medium
+    rng = np.random.default_rng(32)
+    nodes_c = rng.choice(sc["candidates"], size=60, replace=False).astype(np.int32)
+    ids = np.full((60, 4), -1, dtype=np.int32)
+    w = np.zeros((60, 4))
+    slot = rng.integers(0, 4, size=60)
+    ids[np.arange(60), slot] = nodes_c
+    w[np.arange(60), slot] = 1.0
+    _say("[gpu] build_WH mapped single slots vs nodal")
+    W1 = torch.empty(9 * 60 * 60, dtype=torch.float64, device="cuda")
+    W2 = torch.empty_like(W1)
+    s.build_WH(_cuda(nodes_c), W1)
+    s.build_WH(_cuda(ids.ravel()), W2, weights=_cuda(w.ravel()))
+    torch.cuda.synchronize()
+    assert torch.equal(W1, W2)
+
+
+def test_build_WH_two_bodies_matches_oracle():
+    """Two stacked bodies (block-diagonal A): 300 interface points, each the
+    upper body's point minus the lower body's point on a shared interface edge
+    (H = [H_1, -H_2], Eq. 16-17).  W_H against the oracle at 1e-10; W_H is
+    rank deficient (300 points on 64 interface node pairs: rank <= 192) and
+    positive semidefinite."""
+    from paper_2306_06946_amd.scenes import interface_edge_points
+    icr = _icr()
+    sc = _stacked_scene(41)
+    _say("[gpu] build_WH two bodies: assemble+factor")
+    s = icr.Scene()
+    s.assemble(sc)
+    s.factor()
+    rng = np.random.default_rng(42)
+    nc = 300
+    ids, w = interface_edge_points(sc["grid"][0], sc["grid"][1], sc["pairs"], nc, rng)
+    _say(f"[gpu] build_WH two bodies nc={nc}")
+    WH = torch.empty(9 * nc * nc, dtype=torch.float64, device="cuda")
+    s.build_WH(_cuda(ids.ravel()), WH, weights=_cuda(w.ravel()))
+    torch.cuda.synchronize()
+    got = WH.cpu().numpy().reshape(3 * nc, 3 * nc)
+    asm = O.assemble(sc)
+    ref = O.build_WH(O.CholeskyFactor(asm["A"]), ids, asm["n"], weights=w)
+    assert _rel(got, ref) <= 1e-10
+    assert np.array_equal(got, got.T)
+    ev = np.linalg.eigvalsh(got)
+    assert ev[0] >= -1e-12 * ev[-1]
+    assert np.sum(ev > 1e-10 * ev[-1]) <= 3 * len(sc["pairs"])
+    s.close()
+
+
+def test_build_WH_mapped_rejects_bad_input(medium):
+    """Refused on the host: a clamped node, a zero weight on a used slot, a
+    node repeated inside one point, a point with no node."""
+    icr = _icr()
+    sc, s = medium
+    clamped = int(np.nonzero(sc["fixed"])[0][0])
+    free = sc["candidates"][:8].astype(np.int32)
+    cases = [
+        ([[clamped, -1, -1, -1]], [[1.0, 0, 0, 0]]),
+        ([[free[0], free[1], -1, -1]], [[1.0, 0.0, 0, 0]]),
+        ([[free[0], free[0], -1, -1]], [[0.5, 0.5, 0, 0]]),
+        ([[-1, -1, -1, -1]], [[1.0, 1.0, 1.0, 1.0]]),
+    ]
+    WH = torch.empty(9, dtype=torch.float64, device="cuda")
+    for ids, w in cases:
+        with pytest.raises(icr.IcrError) as e:
+            s.build_WH(_cuda(np.array(ids, dtype=np.int32).ravel()), WH, weights=_cuda(np.array(w, dtype=np.float64).ravel()))
+        assert e.value.code == icr.E_ARG
 
 
 @pytest.mark.parametrize("nc", [1, 16, 200, 1000])

@@ -641,3 +641,37 @@ def test_mapped_WH_equals_dense_inverse(tiny_sim):
                     Hd[3 * c + a, 3 * ids[c, k] + a] += w[c, k]
     ref = Hd @ np.linalg.inv(tiny_sim.asm["A"].toarray()) @ Hd.T
     assert np.linalg.norm(WH - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_two_body_WH_is_the_sum_of_the_bodies_compliances():
+    """Two stacked bodies in one mesh (block-diagonal A) with interface points
+    x_1 - x_2: the oracle's W_H equals H_1 A_1^-1 H_1^T + H_2 A_2^-1 H_2^T
+    (Eq. 17), each body assembled and inverted on its own, densely."""
+    from paper_2306_06946_amd.scenes import interface_edge_points, stacked_grids
+    rng = np.random.default_rng(43)
+    nodes, tets, ijk, body, pairs = stacked_grids(4, 4, 3, 3, 0.01, 0.2, rng)
+    base = dict(E=None, rho=1.0e3, alpha=0.1, beta=0.1, h=0.01, gravity=np.array([0.0, 0.0, -9.81]))
+    fixed = ((ijk[:, 2] == 0) & (body == 0)).astype(np.uint8)
+    sc = dict(base, nodes=nodes, tets=tets, E=np.full(len(tets), 1e4), nu_e=np.full(len(tets), 0.45), fixed=fixed)
+    ids, w = interface_edge_points(4, 4, pairs, 20, rng)
+    asm = O.assemble(sc)
+    WH = O.build_WH(O.CholeskyFactor(asm["A"]), ids, asm["n"], weights=w)
+    ref = np.zeros_like(WH)
+    for b in (1, 0):
+        keep = np.nonzero(body == b)[0]
+        new = -np.ones(len(nodes), dtype=np.int64)
+        new[keep] = np.arange(len(keep))
+        bt = tets[np.all(body[tets] == b, axis=1)]
+        sub = dict(base, nodes=nodes[keep], tets=new[bt].astype(np.int32), E=np.full(len(bt), 1e4),
+                   nu_e=np.full(len(bt), 0.45), fixed=fixed[keep])
+        Ab = O.assemble(sub)["A"].toarray()
+        Hb = np.zeros((3 * len(ids), 3 * len(keep)))
+        for c in range(len(ids)):
+            for k in range(4):
+                v = ids[c, k]
+                if body[v] == b:
+                    for a in range(3):
+                        Hb[3 * c + a, 3 * new[v] + a] += w[c, k]
+        assert np.all(np.sign(w[:, :2]) > 0) and np.all(np.sign(w[:, 2:]) < 0)
+        ref += Hb @ np.linalg.inv(Ab) @ Hb.T
+    assert np.linalg.norm(WH - ref) <= 1e-12 * np.linalg.norm(ref)
