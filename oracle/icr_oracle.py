@@ -59,7 +59,7 @@ import math
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
-from scipy.sparse.csgraph import reverse_cuthill_mckee
+from scipy.sparse.csgraph import breadth_first_order, reverse_cuthill_mckee
 
 SEPARATE, STICK, SLIP = 0, 1, 2
 
@@ -296,6 +296,53 @@ def build_WH(factor, nodes_c, n, columns=None, weights=None):
     return H @ Y
 
 
+def build_WH_schur(A, nodes_c):
+    """W_H = H A^{-1} H^T for nodal contacts (Eq. 28) as the inverse of a Schur complement.
+
+    For nodal contacts H selects the contact DOFs c, so W_H = (A^{-1})_cc, the
+    contact block of the inverse.  Order the DOFs with the contacts last (P A
+    P^T = [[A_rr, A_rc], [A_cr, A_cc]]); block elimination gives
+    (A^{-1})_cc = S^{-1} with the Schur complement S = A_cc - A_cr A_rr^{-1} A_rc,
+    and S = L_cc L_cc^T for the trailing block L_cc of the Cholesky factor of
+    P A P^T.  So W_H = L_cc^{-T} L_cc^{-1}, symmetrised (R15).  The remaining
+    nodes are ordered by breadth-first levels from the contact set, farthest
+    first, which keeps P A P^T banded for LAPACK's banded Cholesky.
+    Rows and columns come out in contact order, 3 per contact.
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    N = n // 3
+    nodes_c = np.asarray(nodes_c, dtype=np.int64)
+    Ac = A.tocoo()
+    G = sp.csr_matrix((np.ones(len(Ac.row)), (Ac.row // 3, Ac.col // 3)), shape=(N, N))
+    k = len(nodes_c)
+    link = sp.csr_matrix((np.ones(k), (nodes_c, np.zeros(k, dtype=np.int64))), shape=(N, 1))
+    Ge = sp.bmat([[G, link], [link.T, None]]).tocsr()           # node N joins every contact node
+    order = breadth_first_order(Ge, N, directed=False, return_predecessors=False)[1:]
+    seen = np.zeros(N, dtype=bool)
+    seen[order] = True
+    is_c = np.zeros(N, dtype=bool)
+    is_c[nodes_c] = True
+    rest = np.concatenate([np.nonzero(~seen)[0], order[~is_c[order]][::-1]])   # unreached = clamped nodes
+    perm = (3 * np.concatenate([rest, nodes_c])[:, None] + np.arange(3)[None, :]).ravel()
+    Ap = A[perm][:, perm].tocoo()
+    low = Ap.row >= Ap.col
+    r, c, v = Ap.row[low], Ap.col[low], Ap.data[low]
+    bw = int((r - c).max())
+    ab = np.zeros((bw + 1, n))
+    ab[r - c, c] = v
+    cb = sla.cholesky_banded(ab, lower=True, overwrite_ab=True, check_finite=False)
+    m = 3 * k
+    r0 = n - m
+    Lcc = np.zeros((m, m))
+    for d in range(min(bw + 1, m)):
+        j = np.arange(r0, n - d)
+        Lcc[j - r0 + d, j - r0] = cb[d, j]
+    Linv = sla.solve_triangular(Lcc, np.eye(m), lower=True, check_finite=False)
+    WH = Linv.T @ Linv
+    return 0.5 * (WH + WH.T)
+
+
 def rotation_blocks_apply(C, x):
     """Block-diagonal C (Eq. 26) times x: y_a = C_a x_a."""
     return np.einsum("aij,aj->ai", C, x.reshape(-1, 3)).ravel()
@@ -501,8 +548,8 @@ def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_s
                 record=None, margins=False):
     """Algorithm 3 with readings R8-R10.  Returns (f world force [nc,3], p, last C, lambda, info).
 
-    With ``margins``, each entry of ``info`` also holds the decision margins of
-    that iteration's last PGS sweep (``pgs``).
+    With ``margins``, each entry of ``info`` (and of ``record``) also holds the
+    decision margins of that iteration's last PGS sweep (``pgs``).
     """
     nc = len(p_free) // 3
     p = p_free.copy()
@@ -525,6 +572,8 @@ def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_s
         if record is not None:
             record.append(dict(C=C, W=W, d=dk, lam0=lam0, lam=lam.copy(), status=status.copy(), p=p.copy(),
                                sweeps=sweeps, eps=eps))
+            if margins:
+                record[-1]["margins"] = marg[0]
     return f, p, C, lam, info
 
 
@@ -633,7 +682,10 @@ class Simulation:
         self.mu_of_node = np.zeros(len(scene["nodes"]))
         self.mu_of_node[cand] = scene["cand_mu"]
 
-    def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False, margins=False):
+    def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False, margins=False,
+             wh="solve"):
+        """One time step.  ``wh`` = "solve" builds W_H by A^-1 H^T solves
+        (``build_WH``), "schur" by the Schur complement (``build_WH_schur``)."""
         sc = self.scene
         h = sc["h"]
         t0, t1 = self.t, self.t + h
@@ -652,7 +704,7 @@ class Simulation:
                                                t0, t1, mu, h, f_init, sc["n_newton"], ms, tl, sc["j_inner"],
                                                record)
         else:
-            WH = build_WH(self.factor, nodes_c, self.n)
+            WH = build_WH_schur(self.asm["A"], nodes_c) if wh == "schur" else build_WH(self.factor, nodes_c, self.n)
             out["WH"] = WH
             if per_constraint:
                 f, p, C, lam, info = newton_per_constraint(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h,

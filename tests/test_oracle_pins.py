@@ -150,6 +150,28 @@ def test_banded_factor_agrees_with_dense():
     assert np.linalg.norm(Xb - Xd) <= 1e-11 * np.linalg.norm(Xd)
 
 
+def test_WH_schur_complement_equals_dense_inverse(tiny_sim):
+    """W_H by the inverse of the Schur complement onto the contact DOFs equals
+    the contact block of numpy's dense inverse of A, in the given contact
+    order (unsorted ids included)."""
+    nodes_c = np.array([250, 251, 240, 255, 243, 17, 130])
+    WH = O.build_WH_schur(tiny_sim.asm["A"], nodes_c)
+    Ainv = np.linalg.inv(tiny_sim.asm["A"].toarray())
+    idx = (3 * nodes_c[:, None] + np.arange(3)).ravel()
+    ref = Ainv[np.ix_(idx, idx)]
+    assert np.linalg.norm(WH - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_WH_schur_complement_equals_solves_on_medium():
+    """The same on the medium mesh against W_H = H (A^-1 H^T) by banded solves."""
+    sc = make_scene("medium", 2)
+    asm = O.assemble(sc)
+    nodes_c = np.sort(np.random.default_rng(5).choice(sc["candidates"], size=120, replace=False))
+    ref = O.build_WH(O.CholeskyFactor(asm["A"]), nodes_c, asm["n"])
+    WH = O.build_WH_schur(asm["A"], nodes_c)
+    assert np.linalg.norm(WH - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
 def test_WH_equals_dense_inverse(tiny_sim):
     nodes_c = np.array([250, 251, 240, 255, 243])
     WH = O.build_WH(tiny_sim.factor, nodes_c, tiny_sim.n)
