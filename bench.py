@@ -176,48 +176,29 @@ def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
     return out
 
 
-def cpu_baseline(sc, sweeps, budget_cols):
-    """The FP64 oracle on a bounded sample of the same step.
-
-    W_H: a subset of its RHS columns by the oracle's banded solves, scaled to
-    all columns; Newton loop: the oracle's full loop at the same contact count
-    on a same-size SPD stand-in for W_H.  Setup (assembly, factor) excluded.
-    """
+def cpu_baseline(sc, sweeps):
+    """The FP64 oracle on the same step: the first time step of the
+    configuration's trajectory (the step the GPU's trajectory starts with),
+    run whole by the oracle -- free motion, contact selection, W_H (as the
+    inverse of the Schur complement onto the contact DOFs), the Newton loop
+    with the same sweep count, corrective motion and integration.  Set-up
+    (assembly, the banded factor of A for the single-RHS solves) is excluded
+    and reported beside it."""
     import oracle.icr_oracle as O
-    from paper_2306_06946_amd.scenes import random_spd
     t0 = time.perf_counter()
     sim = O.Simulation(sc)
     setup = time.perf_counter() - t0
-    h = sc["h"]
-    dv_free, q_free, _ = O.free_motion(sim.asm, sim.factor, sc, sim.q, sim.v, sim.q_rest)
-    nodes_c = O.select_contacts(q_free, sc, h)
-    nc = len(nodes_c)
-    m = 3 * nc
-    cols = np.linspace(0, m - 1, budget_cols).astype(np.int64)
     t0 = time.perf_counter()
-    O.build_WH(sim.factor, nodes_c, sim.n, columns=cols)
-    t_cols = time.perf_counter() - t0
-    t_wh = t_cols * m / len(cols)
-    # Newton loop on a same-size SPD stand-in for W_H (operation count of the
-    # loop does not depend on the values except through the PGS branch mix)
-    rng = np.random.default_rng(0)
-    WH = random_spd(m, rng) * 2e-3
-    H = O.mapping_H(nodes_c, sim.n)
-    p_free = H @ q_free
-    p_start = H @ sim.q
-    mu = sim.mu_of_node[nodes_c]
-    t0 = time.perf_counter()
-    O.newton_fast(WH, p_free, p_start, sc["obstacle"], 0.0, h, mu, h, np.zeros((nc, 3)), sc["n_newton"], sweeps,
-                  0.0, sc["j_inner"])
-    t_newton = time.perf_counter() - t0
-    per_step = t_wh + t_newton
+    out = sim.step(max_sweeps=sweeps, tol=0.0, wh="schur")
+    per_step = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
+    nc = len(out["nodes_c"])
     return dict(value=1.0 / per_step, unit="time-steps/s", cores=cores, kind="oracle",
-                sample=(f"W_H: {len(cols)} of {m} RHS columns by banded LAPACK solves ({t_cols:.1f} s, scaled x"
-                        f"{m / len(cols):.1f}); Newton loop: {sc['n_newton']} iterations x {sweeps} PGS sweeps at "
-                        f"n_c={nc} on a same-size SPD stand-in W_H ({t_newton:.1f} s); setup (assembly + banded "
-                        f"factor, {setup:.1f} s) excluded; BLAS threads = host cores"),
-                seconds_per_step=per_step, build_WH_s=t_wh, newton_s=t_newton)
+                sample=(f"one whole time step (the trajectory's first) of the same configuration: free motion, "
+                        f"selection of {nc} contacts, W_H {3 * nc}x{3 * nc} by the Schur complement, "
+                        f"{sc['n_newton']} Newton iterations x {sweeps} PGS sweeps, corrective motion; "
+                        f"set-up (assembly + banded factor, {setup:.1f} s) excluded; BLAS threads = host cores"),
+                seconds_per_step=per_step, setup_s=setup)
 
 
 def copy_probe(mib):
@@ -245,7 +226,6 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sweeps", type=int, default=30, help="PGS sweeps per Newton iteration (paper: 30)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=40)
     ap.add_argument("--standard-steps", type=int, default=20,
                     help="also time this many steps of the standard rebuild scheme (Algorithm 2); 0 = skip")
     ap.add_argument("--per-sweep-steps", type=int, default=0,
@@ -461,8 +441,8 @@ def main():
         out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots,
                                      seconds=args.serving_seconds)
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle sample)...")
-        out["cpu_baseline"] = cpu_baseline(sc, args.sweeps, args.cpu_cols)
+        log("[bench] cpu baseline (the oracle's first step)...")
+        out["cpu_baseline"] = cpu_baseline(sc, args.sweeps)
     print(json.dumps(out), flush=True)
 
 
