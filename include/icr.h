@@ -263,6 +263,12 @@ typedef struct {
  */
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep);
 
+/* Allocate now every device buffer that a time step (or icr_build_WH) with up
+ * to max_contacts nodal contacts uses, so that such calls allocate nothing
+ * later (serving admission charges these bytes).  ICR_E_STATE before
+ * icr_factor; ICR_E_ARG unless max_contacts is in [1, 4096]; ICR_E_OOM. */
+icr_status icr_reserve(icr_scene *s, int32_t max_contacts);
+
 /* Scene state, device buffers of n = 3N doubles (read / overwrite).
  * icr_set_state starts a new trajectory: it also clears the per-node contact
  * forces that warm-start the next step's PGS. */
@@ -302,18 +308,23 @@ icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int3
  * scene run in submission order; those of different scenes overlap on the
  * device.  A request runs exactly icr_step(scene, obstacle, opts, NULL) on
  * the slot's stream, so its results equal the same step run alone.
- * Scenes are admitted against a device-memory budget: the sum of the
- * admitted scenes' library-owned device bytes (icr_factor_info.device_bytes
- * at admission; admit a scene after one warm-up step so that its contact
- * and multi-RHS buffers are counted) may not exceed it.  Not thread-safe; the
- * server does not own the scenes (destroy them after the server).
+ * Scenes are admitted against a device-memory budget: admission first
+ * allocates every buffer the scene's steps use (icr_reserve for the contacts
+ * reserved before, else for its candidate count) and charges the scene's
+ * library-owned device bytes (icr_factor_info.device_bytes) after that, so
+ * that served steps allocate nothing; the sum may not exceed the budget.
+ * Not thread-safe; the server does not own the scenes (destroy them after
+ * the server).
  * ------------------------------------------------------------------------- */
 typedef struct icr_server icr_server;
 
 typedef struct {
   uint64_t tag;        /* the caller's request id (icr_server_submit) */
   int32_t scene;       /* scene id (icr_server_admit) */
-  int32_t status;      /* icr_status of the step */
+  int32_t status;      /* icr_status of the step: ICR_OK; ICR_WARN_NOT_CONVERGED when the request's
+                          tol > 0 and a Newton iteration's PGS ended with eps > tol (tol = 0 asks for a
+                          fixed sweep count); or the error of a launch that failed (the scene stays
+                          admitted and later requests run) */
   double latency_ms;   /* submission -> completion seen by icr_server_poll (host clock) */
   double queue_ms;     /* submission -> launch */
 } icr_completion;
@@ -329,11 +340,13 @@ const char *icr_server_last_error(const icr_server *srv);
 
 /* Admit a factored scene with candidates set; *scene_id receives its id.
  * Synchronises the device once (the scene's set-up work must be complete
- * before its steps run on the slot streams).  ICR_E_OOM (nothing admitted)
- * when it would exceed the budget.  While admitted, the scene's stream is
- * the slot stream of its last request: set it back (icr_set_stream) before
- * calling the scene directly, after its requests have completed.  Admission
- * also turns the scene's second stream off (icr_set_overlap(scene, 0)). */
+ * before its steps run on the slot streams).  ICR_E_OOM (nothing admitted;
+ * the scene keeps the buffers reserved for it) when it would exceed the
+ * budget.  A request runs on a slot's stream; when it completes (or its
+ * launch fails) the scene is set back to the stream it had at admission, so
+ * that direct calls on the scene after its requests have completed
+ * (icr_destroy included) run on its own stream.  Admission also turns the
+ * scene's second stream off (icr_set_overlap(scene, 0)). */
 icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id);
 /* Remove an idle scene (no request queued or in flight: else ICR_E_STATE);
  * its bytes return to the budget.  The scene itself is not destroyed. */
@@ -341,7 +354,10 @@ icr_status icr_server_evict(icr_server *srv, int32_t scene_id);
 /* Device bytes currently admitted (host out). */
 icr_status icr_server_used(const icr_server *srv, int64_t *bytes);
 
-/* Queue one time step of an admitted scene (obstacle and options copied). */
+/* Queue one time step of an admitted scene (obstacle and options copied).
+ * The request is checked as icr_step checks it (same error codes) and
+ * refused with ICR_E_ARG when n_contacts exceeds the contacts reserved at
+ * admission. */
 icr_status icr_server_submit(icr_server *srv, int32_t scene_id, const icr_obstacle *obs, const icr_step_opts *opt,
                              uint64_t tag);
 /* Launch what fits on free slots, then collect completed requests into

@@ -7,6 +7,7 @@
 #include <numeric>
 
 #include "scene.hpp"
+#include "server_hooks.hpp"
 
 using namespace icr;
 
@@ -597,6 +598,21 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
 
 namespace {
 
+// Preconditions of icr_step (throws the error icr_step returns).
+void check_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt) {
+  if (!s->factored) throw StateError("icr_step before icr_factor");
+  if (!s->has_candidates) throw StateError("icr_step before icr_set_candidates");
+  check_obstacle(obs);
+  REQUIRE(opt, "NULL options");
+  const int nc = opt->n_contacts;
+  REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
+  REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
+  REQUIRE(opt->n_newton >= 1 && opt->n_newton <= kMaxNewton, "n_newton must be in [1, 256]");
+  REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
+  REQUIRE(opt->scheme >= 0 && opt->scheme <= 2, "scheme must be 0 (fast), 1 (standard) or 2 (per constraint)");
+  REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");
+}
+
 // Enqueue one whole time step on s->stream.  With opt->timing, one-thread
 // kernels stamp the device clock between phases (slots 0..5 for the step,
 // 6 + 4k + j for Newton iteration k); stamps work the same in a replayed
@@ -674,17 +690,8 @@ bool same_opts(const icr_step_opts &a, const icr_step_opts &b) {
 
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep) {
   return guarded(s, [&] {
-    if (!s->factored) throw StateError("icr_step before icr_factor");
-    if (!s->has_candidates) throw StateError("icr_step before icr_set_candidates");
-    check_obstacle(obs);
-    REQUIRE(opt, "NULL options");
+    check_step(s, obs, opt);
     const int nc = opt->n_contacts;
-    REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
-    REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
-    REQUIRE(opt->n_newton >= 1 && opt->n_newton <= kMaxNewton, "n_newton must be in [1, 256]");
-    REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
-    REQUIRE(opt->scheme >= 0 && opt->scheme <= 2, "scheme must be 0 (fast), 1 (standard) or 2 (per constraint)");
-    REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");
     ensure_contact_buffers(s, nc);
     ensure_rhs_capacity(s, nc);
     hipStream_t st = s->stream;
@@ -759,6 +766,16 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
         }
       }
     }
+    return ICR_OK;
+  });
+}
+
+icr_status icr_reserve(icr_scene *s, int32_t max_contacts) {
+  return guarded(s, [&] {
+    if (!s->factored) throw StateError("icr_reserve before icr_factor");
+    REQUIRE(max_contacts >= 1 && max_contacts <= kPgsMaxContacts, "max_contacts must be in [1, 4096]");
+    ensure_contact_buffers(s, max_contacts);
+    ensure_rhs_capacity(s, max_contacts);
     return ICR_OK;
   });
 }
@@ -841,3 +858,30 @@ icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int3
 }
 
 }  // extern "C"
+
+namespace icr {
+
+icr_status check_step_request(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, std::string &msg) {
+  const icr_status st = guarded(s, [&] {
+    check_step(s, obs, opt);
+    return ICR_OK;
+  });
+  msg = s ? s->err : std::string("null scene");
+  return st;
+}
+
+icr_status enqueue_eps_readback(icr_scene *s, int n_newton, double *dst) {
+  return guarded(s, [&] {
+    REQUIRE(n_newton >= 1 && n_newton <= kMaxNewton && s->con.d_eps, "no Newton iterations to read");
+    ICR_HIP(hipMemcpyAsync(dst, s->con.d_eps, sizeof(double) * n_newton, hipMemcpyDeviceToHost, s->stream));
+    return ICR_OK;
+  });
+}
+
+int reserved_contacts(const icr_scene *s) { return s ? std::min(s->con.nc_cap, s->fac.nc_cap) : 0; }
+
+int candidate_count(const icr_scene *s) { return (s && s->has_candidates) ? s->con.count : 0; }
+
+void *scene_stream(const icr_scene *s) { return s ? (void *)s->stream : nullptr; }
+
+}  // namespace icr

@@ -78,6 +78,7 @@ _SIGS = {
     "icr_proximity_update": (C.c_int, [_P, _I, _P, _P, _P, _D, _P]),
     "icr_set_candidates": (C.c_int, [_P, _I, _P, _P]),
     "icr_step": (C.c_int, [_P, C.POINTER(Obstacle), C.POINTER(StepOpts), C.POINTER(StepReport)]),
+    "icr_reserve": (C.c_int, [_P, _I]),
     "icr_get_state": (C.c_int, [_P, _P, _P, C.POINTER(_D)]),
     "icr_set_state": (C.c_int, [_P, _P, _P, _D]),
     "icr_get_step_results": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -269,6 +270,9 @@ class Scene:
         out["sweeps"] = list(rep.sweeps)[:n_newton]
         out["eps"] = list(rep.eps)[:n_newton]
         return out
+
+    def reserve(self, max_contacts):
+        self._check(self.L.icr_reserve(self._h, int(max_contacts)))
 
     def get_state(self):
         t = self._torch

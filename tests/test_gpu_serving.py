@@ -105,6 +105,7 @@ def test_admission_budget_and_eviction():
     icr = _icr()
     a = icr.scene_from_dict(make_scene("serving", SEEDS[0]))
     b = icr.scene_from_dict(make_scene("serving", SEEDS[1]))
+    a.reserve(make_scene("serving", SEEDS[0])["n_contacts"])
     ba = a.factor_info()["device_bytes"]
     srv = icr.Server(hbm_budget=ba + 1, slots=2)
     ia = srv.admit(a)
@@ -117,6 +118,82 @@ def test_admission_budget_and_eviction():
     assert srv.used() == 0
     srv.admit(b)
     assert srv.used() == b.factor_info()["device_bytes"]
+    srv.close()
+
+
+def test_admission_charges_every_buffer_a_step_allocates():
+    """Scenes admitted before they ever stepped: admission reserves their step
+    buffers (for the candidate count, or what icr_reserve set) and charges
+    them; served steps of any allowed contact count then allocate nothing, so
+    the bytes charged are the bytes held.  A request above the reservation is
+    refused at submission."""
+    icr = _icr()
+    scs = [make_scene("serving", sd) for sd in SEEDS[:2]]
+    scenes = [icr.scene_from_dict(sc) for sc in scs]
+    scenes[1].reserve(scs[1]["n_contacts"])
+    srv = icr.Server(hbm_budget=64 << 30, slots=2)
+    ids = [srv.admit(s) for s in scenes]
+    charged = srv.used()
+    assert charged == sum(s.factor_info()["device_bytes"] for s in scenes)
+    tag = 0
+    for sid, sc in zip(ids, scs):
+        for nc in (sc["n_contacts"], max(1, sc["n_contacts"] // 2)):
+            srv.submit(sid, sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"], tag=tag)
+            tag += 1
+    done = []
+    while len(done) < tag:
+        out, _ = srv.poll(wait=True)
+        done += out
+    assert all(c["status"] == icr.OK for c in done)
+    assert sum(s.factor_info()["device_bytes"] for s in scenes) == charged
+    with pytest.raises(icr.IcrError) as e:
+        srv.submit(ids[1], scs[1]["obstacle"], scs[1]["n_contacts"] + 1, 5, 30, 0.0, 8)
+    assert e.value.code == icr.E_ARG
+    srv.close()
+
+
+def test_completion_status_and_failed_requests():
+    """Completions carry the step's status: ICR_WARN_NOT_CONVERGED for a
+    request whose PGS stopped above its tolerance, the error of a launch that
+    failed (here a scene re-assembled after its request was accepted, so the
+    step meets no factor: ICR_E_STATE) without holding up the other requests,
+    whose results equal the same steps run alone.  Invalid options are refused
+    at submission with icr_step's error."""
+    icr = _icr()
+    scs = [make_scene("serving", sd) for sd in SEEDS[:2]]
+    alone = _run_alone(scs[0], 2)
+    scenes = [icr.scene_from_dict(sc) for sc in scs]
+    srv = icr.Server(hbm_budget=64 << 30, slots=2)
+    ids = [srv.admit(s) for s in scenes]
+    sc0, sc1 = scs
+    with pytest.raises(icr.IcrError) as e:
+        srv.submit(ids[0], sc0["obstacle"], sc0["n_contacts"], 0, 30, 0.0, 8)
+    assert e.value.code == icr.E_ARG
+    # scene 1: one converged request, one that cannot converge in one sweep
+    srv.submit(ids[1], sc1["obstacle"], sc1["n_contacts"], sc1["n_newton"], 400, 1e-10, 8, tag=10)
+    srv.submit(ids[1], sc1["obstacle"], sc1["n_contacts"], sc1["n_newton"], 1, 1e-14, 8, tag=11)
+    srv.submit(ids[0], sc0["obstacle"], sc0["n_contacts"], sc0["n_newton"], 30, 0.0, sc0["j_inner"], tag=0)
+    got = {}
+    while len(got) < 3:
+        out, _ = srv.poll(wait=True)
+        got.update({c["tag"]: c["status"] for c in out})
+    assert got == {0: icr.OK, 10: icr.OK, 11: icr.WARN_NOT_CONVERGED}
+    # accepted while factored, launched after a re-assembly dropped the factor
+    srv.submit(ids[1], sc1["obstacle"], sc1["n_contacts"], sc1["n_newton"], 30, 0.0, 8, tag=12)
+    scenes[1].set_stream(torch.cuda.current_stream().cuda_stream)
+    scenes[1].assemble(sc1)
+    srv.submit(ids[0], sc0["obstacle"], sc0["n_contacts"], sc0["n_newton"], 30, 0.0, sc0["j_inner"], tag=1)
+    got = {}
+    while len(got) < 2:
+        out, _ = srv.poll(wait=True)
+        got.update({c["tag"]: c["status"] for c in out})
+    assert got == {12: icr.E_STATE, 1: icr.OK}
+    torch.cuda.synchronize()
+    scenes[0].set_stream(torch.cuda.current_stream().cuda_stream)
+    q, v, t = scenes[0].get_state()
+    lam = scenes[0].step_results(sc0["n_contacts"])["lam"]
+    torch.cuda.synchronize()
+    assert torch.equal(q.cpu(), alone[0]) and torch.equal(v.cpu(), alone[1]) and torch.equal(lam.cpu(), alone[2])
     srv.close()
 
 
