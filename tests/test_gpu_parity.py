@@ -258,6 +258,53 @@ def test_build_WH_mapped_rejects_bad_input(medium):
         assert e.value.code == icr.E_ARG
 
 
+def test_factor_reports_a_singular_system():
+    """A node that no tetrahedron references has no mass and no stiffness, so
+    A has a zero pivot: icr_factor returns ICR_E_NOT_SPD naming the column,
+    and the scene stays unfactored (icr_build_WH refuses with ICR_E_STATE)."""
+    icr = _icr()
+    sc = make_scene("tiny", 0)
+    nodes = np.vstack([sc["nodes"], [[0.5, 0.5, 0.5]]])
+    sc = dict(sc, nodes=nodes, fixed=np.append(sc["fixed"], 0).astype(np.uint8))
+    s = icr.Scene()
+    s.assemble(sc)
+    _say("[gpu] factor of a singular A")
+    with pytest.raises(icr.IcrError) as e:
+        s.factor()
+    assert e.value.code == icr.E_NOT_SPD
+    assert "column" in str(e.value)
+    WH = torch.empty(9, dtype=torch.float64, device="cuda")
+    with pytest.raises(icr.IcrError) as e:
+        s.build_WH(_cuda(np.array([5], dtype=np.int32)), WH)
+    assert e.value.code == icr.E_STATE
+    s.close()
+
+
+def test_solve_contacts_reports_non_convergence(tiny):
+    """PGS stopped by max_sweeps with eps above tol returns
+    ICR_WARN_NOT_CONVERGED; its results are those of the sweeps it ran (the
+    oracle's, same sweep count)."""
+    import ctypes
+    icr = _icr()
+    _, s = tiny
+    rng = np.random.default_rng(207)
+    nc = 40
+    W, d, mu, lam0 = random_contact_problem(nc, rng)
+    h = 0.01
+    lam = _cuda(lam0)
+    status = torch.empty(nc, dtype=torch.int8, device="cuda")
+    Wd, dd, mud = _cuda(W.ravel()), _cuda(d), _cuda(mu)
+    sw, ep = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _say("[gpu] solve_contacts, 2 sweeps, tol 1e-14")
+    code = s.L.icr_solve_contacts(s._h, nc, Wd.data_ptr(), dd.data_ptr(), mud.data_ptr(), h, lam.data_ptr(),
+                                  status.data_ptr(), 2, 1e-14, 8, ctypes.byref(sw), ctypes.byref(ep))
+    assert code == icr.WARN_NOT_CONVERGED
+    lam_ref, st_ref, sw_ref, eps_ref = O.pgs(W, d, mu, h, lam0, 2, 1e-14, 8)
+    assert sw.value == sw_ref == 2 and ep.value > 1e-14
+    assert np.array_equal(status.cpu().numpy(), st_ref)
+    assert _rel(lam.cpu().numpy(), lam_ref) <= 1e-10
+
+
 @pytest.mark.parametrize("nc", [1, 16, 200, 1000])
 def test_update_W_matches_oracle(nc, tiny):
     _, s = tiny

@@ -3,6 +3,8 @@ the nested-dissection / supernodal analysis."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -90,3 +92,35 @@ def test_null_scene_is_rejected():
     L = icr.lib()
     assert L.icr_factor(None) == icr.E_ARG
     assert L.icr_last_error(None) == b"null scene"
+
+
+def test_analysis_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The host analysis (graph, nested dissection, supernodal structure,
+    consistency check) built with -fsanitize=address,undefined and run on the
+    tiny and medium meshes and on two stacked bodies (two components)."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    from paper_2306_06946_amd.scenes import stacked_grids
+    exe = str(tmp_path / "analysis_check")
+    csrc = os.path.join(ROOT, "paper_2306_06946_amd", "csrc")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           os.path.join(csrc, "analysis.cpp"), os.path.join(ROOT, "tests", "host", "analysis_check.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    meshes = [make_scene("tiny", 0), make_scene("medium", 0)]
+    nodes, tets, _, _, _ = stacked_grids(6, 5, 4, 3, 0.01, 0.2, np.random.default_rng(3))
+    meshes.append(dict(nodes=nodes, tets=tets))
+    for k, sc in enumerate(meshes):
+        path = tmp_path / f"mesh{k}.bin"
+        with open(path, "wb") as f:
+            f.write(np.array([len(sc["nodes"]), len(sc["tets"])], dtype=np.int32).tobytes())
+            f.write(np.ascontiguousarray(sc["nodes"], dtype=np.float64).tobytes())
+            f.write(np.ascontiguousarray(sc["tets"], dtype=np.int32).tobytes())
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+                   UBSAN_OPTIONS="print_stacktrace=1")
+        r = subprocess.run([exe, str(path)], capture_output=True, text=True, env=env)
+        assert r.returncode == 0 and r.stdout.startswith("ok "), (r.stdout, r.stderr[-2000:])
+        a = icr.analyze(sc["nodes"], sc["tets"])
+        assert r.stdout.split()[1:] == [str(len(a["sup"])), str(len(a["rows"]))]
