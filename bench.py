@@ -231,6 +231,9 @@ def main():
     ap.add_argument("--per-sweep-steps", type=int, default=0,
                     help="also time this many steps with the directions updated after every PGS sweep "
                          "(n_newton x sweeps iterations of one sweep); 0 = skip")
+    ap.add_argument("--mixed-steps", type=int, default=20,
+                    help="also time this many steps in mixed precision (FP32 multi-RHS solve with 0 and 1 FP64-"
+                         "residual refinement steps, FP32 W_H / W storage) against the FP64 path; 0 = skip")
     ap.add_argument("--per-constraint-steps", type=int, default=0,
                     help="also time this many steps with the directions updated before every local solve; 0 = skip")
     ap.add_argument("--graph", action="store_true",
@@ -420,6 +423,35 @@ def main():
             "fast_ms_per_step": fp["ms_total"], "fast_metric_scope_ms": fp["ms_build_WH"] + fp["ms_newton"],
             "status_counts": [pr[-1]["n_separate"], pr[-1]["n_stick"], pr[-1]["n_slip"]],
         }
+    if args.mixed_steps > 0:
+        # mixed precision (FP32 solve + FP64-residual refinement, FP32 W_H / W)
+        # on the same trajectory, against the FP64 path of the same GPU: time
+        # per step and, on the trajectory's first step, errors against FP64
+        nms = min(args.mixed_steps, traj)
+        s.set_state(q0, v0, t_init)
+        one_step(True)
+        r64 = s.step_results(nc, with_WH=True)
+        res64 = {k: r64[k].cpu().numpy() for k in ("WH", "lam", "p")}
+        out["mixed_precision"] = {"steps": nms, "fp64_ms_per_step": ph["ms_total"],
+                                  "fp64_ms_build_WH": ph["ms_build_WH"], "fp64_ms_newton": ph["ms_newton"]}
+        for refine in (0, 1):
+            log(f"[bench] mixed precision, {refine} refinement step(s): {nms} steps...")
+            kw = dict(timing=True, graph=False, precision=icr.FP32_IR, refine=refine)
+            s.set_state(q0, v0, t_init)
+            s.step(sc["obstacle"], nc, n_newton, args.sweeps, 0.0, sc["j_inner"], **kw)
+            r32 = s.step_results(nc, with_WH=True)
+            err = {k: float(np.linalg.norm(r32[k].cpu().numpy() - res64[k]) / np.linalg.norm(res64[k]))
+                   for k in ("WH", "lam")}
+            s.set_state(q0, v0, t_init)
+            mr = [s.step(sc["obstacle"], nc, n_newton, args.sweeps, 0.0, sc["j_inner"], **kw) for _ in range(nms)]
+            keys = ("ms_total", "ms_build_WH", "ms_newton", "ms_update_W", "ms_pgs", "ms_corr")
+            mp = {k: float(np.mean([r[k] for r in mr])) for k in keys}
+            out["mixed_precision"][f"refine_{refine}"] = {
+                "ms_per_step": mp["ms_total"], "steps_per_s": 1e3 / mp["ms_total"], "ms_build_WH": mp["ms_build_WH"],
+                "ms_newton": mp["ms_newton"], "ms_update_W": mp["ms_update_W"], "ms_pgs": mp["ms_pgs"],
+                "metric_scope_steps_per_s": 1e3 / (mp["ms_build_WH"] + mp["ms_newton"]),
+                "rel_err_vs_fp64_first_step": err}
+        s.set_state(q0, v0, t_init)
     if args.per_constraint_steps > 0:
         # variant of the results section: directions updated before every
         # local solve (one-workgroup Gauss-Seidel on world-frame forces), same

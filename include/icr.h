@@ -47,6 +47,16 @@ typedef enum {
   ICR_E_STATE = -5            /* call order violated (e.g. build_WH before factor) */
 } icr_status;
 
+/* Arithmetic of a time step (icr_step_opts.precision). */
+typedef enum {
+  ICR_FP64 = 0,    /* every solve, product and store in FP64 */
+  ICR_FP32_IR = 1  /* the multi-RHS forward solve of W_H in FP32 (FP32 MFMA) followed by
+                      icr_step_opts.refine steps of iterative refinement whose residual
+                      P H^T - L Z is formed in FP64 against the FP64 factor, W_H = Z^T Z summed
+                      in FP64; W_H and W stored in FP32 for the Newton loop, every product
+                      with them and the PGS local solves accumulated in FP64 */
+} icr_precision;
+
 /* Contact status codes written by icr_solve_contacts / icr_step. */
 enum { ICR_SEPARATE = 0, ICR_STICK = 1, ICR_SLIP = 2 };
 
@@ -231,6 +241,8 @@ typedef struct {
                            p_a = p_free,a + h^2 (W_H f)_a, followed by Eq. 31 */
   int32_t graph;        /* 1: capture the step's launch sequence once (per options) as a HIP graph
                            and replay it; 0: launch every kernel eagerly.  Same results. */
+  int32_t precision;    /* icr_precision; ICR_FP32_IR needs scheme 0 */
+  int32_t refine;       /* refinement steps of ICR_FP32_IR, 0..2 (0: the raw FP32 solve) */
 } icr_step_opts;
 
 typedef struct {
@@ -264,10 +276,12 @@ typedef struct {
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep);
 
 /* Allocate now every device buffer that a time step (or icr_build_WH) with up
- * to max_contacts nodal contacts uses, so that such calls allocate nothing
- * later (serving admission charges these bytes).  ICR_E_STATE before
- * icr_factor; ICR_E_ARG unless max_contacts is in [1, 4096]; ICR_E_OOM. */
-icr_status icr_reserve(icr_scene *s, int32_t max_contacts);
+ * to max_contacts nodal contacts uses in the given icr_precision (ICR_FP32_IR
+ * adds the FP32 copy of the factor and the FP32 solve buffers), so that such
+ * calls allocate nothing later (serving admission charges these bytes).
+ * ICR_E_STATE before icr_factor; ICR_E_ARG unless max_contacts is in
+ * [1, 4096] and precision is an icr_precision; ICR_E_OOM. */
+icr_status icr_reserve(icr_scene *s, int32_t max_contacts, int32_t precision);
 
 /* Scene state, device buffers of n = 3N doubles (read / overwrite).
  * icr_set_state starts a new trajectory: it also clears the per-node contact
@@ -357,7 +371,8 @@ icr_status icr_server_used(const icr_server *srv, int64_t *bytes);
 /* Queue one time step of an admitted scene (obstacle and options copied).
  * The request is checked as icr_step checks it (same error codes) and
  * refused with ICR_E_ARG when n_contacts exceeds the contacts reserved at
- * admission. */
+ * admission, or when it asks for ICR_FP32_IR and the scene was not reserved
+ * for that precision (icr_reserve) before admission. */
 icr_status icr_server_submit(icr_server *srv, int32_t scene_id, const icr_obstacle *obs, const icr_step_opts *opt,
                              uint64_t tag);
 /* Launch what fits on free slots, then collect completed requests into

@@ -73,6 +73,8 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.d_f = C.arena.alloc<double>(m);
   C.d_WH = C.arena.alloc<double>(m * m);
   C.d_W = C.arena.alloc<double>(m * m);
+  C.d_WH32 = C.arena.alloc<float>(m * m);
+  C.d_W32 = C.arena.alloc<float>(m * m);
   C.pgs.g = C.arena.alloc<double>(m);
   C.pgs.Wss = C.arena.alloc<double>(pgs_wss_elems(nc));
   C.pgs.gnSet = C.arena.alloc<double>(nc);
@@ -206,6 +208,10 @@ void prepare_factor(icr_scene *s) {
   s->fac_arena.release();
   F.rhs_arena.release();
   F.nc_cap = 0;
+  F.fac32_arena.release();
+  F.have32 = false;
+  F.mixed_arena.release();
+  F.mixed_cap = 0;
   hipStream_t st = s->stream;
   auto &A = s->fac_arena;
   F.d_sup = A.upload(F.sup, st);
@@ -268,6 +274,8 @@ void icr_destroy(icr_scene *s) {
   s->con.arena.release();
   s->map_arena.release();
   s->fac.rhs_arena.release();
+  s->fac.fac32_arena.release();
+  s->fac.mixed_arena.release();
   s->fac_arena.release();
   s->mesh_arena.release();
   s->state_arena.release();
@@ -318,6 +326,10 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     s->map_nc_cap = s->map_nu_cap = 0;
     s->fac.rhs_arena.release();
     s->fac.nc_cap = 0;
+    s->fac.fac32_arena.release();
+    s->fac.have32 = false;
+    s->fac.mixed_arena.release();
+    s->fac.mixed_cap = 0;
     s->fac_arena.release();
     s->mesh_arena.release();
     s->state_arena.release();
@@ -444,7 +456,8 @@ icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out) {
     out->factor_flops = s->fac.flops;
     out->factor_ms = s->fac.ms;
     out->device_bytes = (int64_t)(s->mesh_arena.bytes + s->fac_arena.bytes + s->fac.rhs_arena.bytes +
-                                  s->state_arena.bytes + s->con.arena.bytes + s->map_arena.bytes);
+                                  s->state_arena.bytes + s->con.arena.bytes + s->map_arena.bytes +
+                                  s->fac.fac32_arena.bytes + s->fac.mixed_arena.bytes);
     return ICR_OK;
   });
 }
@@ -524,7 +537,7 @@ icr_status icr_update_W(icr_scene *s, int32_t n_c, const double *WH, const doubl
     REQUIRE(n_c >= 1, "n_c must be >= 1");
     REQUIRE(WH && C && W, "NULL device pointer");
     REQUIRE(W != WH, "W may not alias WH");
-    launch_update_W(s->stream, n_c, WH, C, W);
+    launch_update_W<double>(s->stream, n_c, WH, C, W);
     return ICR_OK;
   });
 }
@@ -539,7 +552,7 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
     REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
     REQUIRE(W && d && mu && lambda && status, "NULL device pointer");
     ensure_contact_buffers(s, std::max(n_c, 1));
-    launch_pgs(s->stream, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, s->con.d_sweeps,
+    launch_pgs<double>(s->stream, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, s->con.d_sweeps,
                s->con.d_eps, s->con.pgs);
     if (sweeps_out || eps_out) {
       int sw = 0;
@@ -561,7 +574,7 @@ icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, con
     REQUIRE(n_c >= 1, "n_c must be >= 1");
     REQUIRE(std::isfinite(h) && h > 0, "h must be positive");
     REQUIRE(WH && p_free && f && p, "NULL device pointer");
-    launch_proximity(s->stream, n_c, WH, p_free, f, h, p);
+    launch_proximity<double>(s->stream, n_c, WH, p_free, f, h, p);
     return ICR_OK;
   });
 }
@@ -611,6 +624,9 @@ void check_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt)
   REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
   REQUIRE(opt->scheme >= 0 && opt->scheme <= 2, "scheme must be 0 (fast), 1 (standard) or 2 (per constraint)");
   REQUIRE(opt->graph == 0 || opt->graph == 1, "graph must be 0 or 1");
+  REQUIRE(opt->precision == ICR_FP64 || opt->precision == ICR_FP32_IR, "precision must be ICR_FP64 or ICR_FP32_IR");
+  REQUIRE(opt->precision == ICR_FP64 || opt->scheme == 0, "ICR_FP32_IR runs the fast scheme (scheme 0) only");
+  REQUIRE(opt->refine >= 0 && opt->refine <= 2, "refine must be in [0, 2]");
 }
 
 // Enqueue one whole time step on s->stream.  With opt->timing, one-thread
@@ -638,10 +654,14 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   mark(ev, 1);
   launch_select_contacts(s, nc);
   mark(ev, 2);
-  if (!standard) build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
+  const bool mixed = opt->precision == ICR_FP32_IR;
+  if (mixed)
+    build_WH_mixed(s, nc, C.d_nodes_c, opt->refine, C.d_WH32, nullptr);
+  else if (!standard)
+    build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
   mark(ev, 3);
   // directions updated before every local solve: proximity of the warm start
-  if (per_constraint) launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
+  if (per_constraint) launch_proximity<double>(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
   for (int k = 0; k < nk; ++k) {
     if (per_constraint) {
       mark(kev, 4 * k);
@@ -649,7 +669,7 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
       launch_pgs_per_constraint(st, nc, S.d_ctx, C.d_WH, C.d_p, C.d_pstart, C.d_mu, h, C.d_f, C.d_C, C.d_lam,
                                 C.d_status, opt->max_sweeps, opt->tol, opt->j_inner, C.d_sweeps + k, C.d_eps + k);
       mark(kev, 4 * k + 2);
-      launch_proximity(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
+      launch_proximity<double>(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
       mark(kev, 4 * k + 3);
       continue;
     }
@@ -657,18 +677,26 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
     mark(kev, 4 * k);
     if (standard)
       build_WH_device(s, nc, C.d_nodes_c, C.d_W, false, C.d_C);   // W_k = J_k A^-1 J_k^T
+    else if (mixed)
+      launch_update_W<float>(st, nc, C.d_WH32, C.d_C, C.d_W32);
     else
-      launch_update_W(st, nc, C.d_WH, C.d_C, C.d_W);                // W_k = C_k W_H C_k^T
+      launch_update_W<double>(st, nc, C.d_WH, C.d_C, C.d_W);      // W_k = C_k W_H C_k^T
     mark(kev, 4 * k + 1);
-    launch_pgs(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner,
-               C.d_sweeps + k, C.d_eps + k, C.pgs);
+    if (mixed)
+      launch_pgs<float>(st, nc, C.d_W32, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol,
+                        opt->j_inner, C.d_sweeps + k, C.d_eps + k, C.pgs);
+    else
+      launch_pgs<double>(st, nc, C.d_W, C.d_dk, C.d_mu, h, C.d_lam, C.d_status, opt->max_sweeps, opt->tol,
+                         opt->j_inner, C.d_sweeps + k, C.d_eps + k, C.pgs);
     mark(kev, 4 * k + 2);
     if (standard) {
       launch_world_force(st, nc, C.d_C, C.d_lam, C.d_f);
       contact_force_solve(s, C.d_lam, S.d_sol);                      // A^-1 J_k^T lambda_k
       launch_standard_proximity(s, nc);                               // p_k = H (q_free + h^2 sol)
+    } else if (mixed) {
+      launch_world_force_proximity<float>(st, nc, C.d_C, C.d_lam, C.d_f, C.d_WH32, C.d_pfree, h, C.d_p);
     } else {
-      launch_world_force_proximity(st, nc, C.d_C, C.d_lam, C.d_f, C.d_WH, C.d_pfree, h, C.d_p);  // Eq. 31
+      launch_world_force_proximity<double>(st, nc, C.d_C, C.d_lam, C.d_f, C.d_WH, C.d_pfree, h, C.d_p);  // Eq. 31
     }
     mark(kev, 4 * k + 3);
   }
@@ -683,7 +711,8 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
 
 bool same_opts(const icr_step_opts &a, const icr_step_opts &b) {
   return a.n_contacts == b.n_contacts && a.n_newton == b.n_newton && a.max_sweeps == b.max_sweeps &&
-         a.j_inner == b.j_inner && a.tol == b.tol && a.timing == b.timing && a.scheme == b.scheme;
+         a.j_inner == b.j_inner && a.tol == b.tol && a.timing == b.timing && a.scheme == b.scheme &&
+         a.precision == b.precision && a.refine == b.refine;
 }
 
 }  // namespace
@@ -694,6 +723,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     const int nc = opt->n_contacts;
     ensure_contact_buffers(s, nc);
     ensure_rhs_capacity(s, nc);
+    if (opt->precision == ICR_FP32_IR) ensure_mixed(s);
     hipStream_t st = s->stream;
     auto &C = s->con;
     auto &S = s->st;
@@ -734,6 +764,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     S.t = S.t + s->mesh.h;
     s->stepped = true;
     s->last_nc = nc;
+    s->last_mixed = opt->precision == ICR_FP32_IR;
     if (rep) {
       std::memset(rep, 0, sizeof(*rep));
       rep->t = S.t;
@@ -770,12 +801,15 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
   });
 }
 
-icr_status icr_reserve(icr_scene *s, int32_t max_contacts) {
+icr_status icr_reserve(icr_scene *s, int32_t max_contacts, int32_t precision) {
   return guarded(s, [&] {
     if (!s->factored) throw StateError("icr_reserve before icr_factor");
     REQUIRE(max_contacts >= 1 && max_contacts <= kPgsMaxContacts, "max_contacts must be in [1, 4096]");
+    REQUIRE(precision == ICR_FP64 || precision == ICR_FP32_IR, "precision must be ICR_FP64 or ICR_FP32_IR");
     ensure_contact_buffers(s, max_contacts);
     ensure_rhs_capacity(s, max_contacts);
+    if (precision == ICR_FP32_IR) ensure_mixed(s);
+    ICR_HIP(hipStreamSynchronize(s->stream));
     return ICR_OK;
   });
 }
@@ -822,7 +856,10 @@ icr_status icr_get_step_results(icr_scene *s, int32_t *node_ids, double *q_free,
     cp(C, s->con.d_C, sizeof(double) * 9 * nc);
     cp(f, s->con.d_f, sizeof(double) * m);
     cp(status, s->con.d_status, nc);
-    cp(WH, s->con.d_WH, sizeof(double) * m * m);
+    if (WH && s->last_mixed)
+      launch_widen(s, s->con.d_WH32, WH, (long)(m * m));   // the step kept W_H in FP32
+    else
+      cp(WH, s->con.d_WH, sizeof(double) * m * m);
     return ICR_OK;
   });
 }
@@ -883,5 +920,7 @@ int reserved_contacts(const icr_scene *s) { return s ? std::min(s->con.nc_cap, s
 int candidate_count(const icr_scene *s) { return (s && s->has_candidates) ? s->con.count : 0; }
 
 void *scene_stream(const icr_scene *s) { return s ? (void *)s->stream : nullptr; }
+
+bool mixed_reserved(const icr_scene *s) { return s && s->fac.have32 && s->fac.mixed_cap == s->fac.nc_cap; }
 
 }  // namespace icr

@@ -151,23 +151,48 @@ __device__ inline void AccM::acc(const double *A, long ars, long acs, const doub
   }
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 MFMA per element type: FP64 (v_mfma_f64_16x16x4f64) or FP32
+// (v_mfma_f32_16x16x4f32).  Both take A(i, k) from lane i + 16 k and B(k, j)
+// from lane j + 16 k; they differ in where D(i, j) lands (checked on gfx950):
+// FP64 in lane j + 16 (i % 4), register i / 4; FP32 in lane j + 16 (i / 4),
+// register i % 4.
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef mfma_d4 V;
+  __device__ static V op(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef mfma_f4 V;
+  __device__ static V op(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
 // Generalised MFMA tile: 4 waves as 2x2, each (16 WB) x (16 WB) of 16x16
-// blocks, output tile T = 32 WB.  The K-chunk of A (T x KT) and B (KT x T)
-// is staged in LDS as [k][i] / [k][j] rows padded to T + 1 doubles (no bank
+// blocks, output tile T = 32 WB, element type E (double or float, operands
+// and accumulation alike).  The K-chunk of A (T x KC) and B (KC x T) is
+// staged in LDS as [k][i] / [k][j] rows padded to T + 1 elements (no bank
 // conflicts for either staging order or the MFMA operand reads), the next
 // chunk is prefetched into registers while the MFMAs of the current one run.
-template <int WB, int KC = KT>
+template <int WB, int KC = KT, class E = double>
 struct AccMT {
+  typedef E elem;
+  typedef typename Mfma<E>::V V;
   static constexpr int T = 32 * WB;
   static constexpr int TP = T + 1;
   static constexpr int NE = T * KC / 256;   // staged elements per thread and operand
-  static constexpr int LDS = 2 * KC * TP;   // doubles of LDS
-  mfma_d4 c[WB][WB];
+  static constexpr int LDS = 2 * KC * TP;   // elements of LDS
+  V c[WB][WB];
   __device__ void zero() {
 #pragma unroll
     for (int a = 0; a < WB; ++a)
 #pragma unroll
-      for (int b = 0; b < WB; ++b) c[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < WB; ++b) c[a][b] = V{0, 0, 0, 0};
   }
   // Thread tid stages, for every q < NE, element (i, k) of A: with rows
   // contiguous (AF) i = tid % T, k = tid / T + q (256 / T); else k = tid % KC,
@@ -175,9 +200,10 @@ struct AccMT {
   // operand and a constant stride per q.
   // c += A(i, k) B(k, j) over k in [k0, k1); A(i, k) = A[i ars + k acs],
   // B(k, j) = B[k brs + j bcs]; rows i < M and columns j < N of the tile.
-  template <bool AF, bool BF>
-  __device__ void acc(const double *A, long ars, long acs, const double *B, long brs, long bcs, int M, int N, int k0,
-                      int k1, double *lds) {
+  // TRI: A is lower triangular, A(i, k) = 0 for k > i + tri.
+  template <bool AF, bool BF, bool TRI = false>
+  __device__ void acc(const E *A, long ars, long acs, const E *B, long brs, long bcs, int M, int N, int k0, int k1,
+                      E *lds, int tri = 0) {
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63;
     const int r0 = (T / 2) * (w >> 1), c0 = (T / 2) * (w & 1);
@@ -188,18 +214,18 @@ struct AccMT {
     const int ia = AF ? tid % T : tid / KC, ka = AF ? tid / T : tid % KC;
     const int jb = BF ? tid % T : tid / KC, kbb = BF ? tid / T : tid % KC;
     const long qa = AF ? QS * acs : QK * ars, qb = BF ? QS * brs : QK * bcs;
-    const double *pa = A + (long)ia * ars + (long)(k0 + ka) * acs;
-    const double *pb = B + (long)(k0 + kbb) * brs + (long)jb * bcs;
-    double *sa = lds + ka * TP + ia, *sb = lds + KC * TP + kbb * TP + jb;
+    const E *pa = A + (long)ia * ars + (long)(k0 + ka) * acs;
+    const E *pb = B + (long)(k0 + kbb) * brs + (long)jb * bcs;
+    E *sa = lds + ka * TP + ia, *sb = lds + KC * TP + kbb * TP + jb;
     const int sqa = AF ? QS * TP : QK, sqb = BF ? QS * TP : QK;
-    double ra[NE], rb[NE];
+    E ra[NE], rb[NE];
     auto load = [&](int kb) {
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int i = AF ? ia : ia + QK * q, k = kb + (AF ? ka + QS * q : ka);
-        ra[q] = (i < M && k < k1) ? pa[q * qa] : 0.0;
+        ra[q] = (i < M && k < k1 && (!TRI || k <= i + tri)) ? pa[q * qa] : E(0);
         const int j = BF ? jb : jb + QK * q, kq = kb + (BF ? kbb + QS * q : kbb);
-        rb[q] = (j < N && kq < k1) ? pb[q * qb] : 0.0;
+        rb[q] = (j < N && kq < k1) ? pb[q * qb] : E(0);
       }
     };
     load(k0);
@@ -218,7 +244,7 @@ struct AccMT {
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
         const int k = kk + lk;
-        double av[WB], bv[WB];
+        E av[WB], bv[WB];
 #pragma unroll
         for (int a = 0; a < WB; ++a) av[a] = lds[k * TP + r0 + 16 * a + li];
 #pragma unroll
@@ -226,7 +252,7 @@ struct AccMT {
 #pragma unroll
         for (int a = 0; a < WB; ++a)
 #pragma unroll
-          for (int b = 0; b < WB; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+          for (int b = 0; b < WB; ++b) c[a][b] = Mfma<E>::op(av[a], bv[b], c[a][b]);
       }
       __syncthreads();
     }
@@ -240,10 +266,11 @@ struct AccMT {
 #pragma unroll
       for (int b = 0; b < WB; ++b)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) f(r0 + 16 * a + 4 * t + (l >> 4), c0 + 16 * b + (l & 15), c[a][b][t]);
+        for (int t = 0; t < 4; ++t) f(r0 + 16 * a + Mfma<E>::row(l, t), c0 + 16 * b + (l & 15), c[a][b][t]);
   }
 };
-typedef AccMT<2, 32> AccS;   // 64 x 64, K-chunk 32
+typedef AccMT<2, 32> AccS;          // 64 x 64 FP64, K-chunk 32
+typedef AccMT<2, 32, float> AccS32;  // 64 x 64 FP32, K-chunk 32
 
 // The tile accumulator of the factor kernels.
 typedef AccM Acc;

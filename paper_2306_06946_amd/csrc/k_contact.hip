@@ -226,8 +226,8 @@ __global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const doub
 // W_ab = C_a (W_H)_ab C_b^T.  Block (a, b) with a < b is computed as the
 // transpose of block (b, a) from the same inputs (W_H is exactly symmetric),
 // so W is exactly symmetric.
-__global__ void k_update_W(int nc, const double *__restrict__ WH, const double *__restrict__ C,
-                           double *__restrict__ W) {
+template <class TW>
+__global__ void k_update_W(int nc, const TW *__restrict__ WH, const double *__restrict__ C, TW *__restrict__ W) {
   long blk = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (blk >= (long)nc * nc) return;
   const int a = (int)(blk / nc), b = (int)(blk % nc);
@@ -236,7 +236,7 @@ __global__ void k_update_W(int nc, const double *__restrict__ WH, const double *
   double M[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
-      double v = WH[(3L * a + i) * m + 3L * b + j];
+      double v = (double)WH[(3L * a + i) * m + 3L * b + j];
       if (lower)
         M[i][j] = v;
       else
@@ -258,7 +258,7 @@ __global__ void k_update_W(int nc, const double *__restrict__ WH, const double *
         v = (i >= j) ? R[i][j] : R[j][i];
       else
         v = lower ? R[i][j] : R[j][i];
-      W[(3L * a + i) * m + 3L * b + j] = v;
+      W[(3L * a + i) * m + 3L * b + j] = (TW)v;
     }
 }
 
@@ -602,7 +602,8 @@ __device__ inline bool block_nonzero(const double *__restrict__ v, long c) {
 // With C given, the vector is the world-frame force f = C^T lambda of the
 // contacts (v is then ignored): every block forms the entries it needs from
 // C and lambda, and block 0 also writes f for all contacts to fout.
-__global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double *__restrict__ M,
+template <class TM>
+__global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const TM *__restrict__ M,
                                                            const double *__restrict__ x0,
                                                            const double *__restrict__ v, double h2,
                                                            double *__restrict__ y, const double *__restrict__ C,
@@ -649,9 +650,9 @@ __global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double 
       for (int q = wv; q < total; q += SG_NW) {
         const long r = 3L * list[q];
         const double v0 = C ? fl[3 * q] : v[r], v1 = C ? fl[3 * q + 1] : v[r + 1], v2 = C ? fl[3 * q + 2] : v[r + 2];
-        s = fma(M[r * m + i], v0, s);
-        s = fma(M[(r + 1) * m + i], v1, s);
-        s = fma(M[(r + 2) * m + i], v2, s);
+        s = fma((double)M[r * m + i], v0, s);
+        s = fma((double)M[(r + 1) * m + i], v1, s);
+        s = fma((double)M[(r + 2) * m + i], v2, s);
       }
     }
     __syncthreads();   // list and wsum are rewritten by the next chunk
@@ -675,7 +676,8 @@ __global__ __launch_bounds__(SG_NT) void k_sym_gemv_sparse(int nc, const double 
 constexpr int PGS_MAX_NC = 4096;
 // dynamic LDS of k_pgs_single: g[3 nc] doubles, then nz[nc] bytes
 __host__ __device__ inline size_t pgs_single_lds(int nc) { return (size_t)nc * (3 * sizeof(double) + 1); }
-__global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__restrict__ W,
+template <class TW>
+__global__ __launch_bounds__(1024) void k_pgs_single(int nc, const TW *__restrict__ W,
                                                      const double *__restrict__ d, const double *__restrict__ g0,
                                                      const double *__restrict__ mu, double h2,
                                                      double *__restrict__ lam, int8_t *__restrict__ status,
@@ -702,7 +704,7 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
   } else {
     for (int i = wv; i < m; i += 16) {
       double sacc = 0.0;
-      for (int j = ln; j < m; j += 64) sacc = fma(W[(long)i * m + j], lam[j], sacc);
+      for (int j = ln; j < m; j += 64) sacc = fma((double)W[(long)i * m + j], lam[j], sacc);
       for (int o = 32; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 64);
       if (ln == 0) g[i] = d[i] + h2 * sacc;
     }
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
           double w[3][3], lo[3], dd[3];
           for (int i = 0; i < 3; ++i) {
             lo[i] = lam[3 * next + i];
-            for (int j = 0; j < 3; ++j) w[i][j] = h2 * W[(3L * next + i) * m + 3L * next + j];
+            for (int j = 0; j < 3; ++j) w[i][j] = h2 * (double)W[(3L * next + i) * m + 3L * next + j];
           }
           for (int i = 0; i < 3; ++i)
             dd[i] = g[3 * next + i] - (w[i][0] * lo[0] + w[i][1] * lo[1] + w[i][2] * lo[2]);
@@ -765,9 +767,9 @@ __global__ __launch_bounds__(1024) void k_pgs_single(int nc, const double *__res
       if (cur >= nc) break;
       const double d0 = bc[0], d1 = bc[1], d2 = bc[2];
       if (d0 != 0.0 || d1 != 0.0 || d2 != 0.0) {
-        const double *r0 = W + (3L * cur) * m;
+        const TW *r0 = W + (3L * cur) * m;
         for (int i = tid; i < m; i += 1024)
-          g[i] += h2 * (r0[i] * d0 + r0[m + i] * d1 + r0[2L * m + i] * d2);
+          g[i] += h2 * ((double)r0[i] * d0 + (double)r0[m + i] * d1 + (double)r0[2L * m + i] * d2);
       }
       __syncthreads();
       a = cur + 1;
@@ -1199,7 +1201,8 @@ __device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds
 // block 0 writes S and |S|.  For a set of at most PGS_WAVE_MAX contacts the blocks then
 // write the blocked W~_SS with zero diagonal blocks, the per-contact records
 // and the gaps without the own term, e = g0 - W~_cc lambda_c.
-__global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__restrict__ W,
+template <class TW>
+__global__ __launch_bounds__(256) void k_pgs_gather(int nc, const TW *__restrict__ W,
                                                     const double *__restrict__ g0, const double *__restrict__ lam,
                                                     const double *__restrict__ mu, double h2,
                                                     int *__restrict__ Sidx_out, int *__restrict__ nS_out,
@@ -1215,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__rest
   const long stride = (long)gridDim.x * blockDim.x, t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long c = t0; c < nc; c += stride) {
     gnSet[c] = g0[3 * c];
-    swn[c] = sqrt(h2 * W[(3L * c) * m + 3L * c]);
+    swn[c] = sqrt(h2 * (double)W[(3L * c) * m + 3L * c]);
   }
   auto in_set = [&](int c) {
     return c < nc && (lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0 || g0[3 * c] < 0.0);
@@ -1255,14 +1258,14 @@ __global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__rest
     const long ic = e / PGS_BLK;
     const int c = (int)(ic % nsp), i = (int)(ic / nsp);
     double v = 0.0;
-    if (j < 9 && c < nS && c != i) v = h2 * W[(3L * Sidx[c] + j / 3) * m + 3L * Sidx[i] + j % 3];
+    if (j < 9 && c < nS && c != i) v = h2 * (double)W[(3L * Sidx[c] + j / 3) * m + 3L * Sidx[i] + j % 3];
     Wss[e] = v;
   }
   for (long i = t0; i < nS; i += stride) {
     double wb[3][3];
     const long ci = 3L * Sidx[i];
     for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q) wb[p][q] = h2 * W[(ci + p) * m + ci + q];
+      for (int q = 0; q < 3; ++q) wb[p][q] = h2 * (double)W[(ci + p) * m + ci + q];
     double tmp[19];
     make_record(wb, mu[Sidx[i]], tmp);
     for (int q = 0; q < 19; ++q) rec[PGS_RW * i + q] = tmp[q];
@@ -1271,12 +1274,13 @@ __global__ __launch_bounds__(256) void k_pgs_gather(int nc, const double *__rest
     const long cr = 3L * Sidx[r / 3];
     const int a = (int)(r % 3);
     double own = 0.0;
-    for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + a) * m + cr + q], lam[cr + q], own);
+    for (int q = 0; q < 3; ++q) own = fma(h2 * (double)W[(cr + a) * m + cr + q], lam[cr + q], own);
     gS[r] = g0[cr + a] - own;
   }
 }
 
-__global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__restrict__ W,
+template <class TW>
+__global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const TW *__restrict__ W,
                                                        const double *__restrict__ d, const double *__restrict__ g0,
                                                        const double *__restrict__ mu, double h2,
                                                        double *__restrict__ lam, int8_t *__restrict__ status,
@@ -1374,7 +1378,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           const long ic = e / PGS_BLK;
           const int c = (int)(ic % nsp), i = (int)(ic / nsp);
           double v = 0.0;
-          if (j < 9 && c < nS && c != i) v = h2 * W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
+          if (j < 9 && c < nS && c != i) v = h2 * (double)W[(3L * L.Sidx[c] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
           Wss[e] = v;
         }
       }
@@ -1384,7 +1388,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         double wb[3][3];
         const long ci = 3L * L.Sidx[i];
         for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q) wb[p][q] = h2 * W[(ci + p) * m + ci + q];
+          for (int q = 0; q < 3; ++q) wb[p][q] = h2 * (double)W[(ci + p) * m + ci + q];
         double *rc = L.rec + PGS_RW * i;
         double tmp[19];
         make_record(wb, mu[L.Sidx[i]], tmp);
@@ -1397,7 +1401,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         for (int r = tid; r < ldS; r += PGS_NT) {
           const long cr = 3L * L.Sidx[r / 3];
           double own = 0.0;
-          for (int q = 0; q < 3; ++q) own = fma(h2 * W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
+          for (int q = 0; q < 3; ++q) own = fma(h2 * (double)W[(cr + r % 3) * m + cr + q], L.lamS[r - r % 3 + q], own);
           L.gS[r] = g0[cr + r % 3] - own;
         }
       } else {
@@ -1426,7 +1430,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
           if (L.inS[c]) continue;
           double a = 0.0;
           for (int q = ln; q < ldS; q += 64)
-            a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], L.lamS[q], a);
+            a = fma(h2 * (double)W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], L.lamS[q], a);
           for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
           if (ln == 0) gnSet[c] = d[3 * c] + a;
         }
@@ -1531,7 +1535,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const double *__r
         double a = 0.0;
         for (int q = ln; q < ldS; q += 64) {
           const double lt = (L.Sidx[q / 3] < c) ? L.lamS[q] : L.lamS0[q];
-          a = fma(h2 * W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
+          a = fma(h2 * (double)W[(3L * c) * m + 3L * L.Sidx[q / 3] + q % 3], lt - L.lamSet[q], a);
         }
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
         if (ln == 0 && gnSet[c] + a < 0.0) {
@@ -1631,31 +1635,39 @@ void launch_directions(icr_scene *s, int nc, bool first) {
   ICR_LAUNCH_CHECK();
 }
 
-void launch_update_W(hipStream_t st, int nc, const double *WH, const double *Cm, double *W) {
+template <class TW>
+void launch_update_W(hipStream_t st, int nc, const TW *WH, const double *Cm, TW *W) {
   long nb = (long)nc * nc;
-  k_update_W<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nc, WH, Cm, W);
+  k_update_W<TW><<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nc, WH, Cm, W);
   ICR_LAUNCH_CHECK();
 }
+template void launch_update_W<double>(hipStream_t, int, const double *, const double *, double *);
+template void launch_update_W<float>(hipStream_t, int, const float *, const double *, float *);
 
-void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h, double *lam,
+template <class TW>
+void launch_pgs(hipStream_t st, int nc, const TW *W, const double *d, const double *mu, double h, double *lam,
                 int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev, double *eps_dev,
                 const PgsWork &wk) {
   const int m = 3 * nc;
   // g0 = d + W~ lambda over the contacts with a warm-start force
-  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g, nullptr, nullptr, nullptr);
+  k_sym_gemv_sparse<TW><<<cdiv(m, 64), SG_NT, 0, st>>>(nc, W, d, lam, h * h, wk.g, nullptr, nullptr, nullptr);
   ICR_LAUNCH_CHECK();
-  k_pgs_gather<<<512, 256, 0, st>>>(nc, W, wk.g, lam, mu, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn, wk.Wss, wk.rec,
+  k_pgs_gather<TW><<<512, 256, 0, st>>>(nc, W, wk.g, lam, mu, h * h, wk.Sidx, wk.nS, wk.gnSet, wk.swn, wk.Wss, wk.rec,
                                     wk.gS);
   ICR_LAUNCH_CHECK();
-  k_pgs_active<<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
+  k_pgs_active<TW><<<1, PGS_NT, sizeof(PgsLds), st>>>(nc, W, d, wk.g, mu, h * h, lam, status, max_sweeps, tol, j_inner,
                                                 sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl, wk.Sidx,
                                                 wk.nS, wk.rec, wk.gS);
   ICR_LAUNCH_CHECK();
   // continues only if the active set outgrew the compact path
-  k_pgs_single<<<1, 1024, pgs_single_lds(nc), st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
+  k_pgs_single<TW><<<1, 1024, pgs_single_lds(nc), st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
                                    eps_dev, wk.ctl);
   ICR_LAUNCH_CHECK();
 }
+template void launch_pgs<double>(hipStream_t, int, const double *, const double *, const double *, double, double *,
+                                 int8_t *, int, double, int, int *, double *, const PgsWork &);
+template void launch_pgs<float>(hipStream_t, int, const float *, const double *, const double *, double, double *,
+                                int8_t *, int, double, int, int *, double *, const PgsWork &);
 
 void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
                                const double *pstart, const double *mu, double h, double *f, double *Cm,
@@ -1675,9 +1687,13 @@ void pgs_prepare() {
   const unsigned long long bit = 1ull << (dev & 63);
   std::lock_guard<std::mutex> lock(mtx);
   if (done & bit) return;
-  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active, hipFuncAttributeMaxDynamicSharedMemorySize,
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
-  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single, hipFuncAttributeMaxDynamicSharedMemorySize,
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_active<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PgsLds)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pgs_single_lds(PGS_MAX_NC)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_single<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_single_lds(PGS_MAX_NC)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_pc, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_pc_lds(PGS_MAX_NC)));
@@ -1689,21 +1705,31 @@ void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *
   ICR_LAUNCH_CHECK();
 }
 
+template <class TW>
 void launch_world_force_proximity(hipStream_t st, int nc, const double *Cm, const double *lam, double *f,
-                                  const double *WH, const double *p_free, double h, double *p) {
+                                  const TW *WH, const double *p_free, double h, double *p) {
   const int m = 3 * nc;
   // f = C^T lambda and p = p_free + h^2 W_H f in one launch
-  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, nullptr, h * h, p, Cm, lam, f);
+  k_sym_gemv_sparse<TW><<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, nullptr, h * h, p, Cm, lam, f);
   ICR_LAUNCH_CHECK();
 }
+template void launch_world_force_proximity<double>(hipStream_t, int, const double *, const double *, double *,
+                                                   const double *, const double *, double, double *);
+template void launch_world_force_proximity<float>(hipStream_t, int, const double *, const double *, double *,
+                                                  const float *, const double *, double, double *);
 
-void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
+template <class TW>
+void launch_proximity(hipStream_t st, int nc, const TW *WH, const double *p_free, const double *f, double h,
                       double *p) {
   const int m = 3 * nc;
   // p = p_free + h^2 W_H f; f is zero at separated contacts
-  k_sym_gemv_sparse<<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, f, h * h, p, nullptr, nullptr, nullptr);
+  k_sym_gemv_sparse<TW><<<cdiv(m, 64), SG_NT, 0, st>>>(nc, WH, p_free, f, h * h, p, nullptr, nullptr, nullptr);
   ICR_LAUNCH_CHECK();
 }
+template void launch_proximity<double>(hipStream_t, int, const double *, const double *, const double *, double,
+                                       double *);
+template void launch_proximity<float>(hipStream_t, int, const float *, const double *, const double *, double,
+                                      double *);
 
 void launch_set_ctx(icr_scene *s, const icr_obstacle *obs, const double *t0) {
   icr_obstacle o{};

@@ -236,21 +236,30 @@ __global__ __launch_bounds__(PLAN_NT) void k_rhs_plan(int nc, const int *__restr
 // of an own contact is a unit vector of H^T (or a column of J^T = H^T C^T
 // when frames are given); a column of a contact below a child is the child's
 // below-row part extended into the front rows (extend-add through invmap).
-// Everything that identifies the column is uniform over the wave.
+// With a residual R (the correction solve of the refinement), the columns
+// carry R_s on the supernode's own rows instead of the unit vectors, plus
+// the children's parts.  Everything that identifies the column is uniform
+// over the wave.
+template <class E>
 __device__ inline void rhs_assemble_column(const SupDev *__restrict__ sup, int s, int jc, int l,
                                            const int *__restrict__ child, const int *__restrict__ invmap_off,
                                            const int *__restrict__ invmap, const int *__restrict__ lohi,
                                            const int *__restrict__ order, const int *__restrict__ node_ids,
                                            const int *__restrict__ iperm, const double *__restrict__ frames,
-                                           double *__restrict__ X) {
+                                           const double *__restrict__ R, E *__restrict__ X) {
   const SupDev S = sup[s];
   const int lo = lohi[3 * s], own = lohi[3 * s + 1], hi = lohi[3 * s + 2];
   const int r = 3 * (hi - lo);
   if (jc >= r) return;
-  const int f = 3 * (S.ncol + S.nb);
-  double *Xc = X + S.x_off + (long)jc * f;
+  const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
+  E *Xc = X + S.x_off + (long)jc * f;
+  const double *Rc = R ? R + S.z_off + (long)jc * n3 : nullptr;
   const int p = lo + jc / 3, a = jc % 3;
   if (p >= own) {
+    if (Rc) {
+      for (int i = l; i < f; i += 64) Xc[i] = (i < n3) ? E(Rc[i]) : E(0);
+      return;
+    }
     const int c = order[p];
     const int base = 3 * (iperm[node_ids[c]] - S.col0);
     for (int i = l; i < f; i += 64) {
@@ -259,7 +268,7 @@ __device__ inline void rhs_assemble_column(const SupDev *__restrict__ sup, int s
         v = (i == base + a) ? 1.0 : 0.0;
       else
         v = (i >= base && i < base + 3) ? frames[9L * c + 3 * a + (i - base)] : 0.0;
-      Xc[i] = v;
+      Xc[i] = E(v);
     }
     return;
   }
@@ -273,43 +282,51 @@ __device__ inline void rhs_assemble_column(const SupDev *__restrict__ sup, int s
     }
   }
   if (cc < 0) {   // not below any child (cannot happen for sorted contacts)
-    for (int i = l; i < f; i += 64) Xc[i] = 0.0;
+    for (int i = l; i < f; i += 64) Xc[i] = E(0);
     return;
   }
   const SupDev C = sup[child[S.child_off + cc]];
   const int fc = 3 * (C.ncol + C.nb);
   const int *im = invmap + invmap_off[S.child_off + cc];
-  const double *src = X + C.x_off + (long)(jc - 3 * (clo - lo)) * fc + 3 * C.ncol;
+  const E *src = X + C.x_off + (long)(jc - 3 * (clo - lo)) * fc + 3 * C.ncol;
   for (int i = l; i < f; i += 64) {
     const int ii = im[i / 3];
-    Xc[i] = (ii >= 0) ? src[3 * ii + i % 3] : 0.0;
+    E v = (ii >= 0) ? src[3 * ii + i % 3] : E(0);
+    if (Rc && i < n3) v += E(Rc[i]);
+    Xc[i] = v;
   }
 }
 
 // The product kernels take task blockIdx.x of their level's list; the grid is
 // the list's capacity and the workgroups past its length return after one
 // uniform load.
+template <class E>
 __global__ __launch_bounds__(256) void k_rhs_assemble(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
                                                       const int *__restrict__ ntask, const int *__restrict__ child,
                                                       const int *__restrict__ invmap_off,
                                                       const int *__restrict__ invmap, const int *__restrict__ lohi,
                                                       const int *__restrict__ order, const int *__restrict__ node_ids,
                                                       const int *__restrict__ iperm, const double *__restrict__ frames,
-                                                      double *__restrict__ X) {
+                                                      const double *__restrict__ R, E *__restrict__ X) {
   if ((int)blockIdx.x >= *ntask) return;
   const int2 tk = tasks[blockIdx.x];
-  rhs_assemble_column(sup, tk.x, 4 * (tk.y >> 16) + (threadIdx.x >> 6), threadIdx.x & 63, child, invmap_off, invmap,
-                      lohi, order, node_ids, iperm, frames, X);
+  rhs_assemble_column<E>(sup, tk.x, 4 * (tk.y >> 16) + (threadIdx.x >> 6), threadIdx.x & 63, child, invmap_off,
+                         invmap, lohi, order, node_ids, iperm, frames, R, X);
 }
 
-// Z_s = L_ss^{-1} X_s[:n_s], one 64x64 tile per task
+// Z_s = L_ss^{-1} X_s[:n_s], one 64x64 tile per task.  z64 (FP32 solves of
+// the mixed-precision build): 1 also stores the tile into the FP64 Z,
+// 2 adds it there (a refinement correction).
 template <class Ac>
 __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
                                                   const int *__restrict__ ntask, const int *__restrict__ lohi,
-                                                  const double *__restrict__ linv, const double *__restrict__ X,
-                                                  double *__restrict__ Z) {
+                                                  const typename Ac::elem *__restrict__ linv,
+                                                  const typename Ac::elem *__restrict__ X,
+                                                  typename Ac::elem *__restrict__ Z, double *__restrict__ Z64,
+                                                  int z64) {
+  typedef typename Ac::elem E;
   constexpr int T = Ac::T;
-  __shared__ double lds[Ac::LDS];
+  __shared__ E lds[Ac::LDS];
   if ((int)blockIdx.x >= *ntask) return;
   const int2 tk = tasks[blockIdx.x];
   const int s = tk.x;
@@ -324,9 +341,15 @@ __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup
   acc.zero();
   acc.template acc<true, false>(linv + S.linv_off + i0, 1, n3, X + S.x_off + (long)j0 * f, 1, f, M, N, 0, kend,
                                 lds);
-  double *Zs = Z + S.z_off;
-  acc.for_each([&](int i, int j, double v) {
-    if (i < M && j < N) Zs[(long)(i0 + i) + (long)(j0 + j) * n3] = v;
+  E *Zs = Z + S.z_off;
+  double *Z64s = Z64 ? Z64 + S.z_off : nullptr;
+  acc.for_each([&](int i, int j, E v) {
+    if (i < M && j < N) {
+      const long e = (long)(i0 + i) + (long)(j0 + j) * n3;
+      Zs[e] = v;
+      if (z64 == 1) Z64s[e] = (double)v;
+      if (z64 == 2) Z64s[e] += (double)v;
+    }
   });
 }
 
@@ -334,10 +357,12 @@ __global__ __launch_bounds__(256) void k_rhs_diag(const SupDev *__restrict__ sup
 template <class Ac>
 __global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
                                                  const int *__restrict__ ntask, const int *__restrict__ lohi,
-                                                 const double *__restrict__ front, const double *__restrict__ Z,
-                                                 double *__restrict__ X) {
+                                                 const typename Ac::elem *__restrict__ front,
+                                                 const typename Ac::elem *__restrict__ Z,
+                                                 typename Ac::elem *__restrict__ X) {
+  typedef typename Ac::elem E;
   constexpr int T = Ac::T;
-  __shared__ double lds[Ac::LDS];
+  __shared__ E lds[Ac::LDS];
   if ((int)blockIdx.x >= *ntask) return;
   const int2 tk = tasks[blockIdx.x];
   const int s = tk.x;
@@ -351,9 +376,42 @@ __global__ __launch_bounds__(256) void k_rhs_off(const SupDev *__restrict__ sup,
   acc.zero();
   acc.template acc<true, false>(front + S.front_off + n3 + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0,
                                 n3, lds);
-  double *Xs = X + S.x_off;
-  acc.for_each([&](int i, int j, double v) {
+  E *Xs = X + S.x_off;
+  acc.for_each([&](int i, int j, E v) {
     if (i < M && j < N) Xs[(long)(n3 + i0 + i) + (long)(j0 + j) * f] -= v;
+  });
+}
+
+// Residual of the forward solve on a supernode's own rows (FP64, the
+// refinement of the mixed-precision build): R_s = X_s[:n_s] - L_ss Z_s with
+// X_s assembled in FP64 from the unit columns and the children's FP64
+// updates; L_ss is the lower triangle of the front's diagonal block.
+template <class Ac>
+__global__ __launch_bounds__(256) void k_rhs_resid(const SupDev *__restrict__ sup, const int2 *__restrict__ tasks,
+                                                   const int *__restrict__ ntask, const int *__restrict__ lohi,
+                                                   const double *__restrict__ front, const double *__restrict__ X,
+                                                   const double *__restrict__ Z, double *__restrict__ R) {
+  constexpr int T = Ac::T;
+  __shared__ double lds[Ac::LDS];
+  if ((int)blockIdx.x >= *ntask) return;
+  const int2 tk = tasks[blockIdx.x];
+  const int s = tk.x;
+  const SupDev S = sup[s];
+  const int r = 3 * (lohi[3 * s + 2] - lohi[3 * s]);
+  const int n3 = 3 * S.ncol, f = 3 * (S.ncol + S.nb);
+  const int i0 = T * (tk.y >> 16), j0 = T * (tk.y & 0xffff);
+  if (i0 >= n3 || j0 >= r) return;
+  const int M = min(T, n3 - i0), N = min(T, r - j0);
+  const int kend = min(n3, i0 + T);
+  Ac acc;
+  acc.zero();
+  // A(i, k) = L_ss(i0 + i, k), zero above the diagonal (k > i0 + i)
+  acc.template acc<true, false, true>(front + S.front_off + i0, 1, f, Z + S.z_off + (long)j0 * n3, 1, n3, M, N, 0,
+                                      kend, lds, i0);
+  const double *Xs = X + S.x_off;
+  double *Rs = R + S.z_off;
+  acc.for_each([&](int i, int j, double v) {
+    if (i < M && j < N) Rs[(long)(i0 + i) + (long)(j0 + j) * n3] = Xs[(long)(i0 + i) + (long)(j0 + j) * f] - v;
   });
 }
 
@@ -414,13 +472,24 @@ __global__ __launch_bounds__(256) void k_wp_mirror(int m, double *__restrict__ W
 
 // W_H[3c+a][3c'+b] = Wp[3 pos(c) + a][3 pos(c') + b] (Wp symmetric): one
 // block per output row, the source row stays in cache.
+template <class TW>
 __global__ __launch_bounds__(256) void k_wh_unpermute(int nc, const int *__restrict__ pos, const double *__restrict__ Wp,
-                                                      double *__restrict__ WH) {
+                                                      TW *__restrict__ WH) {
   const int m = 3 * nc;
   const int i = blockIdx.x;
   const double *src = Wp + (long)(3 * pos[i / 3] + i % 3) * m;
-  double *dst = WH + (long)i * m;
-  for (int j = threadIdx.x; j < m; j += 256) dst[j] = src[3 * pos[j / 3] + j % 3];
+  TW *dst = WH + (long)i * m;
+  for (int j = threadIdx.x; j < m; j += 256) dst[j] = (TW)src[3 * pos[j / 3] + j % 3];
+}
+
+__global__ void k_to_float(long n, const double *__restrict__ x, float *__restrict__ y) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+__global__ void k_to_double(long n, const float *__restrict__ x, double *__restrict__ y) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
 }
 
 // Mapped contacts (Eq. 6): contact a is the point sum_k w_ak x(u_ak) over up
@@ -755,6 +824,11 @@ void launch_wh_expand(hipStream_t st, int nc, int nu, const int *idx, const doub
   ICR_LAUNCH_CHECK();
 }
 
+void launch_widen(icr_scene *s, const float *x, double *y, long n) {
+  k_to_double<<<(unsigned)std::min<long>(1024, (n + 255) / 256), 256, 0, s->stream>>>(n, x, y);
+  ICR_LAUNCH_CHECK();
+}
+
 void launch_fill(icr_scene *s, double *x, long n, double v) {
   k_fill<<<(unsigned)std::min<long>(1024, (n + 255) / 256), 256, 0, s->stream>>>(n, v, x);
   ICR_LAUNCH_CHECK();
@@ -783,6 +857,10 @@ void ensure_rhs_capacity(icr_scene *s, int nc) {
   }
   F.d_X = F.rhs_arena.alloc<double>(xo);
   F.d_Z = F.rhs_arena.alloc<double>(zo);
+  F.x_elems = xo;
+  F.z_elems = zo;
+  F.mixed_arena.release();   // sized for the previous offsets
+  F.mixed_cap = 0;
   {
     // task-list capacities per (level, kind): the counts at r = rmax
     const int nlev = (int)F.levels.size();
@@ -849,7 +927,11 @@ void ensure_rhs_capacity(icr_scene *s, int nc) {
   F.nc_cap = nc;
 }
 
-void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate, const double *frames) {
+namespace {
+
+// Contact order and the task lists of every tree level (shared by the FP64
+// and the mixed-precision builds).
+void rhs_prepare(icr_scene *s, int nc, const int *node_ids, bool validate) {
   auto &F = s->fac;
   hipStream_t st = s->stream;
   const int nsup = (int)F.sup.size();
@@ -865,19 +947,95 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
   ICR_LAUNCH_CHECK();
   k_fill<<<1024, 256, 0, st>>>(m * m, 0.0, F.d_Wp);
   ICR_LAUNCH_CHECK();
-  // grid of a product launch: its list's capacity (one workgroup per task;
-  // the hardware keeps scheduling workgroups of both streams' launches)
-  auto grid = [&](int l, int k) { return (unsigned)std::max(1, F.rhs_cap[RHS_KINDS * l + k]); };
-  auto list = [&](int l, int k) { return F.d_rhs_tasks + F.rhs_off[RHS_KINDS * l + k]; };
-  auto count = [&](int l, int k) { return F.d_rhs_cnt + RHS_KINDS * l + k; };
-  for (int l = 0; l < nlev; ++l) {
-    if (F.rhs_cap[RHS_KINDS * l + RT_ASM] == 0) continue;   // no supernode of the level can hold a contact column
-    k_rhs_assemble<<<grid(l, RT_ASM), 256, 0, st>>>(F.d_sup, list(l, RT_ASM), count(l, RT_ASM), F.d_child,
-                                                    F.d_invmap_off, F.d_invmap, F.d_lohi, F.d_order, node_ids,
-                                                    F.d_iperm, frames, F.d_X);
+}
+
+// Launch geometry of a product: its list's capacity (one workgroup per task;
+// the hardware keeps scheduling workgroups of both streams' launches).
+struct RhsLists {
+  const Factor &F;
+  unsigned grid(int l, int k) const { return (unsigned)std::max(1, F.rhs_cap[RHS_KINDS * l + k]); }
+  const int2 *list(int l, int k) const { return F.d_rhs_tasks + F.rhs_off[RHS_KINDS * l + k]; }
+  const int *count(int l, int k) const { return F.d_rhs_cnt + RHS_KINDS * l + k; }
+  bool any(int l, int k) const { return F.rhs_cap[RHS_KINDS * l + k] > 0; }
+};
+
+// Wp (mirrored) -> W_H in contact order, FP64 or FP32.
+template <class TW>
+void wh_finish(icr_scene *s, int nc, TW *WH) {
+  auto &F = s->fac;
+  const long long m = 3LL * nc;
+  const int nt = cdiv(m, 64);
+  k_wp_mirror<<<nt * (nt + 1) / 2, 256, 0, s->stream>>>((int)m, F.d_Wp);
+  ICR_LAUNCH_CHECK();
+  k_wh_unpermute<TW><<<(unsigned)m, 256, 0, s->stream>>>(nc, F.d_pos, F.d_Wp, WH);
+  ICR_LAUNCH_CHECK();
+}
+
+// One forward sweep over the tree levels in FP32 (the bulk solve of the
+// mixed-precision build): X32 assembled from the unit columns (R null) or
+// from the residual R and the children, Z32 = L_ss^-1 X32 with its FP64 copy
+// stored (z64 = 1) or added (z64 = 2) into Z, X32 below rows -= L_21 Z32.
+void forward_fp32(icr_scene *s, const int *node_ids, const double *R, int z64) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  RhsLists L{F};
+  for (int l = 0; l < (int)F.levels.size(); ++l) {
+    if (!L.any(l, RT_ASM)) continue;
+    k_rhs_assemble<float><<<L.grid(l, RT_ASM), 256, 0, st>>>(F.d_sup, L.list(l, RT_ASM), L.count(l, RT_ASM),
+                                                             F.d_child, F.d_invmap_off, F.d_invmap, F.d_lohi,
+                                                             F.d_order, node_ids, F.d_iperm, nullptr, R, F.d_X32);
     ICR_LAUNCH_CHECK();
-    k_rhs_diag<AccS><<<grid(l, RT_DIAG), 256, 0, st>>>(F.d_sup, list(l, RT_DIAG), count(l, RT_DIAG), F.d_lohi,
-                                                       F.d_linv, F.d_X, F.d_Z);
+    k_rhs_diag<AccS32><<<L.grid(l, RT_DIAG), 256, 0, st>>>(F.d_sup, L.list(l, RT_DIAG), L.count(l, RT_DIAG),
+                                                           F.d_lohi, F.d_linv32, F.d_X32, F.d_Z32, F.d_Z, z64);
+    ICR_LAUNCH_CHECK();
+    if (L.any(l, RT_OFF)) {
+      k_rhs_off<AccS32><<<L.grid(l, RT_OFF), 256, 0, st>>>(F.d_sup, L.list(l, RT_OFF), L.count(l, RT_OFF), F.d_lohi,
+                                                           F.d_front32, F.d_Z32, F.d_X32);
+      ICR_LAUNCH_CHECK();
+    }
+  }
+}
+
+}  // namespace
+
+void ensure_mixed(icr_scene *s) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  if (!F.have32) {
+    F.fac32_arena.release();
+    F.d_front32 = F.fac32_arena.alloc<float>(F.front_elems);
+    F.d_linv32 = F.fac32_arena.alloc<float>(F.linv_elems);
+    k_to_float<<<2048, 256, 0, st>>>(F.front_elems, F.d_front, F.d_front32);
+    ICR_LAUNCH_CHECK();
+    k_to_float<<<2048, 256, 0, st>>>(F.linv_elems, F.d_linv, F.d_linv32);
+    ICR_LAUNCH_CHECK();
+    F.have32 = true;
+  }
+  if (F.mixed_cap != F.nc_cap) {
+    ICR_HIP(hipStreamSynchronize(st));
+    F.mixed_arena.release();
+    F.d_X32 = F.mixed_arena.alloc<float>(F.x_elems);
+    F.d_Z32 = F.mixed_arena.alloc<float>(F.z_elems);
+    F.d_R = F.mixed_arena.alloc<double>(F.z_elems);
+    F.mixed_cap = F.nc_cap;
+  }
+}
+
+void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate, const double *frames) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  const long long m = 3LL * nc;
+  rhs_prepare(s, nc, node_ids, validate);
+  RhsLists L{F};
+  for (int l = 0; l < (int)F.levels.size(); ++l) {
+    if (!L.any(l, RT_ASM)) continue;   // no supernode of the level can hold a contact column
+    k_rhs_assemble<double><<<L.grid(l, RT_ASM), 256, 0, st>>>(F.d_sup, L.list(l, RT_ASM), L.count(l, RT_ASM),
+                                                              F.d_child, F.d_invmap_off, F.d_invmap, F.d_lohi,
+                                                              F.d_order, node_ids, F.d_iperm, frames, nullptr,
+                                                              F.d_X);
+    ICR_LAUNCH_CHECK();
+    k_rhs_diag<AccS><<<L.grid(l, RT_DIAG), 256, 0, st>>>(F.d_sup, L.list(l, RT_DIAG), L.count(l, RT_DIAG), F.d_lohi,
+                                                         F.d_linv, F.d_X, F.d_Z, nullptr, 0);
     ICR_LAUNCH_CHECK();
     // Z of this level is final: its W_H products go to the side stream (they
     // read Z and write Wp only, which nothing on the main stream touches
@@ -888,12 +1046,12 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
       ICR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
       sy = s->side;
     }
-    k_rhs_syrk<AccS><<<grid(l, RT_SYRK), 256, 0, sy>>>(F.d_sup, list(l, RT_SYRK), count(l, RT_SYRK), F.d_lohi,
-                                                       F.d_Z, (int)m, F.d_Wp);
+    k_rhs_syrk<AccS><<<L.grid(l, RT_SYRK), 256, 0, sy>>>(F.d_sup, L.list(l, RT_SYRK), L.count(l, RT_SYRK), F.d_lohi,
+                                                         F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
-    if (F.rhs_cap[RHS_KINDS * l + RT_OFF] > 0) {
-      k_rhs_off<AccS><<<grid(l, RT_OFF), 256, 0, st>>>(F.d_sup, list(l, RT_OFF), count(l, RT_OFF), F.d_lohi,
-                                                       F.d_front, F.d_Z, F.d_X);
+    if (L.any(l, RT_OFF)) {
+      k_rhs_off<AccS><<<L.grid(l, RT_OFF), 256, 0, st>>>(F.d_sup, L.list(l, RT_OFF), L.count(l, RT_OFF), F.d_lohi,
+                                                         F.d_front, F.d_Z, F.d_X);
       ICR_LAUNCH_CHECK();
     }
   }
@@ -901,13 +1059,48 @@ void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool
     ICR_HIP(hipEventRecord(s->ev_join, s->side));
     ICR_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
   }
-  {
-    const int nt = cdiv(m, 64);
-    k_wp_mirror<<<nt * (nt + 1) / 2, 256, 0, st>>>((int)m, F.d_Wp);
+  wh_finish<double>(s, nc, WH);
+}
+
+void build_WH_mixed(icr_scene *s, int nc, const int *node_ids, int refine, float *WH32, double *WH64) {
+  auto &F = s->fac;
+  hipStream_t st = s->stream;
+  const long long m = 3LL * nc;
+  rhs_prepare(s, nc, node_ids, false);
+  RhsLists L{F};
+  forward_fp32(s, node_ids, nullptr, 1);   // Z32 and its FP64 copy Z
+  for (int it = 0; it < refine; ++it) {
+    // FP64 residual of L Z = P H^T on every supernode's rows, level by level
+    for (int l = 0; l < (int)F.levels.size(); ++l) {
+      if (!L.any(l, RT_ASM)) continue;
+      k_rhs_assemble<double><<<L.grid(l, RT_ASM), 256, 0, st>>>(F.d_sup, L.list(l, RT_ASM), L.count(l, RT_ASM),
+                                                                F.d_child, F.d_invmap_off, F.d_invmap, F.d_lohi,
+                                                                F.d_order, node_ids, F.d_iperm, nullptr, nullptr,
+                                                                F.d_X);
+      ICR_LAUNCH_CHECK();
+      k_rhs_resid<AccS><<<L.grid(l, RT_DIAG), 256, 0, st>>>(F.d_sup, L.list(l, RT_DIAG), L.count(l, RT_DIAG),
+                                                            F.d_lohi, F.d_front, F.d_X, F.d_Z, F.d_R);
+      ICR_LAUNCH_CHECK();
+      if (L.any(l, RT_OFF)) {
+        k_rhs_off<AccS><<<L.grid(l, RT_OFF), 256, 0, st>>>(F.d_sup, L.list(l, RT_OFF), L.count(l, RT_OFF), F.d_lohi,
+                                                           F.d_front, F.d_Z, F.d_X);
+        ICR_LAUNCH_CHECK();
+      }
+    }
+    forward_fp32(s, node_ids, F.d_R, 2);   // Z += L^-1 R (FP32 solve of the correction)
+  }
+  // W_H = Z^T Z in FP64 from the refined Z
+  for (int l = 0; l < (int)F.levels.size(); ++l) {
+    if (!L.any(l, RT_ASM)) continue;
+    k_rhs_syrk<AccS><<<L.grid(l, RT_SYRK), 256, 0, st>>>(F.d_sup, L.list(l, RT_SYRK), L.count(l, RT_SYRK), F.d_lohi,
+                                                         F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
   }
-  k_wh_unpermute<<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH);
-  ICR_LAUNCH_CHECK();
+  if (WH32) wh_finish<float>(s, nc, WH32);
+  if (WH64) {
+    k_wh_unpermute<double><<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH64);   // Wp already mirrored
+    ICR_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace icr

@@ -87,7 +87,7 @@ extern "C" icr_status icr_solve_contacts_noalloc(void *stream, int32_t n_c, cons
     int *sweeps_dev = ints + kIntSweeps;
     double *eps_dev = base + kOffEps;
     pgs_prepare();
-    launch_pgs(st, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, sweeps_dev, eps_dev, wk);
+    launch_pgs<double>(st, n_c, W, d, mu, h, lambda, status, max_sweeps, tol, j_inner, sweeps_dev, eps_dev, wk);
     if (sweeps_out || eps_out) {
       int sw = 0;
       double ep = 0;

@@ -97,6 +97,14 @@ struct Factor {
   int n_zf_tasks = 0, n_zf_sum_tasks = 0;   // the first n_zf_sum_tasks tasks have chunk 0
   double *d_zf_part = nullptr;
   Arena rhs_arena;
+  long long x_elems = 0, z_elems = 0;   // sizes of the X and Z arenas
+  // mixed-precision multi-RHS solve: FP32 copies of the fronts and L_ss^-1,
+  // FP32 X and Z, FP64 residual (laid out like Z)
+  Arena fac32_arena, mixed_arena;
+  bool have32 = false;
+  int mixed_cap = 0;   // nc_cap the mixed arena was sized for
+  float *d_front32 = nullptr, *d_linv32 = nullptr, *d_X32 = nullptr, *d_Z32 = nullptr;
+  double *d_R = nullptr;
   // single-RHS work vectors (permuted)
   double *d_y = nullptr;
 };
@@ -121,6 +129,7 @@ struct Contacts {
   double *d_mu = nullptr, *d_pfree = nullptr, *d_pstart = nullptr, *d_p = nullptr;
   double *d_C = nullptr, *d_Cprev = nullptr, *d_delta = nullptr, *d_dk = nullptr;
   double *d_lam = nullptr, *d_f = nullptr, *d_WH = nullptr, *d_W = nullptr;
+  float *d_WH32 = nullptr, *d_W32 = nullptr;   // FP32 storage of the mixed-precision step
   PgsWork pgs;
   int8_t *d_status = nullptr;
   int *d_sweeps = nullptr;       // per Newton iteration
@@ -184,6 +193,7 @@ struct icr_scene {
   int *d_map_nodes = nullptr, *d_map_idx = nullptr;
   double *d_map_WN = nullptr;
   int last_nc = 0;
+  bool last_mixed = false;   // the last step kept W_H in FP32
   int last_build_nc = 0;   // contact count of the last multi-RHS forward solve (Z valid for it)
   long epoch = 0;          // bumped whenever device buffers are (re)allocated
   int clock_khz = 0;       // device wall-clock rate used by the phase stamps
@@ -213,10 +223,16 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x);
 void contact_force_solve(icr_scene *s, const double *f, double *x);
 void ensure_rhs_capacity(icr_scene *s, int nc);
 void launch_fill(icr_scene *s, double *x, long n, double v);
+void launch_widen(icr_scene *s, const float *x, double *y, long n);   // y = (double) x
 // W_H = H A^-1 H^T, or J A^-1 J^T with J = C H when per-contact frames
 // [nc*9] are given (the standard rebuild of Algorithm 2).
 void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate,
                      const double *frames = nullptr);
+// Mixed precision: Z by FP32 MFMA solves, `refine` steps of iterative
+// refinement with the residual P H^T - L Z formed in FP64, W_H = Z^T Z in
+// FP64, written as FP32 (WH32) and/or FP64 (WH64).  Needs ensure_mixed.
+void ensure_mixed(icr_scene *s);
+void build_WH_mixed(icr_scene *s, int nc, const int *node_ids, int refine, float *WH32, double *WH64);
 // W_H of mapped contacts from the nodal W_N of their distinct nodes:
 // idx [nc*4] slot -> index into those nodes (-1 unused), w [nc*4] weights.
 void launch_wh_expand(hipStream_t st, int nc, int nu, const int *idx, const double *w, const double *WN, double *WH);
@@ -226,7 +242,10 @@ void launch_select_contacts(icr_scene *s, int nc);
 void launch_directions(icr_scene *s, int nc, bool first);
 void launch_set_ctx(icr_scene *s, const icr_obstacle *obs, const double *t0);
 void launch_stamp(icr_scene *s, int slot);
-void launch_update_W(hipStream_t st, int nc, const double *WH, const double *C, double *W);
+// W and W_H stored as double, or as float (the mixed-precision step: every
+// sum is still taken in FP64)
+template <class TW>
+void launch_update_W(hipStream_t st, int nc, const TW *WH, const double *C, TW *W);
 constexpr int kPgsMaxContacts = 4096;
 constexpr int kMaxNewton = 256;   // Newton iterations per step (per-iteration sweeps, eps, stamps)
 // Layout of the PGS work buffers: per-contact records of kPgsRecWidth
@@ -248,14 +267,17 @@ void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const
                                const double *pstart, const double *mu, double h, double *f, double *Cm,
                                double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
                                double *eps_dev);
-void launch_pgs(hipStream_t st, int nc, const double *W, const double *d, const double *mu, double h,
+template <class TW>
+void launch_pgs(hipStream_t st, int nc, const TW *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
                 double *eps_dev, const PgsWork &wk);
 void launch_world_force(hipStream_t st, int nc, const double *C, const double *lam, double *f);
 // f = C^T lambda and the proximity update p = p_free + h^2 W_H f (Eq. 31) in one launch
+template <class TW>
 void launch_world_force_proximity(hipStream_t st, int nc, const double *Cm, const double *lam, double *f,
-                                  const double *WH, const double *p_free, double h, double *p);
-void launch_proximity(hipStream_t st, int nc, const double *WH, const double *p_free, const double *f, double h,
+                                  const TW *WH, const double *p_free, double h, double *p);
+template <class TW>
+void launch_proximity(hipStream_t st, int nc, const TW *WH, const double *p_free, const double *f, double h,
                       double *p);
 // World-frame forces of this step's contacts become the next step's warm
 // start (previous contacts cleared), then the step time advances.

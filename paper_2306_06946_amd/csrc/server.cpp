@@ -205,7 +205,7 @@ icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id
     if (reserve < 1) {
       const int cand = icr::candidate_count(scene);
       if (cand < 1) throw ServerError(ICR_E_STATE, "scene has no contact candidates");
-      st = icr_reserve(scene, cand < 4096 ? cand : 4096);
+      st = icr_reserve(scene, cand < 4096 ? cand : 4096, ICR_FP64);
       if (st != ICR_OK) throw ServerError(st, std::string("reservation failed: ") + icr_last_error(scene));
       st = icr_get_factor_info(scene, &info);
       if (st != ICR_OK) throw ServerError(st, icr_last_error(scene));
@@ -257,6 +257,9 @@ icr_status icr_server_submit(icr_server *srv, int32_t scene_id, const icr_obstac
     std::string msg;
     const icr_status st = icr::check_step_request(e.s, obs, opt, msg);
     if (st != ICR_OK) throw ServerError(st, "request refused: " + msg);
+    if (opt->precision == ICR_FP32_IR && !icr::mixed_reserved(e.s))
+      throw ServerError(ICR_E_ARG, "request refused: ICR_FP32_IR steps need icr_reserve(scene, n, ICR_FP32_IR) "
+                                   "before admission");
     if (opt->n_contacts > e.reserved)
       throw ServerError(ICR_E_ARG, "request refused: n_contacts " + std::to_string(opt->n_contacts) +
                                        " exceeds the " + std::to_string(e.reserved) + " contacts reserved at admission");

@@ -26,4 +26,7 @@ int candidate_count(const icr_scene *s);
 // The HIP stream the scene enqueues on (as void*).
 void *scene_stream(const icr_scene *s);
 
+// Whether the buffers of an ICR_FP32_IR step are allocated for the reserved contacts.
+bool mixed_reserved(const icr_scene *s);
+
 }  // namespace icr

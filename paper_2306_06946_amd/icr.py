@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libicr.so")
 
 OK, WARN_NOT_CONVERGED = 0, 1
+FP64, FP32_IR = 0, 1
 E_ARG, E_NOT_SPD, E_OOM, E_HIP, E_STATE = -1, -2, -3, -4, -5
 SEPARATE, STICK, SLIP = 0, 1, 2
 
@@ -34,7 +35,7 @@ class Obstacle(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("n_contacts", C.c_int32), ("n_newton", C.c_int32), ("max_sweeps", C.c_int32),
                 ("j_inner", C.c_int32), ("tol", C.c_double), ("timing", C.c_int32), ("scheme", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32)]
 
 
 class StepReport(C.Structure):
@@ -78,7 +79,7 @@ _SIGS = {
     "icr_proximity_update": (C.c_int, [_P, _I, _P, _P, _P, _D, _P]),
     "icr_set_candidates": (C.c_int, [_P, _I, _P, _P]),
     "icr_step": (C.c_int, [_P, C.POINTER(Obstacle), C.POINTER(StepOpts), C.POINTER(StepReport)]),
-    "icr_reserve": (C.c_int, [_P, _I]),
+    "icr_reserve": (C.c_int, [_P, _I, _I]),
     "icr_get_state": (C.c_int, [_P, _P, _P, C.POINTER(_D)]),
     "icr_set_state": (C.c_int, [_P, _P, _P, _D]),
     "icr_get_step_results": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -257,11 +258,11 @@ class Scene:
                                                 _dptr(p, t.float64)))
 
     def step(self, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, timing=False,
-             report=True, standard=False, graph=True, per_constraint=False):
+             report=True, standard=False, graph=True, per_constraint=False, precision=FP64, refine=1):
         ob = _obstacle(obstacle)
         scheme = 1 if standard else (2 if per_constraint else 0)
         op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 1 if timing else 0, scheme,
-                      1 if graph else 0)
+                      1 if graph else 0, int(precision), int(refine))
         rep = StepReport()
         self._check(self.L.icr_step(self._h, C.byref(ob), C.byref(op), C.byref(rep) if report else None))
         if not report:
@@ -271,8 +272,8 @@ class Scene:
         out["eps"] = list(rep.eps)[:n_newton]
         return out
 
-    def reserve(self, max_contacts):
-        self._check(self.L.icr_reserve(self._h, int(max_contacts)))
+    def reserve(self, max_contacts, precision=FP64):
+        self._check(self.L.icr_reserve(self._h, int(max_contacts), int(precision)))
 
     def get_state(self):
         t = self._torch
@@ -358,8 +359,9 @@ class Server:
         return b.value
 
     def submit(self, sid, obstacle, n_contacts, n_newton=5, max_sweeps=200, tol=1e-10, j_inner=8, tag=0,
-               graph=True):
-        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 0, 0, 1 if graph else 0)
+               graph=True, precision=FP64, refine=1):
+        op = StepOpts(n_contacts, n_newton, max_sweeps, j_inner, tol, 0, 0, 1 if graph else 0, int(precision),
+                      int(refine))
         self._check(self.L.icr_server_submit(self._h, int(sid), C.byref(_obstacle(obstacle)), C.byref(op),
                                              C.c_uint64(tag)))
 

@@ -846,3 +846,73 @@ def test_graph_replay_matches_eager(cfg):
         xa, xb = a.step_results(nc, with_WH=True), b.step_results(nc, with_WH=True)
         for key in ("node_ids", "lam", "p", "status", "WH"):
             assert torch.equal(xa[key], xb[key]), key
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision (ICR_FP32_IR): FP32 multi-RHS solve refined with FP64
+# residuals, W_H and W stored in FP32, FP64 accumulation everywhere
+# ---------------------------------------------------------------------------
+
+def _mixed_run(sc, precision, refine, steps=1):
+    icr = _icr()
+    s = icr.scene_from_dict(sc)
+    nc = sc["n_contacts"]
+    reps = [s.step(sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"], graph=False, precision=precision,
+                   refine=refine) for _ in range(steps)]
+    res = s.step_results(nc, with_WH=True)
+    q, v, _ = s.get_state()
+    torch.cuda.synchronize()
+    out = dict(WH=res["WH"].cpu().numpy(), lam=res["lam"].cpu().numpy(), status=res["status"].cpu().numpy(),
+               p=res["p"].cpu().numpy(), q=q.cpu().numpy(), v=v.cpu().numpy(), sweeps=reps[-1]["sweeps"])
+    s.close()
+    return out
+
+
+def test_mixed_precision_medium_against_oracle():
+    """Two steps of the medium scene in ICR_FP32_IR with 0, 1 and 2
+    refinement steps against the oracle (FP64): raw FP32 errors are reported,
+    refined ones meet 1e-6 on W_H and 1e-5 on lambda (relative, 2-norm)."""
+    sc = make_scene("medium", 0)
+    sim = O.Simulation(sc)
+    rec = []
+    for _ in range(2):
+        rec = []
+        out = sim.step(record=rec, max_sweeps=30, tol=0.0)
+    lam_ref = rec[-1]["lam"]
+    for refine in (0, 1, 2):
+        _say(f"[gpu] medium mixed precision refine={refine}")
+        got = _mixed_run(sc, _icr().FP32_IR, refine, steps=2)
+        e_wh = _rel(got["WH"].reshape(out["WH"].shape), out["WH"])
+        e_lam = _rel(got["lam"], lam_ref)
+        e_q = _rel(got["q"] - sim.q_rest, out["q"] - sim.q_rest)
+        n_diff = int(np.sum(got["status"] != rec[-1]["status"]))
+        _say(f"[gpu] medium refine={refine}: W_H {e_wh:.2e} lambda {e_lam:.2e} q {e_q:.2e} status differences {n_diff}")
+        if refine >= 1:
+            assert e_wh <= 1e-6 and e_lam <= 1e-5 and e_q <= 1e-5
+
+
+@pytest.mark.parametrize("advance", [0, 20])
+def test_mixed_precision_benchmark_configuration(advance):
+    """The benchmark configuration in ICR_FP32_IR against the FP64 path of
+    the same GPU (which the full-size test pins to the oracle at 1e-10): raw
+    and refined errors of W_H, lambda, p and q; refined ones within 1e-6 on
+    W_H and 1e-5 on lambda."""
+    sc = make_scene("precision", 0)
+    if advance:
+        obs = dict(sc["obstacle"])
+        obs["c0"] = np.asarray(obs["c0"]) + advance * sc["h"] * np.asarray(obs["vel"])
+        sc = dict(sc, obstacle=obs)
+    icr = _icr()
+    _say(f"[gpu] precision+{advance} FP64 reference step")
+    ref = _mixed_run(sc, icr.FP64, 0)
+    for refine in (0, 1):
+        _say(f"[gpu] precision+{advance} mixed refine={refine}")
+        got = _mixed_run(sc, icr.FP32_IR, refine)
+        errs = {k: _rel(got[k], ref[k]) for k in ("WH", "lam")}
+        errs["p"] = _rel(got["p"], ref["p"])
+        errs["q"] = _rel(got["q"] - sc["nodes"].ravel(), ref["q"] - sc["nodes"].ravel())
+        n_diff = int(np.sum(got["status"] != ref["status"]))
+        _say(f"[gpu] precision+{advance} refine={refine}: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items())
+             + f" status differences {n_diff} sweeps {got['sweeps']}")
+        if refine >= 1:
+            assert errs["WH"] <= 1e-6 and errs["lam"] <= 1e-5
