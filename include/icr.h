@@ -224,8 +224,33 @@ typedef struct {
  * (signed distance, node id) and numbers its contacts by ascending node id. */
 icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu);
 
+/*
+ * Pair contacts between two deformable bodies meshed in one scene (two
+ * components of the mesh: A is block diagonal).  A pair is a point of body 1
+ * against the same point of body 2: p = H q = x_1 - x_2 with H = [H_1, -H_2]
+ * (Eq. 6, 16-17), given as up to four (node, weight) slots with the body-2
+ * weights negative, so that its force acts as +f on body 1 and -f on body 2
+ * (c_2 = -J_2^T lambda).  Its normal n is the unit normal of body 2's
+ * surface at the point, fixed over a time step; the normal gap is n . p
+ * (0 for points that coincide at rest), the tangential gap the relative
+ * tangential displacement over the step, tangents by the axis rule.  Every
+ * step's contacts are the pairs, in the given order, followed by the
+ * obstacle contacts (n_contacts - count closest candidates); a pair
+ * warm-starts from its own force of the previous step.  Host arrays, copied:
+ *   node_ids [count*4] int32 (-1 unused), weights [count*4], normals
+ *   [count*3] (unit), mu [count] (>= 0).  count = 0 removes the pairs.
+ * Pair nodes may not be clamped or contact candidates; at most 8192
+ * distinct pair nodes; count <= 4096.  More pairs than the interface nodes
+ * can carry (several points per node) make W rank deficient; PGS still runs
+ * (its 3x3 diagonal blocks stay SPD), lambda is then not unique.
+ * ICR_E_STATE before icr_assemble; ICR_E_ARG on a bad id, weight, normal or
+ * friction.
+ */
+icr_status icr_set_pairs(icr_scene *s, int32_t count, const int32_t *node_ids, const double *weights,
+                         const double *normals, const double *mu);
+
 typedef struct {
-  int32_t n_contacts;   /* contacts kept per step (closest candidates) */
+  int32_t n_contacts;   /* contacts per step: the pairs (icr_set_pairs), then the closest candidates */
   int32_t n_newton;     /* Newton iterations (Algorithm 3), 1..256.  With max_sweeps = 1 the
                            directions are updated after every PGS sweep (the per-sweep update
                            the results section proposes) */

@@ -51,6 +51,17 @@ notes of the repository):
       d_a = delta(p_a) - W~_aa C_a f_a with W~_aa = h^2 C_a W_H,aa C_a^T; the
       stopping rule R7 is taken on f.  With a plane obstacle (constant frames,
       affine gap) this is exactly the PGS of one Newton iteration.
+  R19 two deformable bodies: a pair contact is a point of body 1 against the
+      same point of body 2, p = x_1 - x_2 = H q with H = [H_1, -H_2] (the
+      nodes of body 2 carry negative weights; Eq. 6, 16-17), so its force acts
+      as +f on body 1 and -f on body 2 (c_2 = -J_2^T lambda);
+  R20 a pair's normal n is the unit normal of body 2's surface at the pair,
+      given with the pair and fixed over the step; its gap is the normal
+      separation n . p (0 for points that coincide at rest), its tangential
+      gap T (p - p_start) (R4 without an obstacle motion), tangents by R11;
+  R21 the contacts of a step with pairs are the pairs, in their given
+      order, followed by the obstacle contacts of R17 (K = n_contacts - number
+      of pairs); pairs warm-start from their own force of the previous step.
 """
 from __future__ import annotations
 
@@ -392,8 +403,32 @@ def tangent_basis(nrm):
     return t1, t2
 
 
-def directions(p, p_start, obs, t0, t1):
-    """Frames C [nc,3,3] (rows n, t1, t2) and gaps delta [m] at proximity p (Algorithm 3, step 1)."""
+def pair_directions(p, p_start, normals):
+    """Frames and gaps of pair contacts (R20): fixed normal n, gap n . p,
+    tangential gap T (p - p_start)."""
+    p = p.reshape(-1, 3)
+    nrm = np.asarray(normals, dtype=np.float64).reshape(-1, 3)
+    ta, tb = tangent_basis(nrm)
+    C = np.stack([nrm, ta, tb], axis=1)
+    rel = p - p_start.reshape(-1, 3)
+    phi = nrm[:, 0] * p[:, 0] + nrm[:, 1] * p[:, 1] + nrm[:, 2] * p[:, 2]
+    delta = np.stack([phi, (ta * rel).sum(axis=1), (tb * rel).sum(axis=1)], axis=1)
+    return C, delta.ravel()
+
+
+def directions(p, p_start, obs, t0, t1, pair_normals=None):
+    """Frames C [nc,3,3] (rows n, t1, t2) and gaps delta [m] at proximity p (Algorithm 3, step 1).
+
+    With ``pair_normals`` [P, 3], the first P contacts are pairs (R20) and the
+    others obstacle contacts.
+    """
+    if pair_normals is not None and len(pair_normals):
+        P = len(pair_normals)
+        Cp, dp = pair_directions(p[:3 * P], p_start[:3 * P], pair_normals)
+        if 3 * P == len(p):
+            return Cp, dp
+        Co, do = directions(p[3 * P:], p_start[3 * P:], obs, t0, t1)
+        return np.concatenate([Cp, Co]), np.concatenate([dp, do])
     p = p.reshape(-1, 3)
     phi, nrm = signed_distance(p, obs, t1)
     ta, tb = tangent_basis(nrm)
@@ -545,7 +580,7 @@ def pgs(W, d, mu, h, lam0, max_sweeps, tol, j_inner=8, margins=None):
 # ---------------------------------------------------------------------------
 
 def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_sweeps, tol, j_inner,
-                record=None, margins=False):
+                record=None, margins=False, pair_normals=None):
     """Algorithm 3 with readings R8-R10.  Returns (f world force [nc,3], p, last C, lambda, info).
 
     With ``margins``, each entry of ``info`` (and of ``record``) also holds the
@@ -558,7 +593,7 @@ def newton_fast(WH, p_free, p_start, obs, t0, t1, mu, h, f_init, n_newton, max_s
     lam = np.zeros(3 * nc)
     C = None
     for k in range(n_newton):
-        C, delta = directions(p, p_start, obs, t0, t1)                 # step 1
+        C, delta = directions(p, p_start, obs, t0, t1, pair_normals)   # step 1
         W = update_W(WH, C)                                            # step 2
         dk = delta - rotation_blocks_apply(C, p - p_free)              # R9
         lam0 = rotation_blocks_apply(C, f.ravel())                     # R8 warm start
@@ -681,6 +716,9 @@ class Simulation:
         cand = scene["candidates"]
         self.mu_of_node = np.zeros(len(scene["nodes"]))
         self.mu_of_node[cand] = scene["cand_mu"]
+        pr = scene.get("pairs")
+        self.pairs = pr
+        self.pair_force = np.zeros((len(pr["ids"]), 3)) if pr is not None else None   # R21
 
     def step(self, standard=False, record=None, max_sweeps=None, tol=None, per_constraint=False, margins=False,
              wh="solve"):
@@ -692,26 +730,49 @@ class Simulation:
         ms = sc["max_sweeps"] if max_sweeps is None else max_sweeps
         tl = sc["tol"] if tol is None else tol
         dv_free, q_free, _ = free_motion(self.asm, self.factor, sc, self.q, self.v, self.q_rest)
-        nodes_c = select_contacts(q_free, sc, t1)
-        H = mapping_H(nodes_c, self.n)
+        pr = self.pairs
+        P = 0 if pr is None else len(pr["ids"])
+        if P and (standard or per_constraint):
+            raise ValueError("pair contacts run in the fast scheme (Algorithm 3) only")
+        nodes_c = select_contacts(q_free, dict(sc, n_contacts=sc["n_contacts"] - P), t1) \
+            if sc["n_contacts"] > P else np.zeros(0, dtype=np.int64)
+        if P:
+            # R21: the pairs, then the obstacle contacts as one-slot points
+            ids = np.full((P + len(nodes_c), 4), -1, dtype=np.int64)
+            w = np.zeros((P + len(nodes_c), 4))
+            ids[:P], w[:P] = pr["ids"], pr["w"]
+            ids[P:, 0], w[P:, 0] = nodes_c, 1.0
+            H = mapping_H(ids, self.n, w)
+            mu = np.concatenate([pr["mu"], self.mu_of_node[nodes_c]])
+            f_init = np.concatenate([self.pair_force, self.node_force[nodes_c]])
+            normals = pr["normals"]
+        else:
+            ids = w = None
+            H = mapping_H(nodes_c, self.n)
+            mu = self.mu_of_node[nodes_c]
+            f_init = self.node_force[nodes_c]
+            normals = None
         p_free = H @ q_free
         p_start = H @ self.q
-        mu = self.mu_of_node[nodes_c]
-        f_init = self.node_force[nodes_c]
         out = dict(nodes_c=nodes_c, q_free=q_free, dv_free=dv_free, p_free=p_free)
         if standard:
             f, p, q_new, lam = newton_standard(self.factor, nodes_c, self.n, q_free, p_start, sc["obstacle"],
                                                t0, t1, mu, h, f_init, sc["n_newton"], ms, tl, sc["j_inner"],
                                                record)
         else:
-            WH = build_WH_schur(self.asm["A"], nodes_c) if wh == "schur" else build_WH(self.factor, nodes_c, self.n)
+            if P:
+                WH = build_WH(self.factor, ids, self.n, weights=w)
+            elif wh == "schur":
+                WH = build_WH_schur(self.asm["A"], nodes_c)
+            else:
+                WH = build_WH(self.factor, nodes_c, self.n)
             out["WH"] = WH
             if per_constraint:
                 f, p, C, lam, info = newton_per_constraint(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h,
                                                            f_init, sc["n_newton"], ms, tl, sc["j_inner"], record)
             else:
                 f, p, C, lam, info = newton_fast(WH, p_free, p_start, sc["obstacle"], t0, t1, mu, h, f_init,
-                                                 sc["n_newton"], ms, tl, sc["j_inner"], record, margins)
+                                                 sc["n_newton"], ms, tl, sc["j_inner"], record, margins, normals)
             out["info"] = info
             out["C"] = C
         # corrective motion and integration (Eq. 20, Algorithm 1 last loop, R1)
@@ -719,7 +780,9 @@ class Simulation:
         self.v = self.v + dv
         self.q = self.q + h * self.v
         self.node_force[:] = 0.0
-        self.node_force[nodes_c] = f
+        self.node_force[nodes_c] = f[P:]
+        if P:
+            self.pair_force = f[:P].copy()
         self.t = t1
         out.update(f=f, p=p, lam=lam, q=self.q.copy(), v=self.v.copy())
         return out

@@ -91,6 +91,37 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.nc_cap = nc;
 }
 
+// Buffers and expansion maps of a step with n_contacts = nc when pairs are
+// set: contacts 0..P-1 are the pairs (their slots, indices into the pairs'
+// distinct nodes), contacts P..nc-1 the obstacle contacts (one slot each,
+// the node after the pairs' nodes in the build's list).
+void ensure_pair_step(icr_scene *s, int nc) {
+  auto &Pr = s->pairs;
+  if (Pr.count == 0 || Pr.step_nc == nc) return;
+  ICR_HIP(hipStreamSynchronize(s->stream));
+  s->epoch++;
+  Pr.step_arena.release();
+  const int P = Pr.count, nu = Pr.nu + nc - P;
+  std::vector<int> idx(4L * nc, -1);
+  std::vector<double> w(4L * nc, 0.0);
+  for (long e = 0; e < 4L * P; ++e) {
+    idx[e] = Pr.idx[e];
+    w[e] = Pr.w[e];
+  }
+  for (int c = P; c < nc; ++c) {
+    idx[4L * c] = Pr.nu + c - P;
+    w[4L * c] = 1.0;
+  }
+  auto &A = Pr.step_arena;
+  Pr.d_unodes = A.alloc<int>(nu);
+  Pr.d_idx = A.upload(idx, s->stream);
+  Pr.d_wexp = A.upload(w, s->stream);
+  Pr.d_WN = A.alloc<double>(9L * nu * nu);
+  Pr.d_fu = A.alloc<double>(3L * nu);
+  ICR_HIP(hipStreamSynchronize(s->stream));
+  Pr.step_nc = nc;
+}
+
 // Host-side build of the factor descriptors from the symbolic structure.
 void prepare_factor(icr_scene *s) {
   auto &m = s->mesh;
@@ -273,6 +304,8 @@ void icr_destroy(icr_scene *s) {
   if (s->side) (void)hipStreamDestroy(s->side);
   s->con.arena.release();
   s->map_arena.release();
+  s->pairs.arena.release();
+  s->pairs.step_arena.release();
   s->fac.rhs_arena.release();
   s->fac.fac32_arena.release();
   s->fac.mixed_arena.release();
@@ -324,6 +357,9 @@ icr_status icr_assemble(icr_scene *s, const double *nodes, int32_t N, const int3
     s->con.nc_cap = 0;
     s->map_arena.release();
     s->map_nc_cap = s->map_nu_cap = 0;
+    s->pairs.arena.release();
+    s->pairs.step_arena.release();
+    s->pairs = Pairs();
     s->fac.rhs_arena.release();
     s->fac.nc_cap = 0;
     s->fac.fac32_arena.release();
@@ -457,7 +493,8 @@ icr_status icr_get_factor_info(icr_scene *s, icr_factor_info *out) {
     out->factor_ms = s->fac.ms;
     out->device_bytes = (int64_t)(s->mesh_arena.bytes + s->fac_arena.bytes + s->fac.rhs_arena.bytes +
                                   s->state_arena.bytes + s->con.arena.bytes + s->map_arena.bytes +
-                                  s->fac.fac32_arena.bytes + s->fac.mixed_arena.bytes);
+                                  s->fac.fac32_arena.bytes + s->fac.mixed_arena.bytes + s->pairs.arena.bytes +
+                                  s->pairs.step_arena.bytes);
     return ICR_OK;
   });
 }
@@ -579,6 +616,78 @@ icr_status icr_proximity_update(icr_scene *s, int32_t n_c, const double *WH, con
   });
 }
 
+icr_status icr_set_pairs(icr_scene *s, int32_t count, const int32_t *node_ids, const double *weights,
+                         const double *normals, const double *mu) {
+  return guarded(s, [&] {
+    if (!s->assembled) throw StateError("icr_set_pairs before icr_assemble");
+    REQUIRE(count >= 0 && count <= kPgsMaxContacts, "pair count must be in [0, 4096]");
+    REQUIRE(count == 0 || (node_ids && weights && normals && mu), "NULL host array");
+    const auto &mesh = s->mesh;
+    std::vector<int> nodes;
+    for (int c = 0; c < count; ++c) {
+      int used = 0;
+      const std::string who = "pair " + std::to_string(c);
+      for (int k = 0; k < 4; ++k) {
+        const int v = node_ids[4 * c + k];
+        if (v == -1) continue;
+        REQUIRE(v >= 0 && v < mesh.N, who + ": node id out of range");
+        REQUIRE(!mesh.fixed[v], who + ": node is clamped");
+        REQUIRE(std::isfinite(weights[4 * c + k]) && weights[4 * c + k] != 0.0,
+                who + ": weights of used slots must be finite and non-zero");
+        for (int l = 0; l < k; ++l) REQUIRE(node_ids[4 * c + l] != v, who + ": repeated node");
+        nodes.push_back(v);
+        ++used;
+      }
+      REQUIRE(used > 0, who + " has no node");
+      const double *n = normals + 3 * c;
+      REQUIRE(std::fabs(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] - 1.0) < 1e-12, who + ": normal must be a unit vector");
+      REQUIRE(std::isfinite(mu[c]) && mu[c] >= 0, who + ": friction must be >= 0");
+    }
+    std::sort(nodes.begin(), nodes.end());
+    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+    REQUIRE((int)nodes.size() <= 8192, "the pairs reference more than 8192 distinct nodes");
+    for (int v : s->con.nodes)
+      REQUIRE(!std::binary_search(nodes.begin(), nodes.end(), v), "a pair node is a contact candidate");
+    ICR_HIP(hipStreamSynchronize(s->stream));
+    s->epoch++;
+    auto &Pr = s->pairs;
+    Pr.arena.release();
+    Pr.step_arena.release();
+    Pr = Pairs();
+    if (count == 0) return ICR_OK;
+    Pr.count = count;
+    Pr.nodes = nodes;
+    Pr.nu = (int)nodes.size();
+    Pr.idx.assign(4L * count, -1);
+    Pr.w.assign(4L * count, 0.0);
+    std::vector<int> slot_node(4L * count, -1), cnt(Pr.nu + 1, 0);
+    for (long e = 0; e < 4L * count; ++e) {
+      if (node_ids[e] < 0) continue;
+      slot_node[e] = node_ids[e];
+      Pr.idx[e] = (int)(std::lower_bound(nodes.begin(), nodes.end(), node_ids[e]) - nodes.begin());
+      Pr.w[e] = weights[e];
+      cnt[Pr.idx[e] + 1]++;
+    }
+    for (int u = 0; u < Pr.nu; ++u) cnt[u + 1] += cnt[u];
+    std::vector<int> csr(cnt[Pr.nu]), fill(cnt.begin(), cnt.end() - 1);
+    for (long e = 0; e < 4L * count; ++e)
+      if (Pr.idx[e] >= 0) csr[fill[Pr.idx[e]]++] = (int)e;   // ascending slot order per node
+    hipStream_t st = s->stream;
+    auto &A = Pr.arena;
+    Pr.d_slot_node = A.upload(slot_node, st);
+    Pr.d_w = A.upload(Pr.w, st);
+    Pr.d_normal = A.upload(std::vector<double>(normals, normals + 3L * count), st);
+    Pr.d_mu = A.upload(std::vector<double>(mu, mu + count), st);
+    Pr.d_force = A.alloc<double>(3L * count);
+    ICR_HIP(hipMemsetAsync(Pr.d_force, 0, sizeof(double) * 3 * count, st));
+    Pr.d_nodes = A.upload(nodes, st);
+    Pr.d_csr_ptr = A.upload(cnt, st);
+    Pr.d_csr_slot = A.upload(csr, st);
+    ICR_HIP(hipStreamSynchronize(st));
+    return ICR_OK;
+  });
+}
+
 icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes, const double *mu) {
   return guarded(s, [&] {
     if (!s->assembled) throw StateError("icr_set_candidates before icr_assemble");
@@ -591,6 +700,8 @@ icr_status icr_set_candidates(icr_scene *s, int32_t count, const int32_t *nodes,
       REQUIRE(v >= 0 && v < s->mesh.N, "candidate node out of range");
       REQUIRE(!s->mesh.fixed[v], "candidate node is clamped");
       REQUIRE(!seen[v]++, "duplicate candidate node");
+      REQUIRE(!std::binary_search(s->pairs.nodes.begin(), s->pairs.nodes.end(), v),
+              "candidate node belongs to a pair contact");
       REQUIRE(std::isfinite(mu[i]) && mu[i] >= 0, "friction must be >= 0");
       mu_node[v] = mu[i];
     }
@@ -618,7 +729,11 @@ void check_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt)
   check_obstacle(obs);
   REQUIRE(opt, "NULL options");
   const int nc = opt->n_contacts;
-  REQUIRE(nc >= 1 && nc <= s->con.count, "n_contacts must be in [1, candidate count]");
+  const int P = s->pairs.count;
+  REQUIRE(nc >= 1 && nc >= P && nc - P <= s->con.count,
+          "n_contacts must be in [1, pair count + candidate count] and at least the pair count");
+  REQUIRE(P == 0 || opt->scheme == 0, "pair contacts run in the fast scheme (scheme 0) only");
+  REQUIRE(P == 0 || s->pairs.nu + nc - P <= 8192, "pair nodes and obstacle contacts exceed 8192 nodes");
   REQUIRE(nc <= kPgsMaxContacts, "n_contacts exceeds the PGS kernel limit (4096)");
   REQUIRE(opt->n_newton >= 1 && opt->n_newton <= kMaxNewton, "n_newton must be in [1, 256]");
   REQUIRE(opt->max_sweeps >= 1 && opt->j_inner >= 0, "max_sweeps >= 1 and j_inner >= 0 required");
@@ -652,13 +767,26 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   single_rhs_solve(s, S.d_b, S.d_dvfree);
   launch_axpy_qfree(s);
   mark(ev, 1);
-  launch_select_contacts(s, nc);
+  auto &Pr = s->pairs;
+  const int P = Pr.count;
+  if (nc > P) launch_select_contacts(s, nc);
+  if (P > 0) launch_pair_points(s, nc);   // and the node list of the W_H build
   mark(ev, 2);
   const bool mixed = opt->precision == ICR_FP32_IR;
-  if (mixed)
+  if (P > 0) {
+    // pairs: nodal W_N of the distinct nodes, then W_H = H_w W_N H_w^T
+    const int nu = Pr.nu + nc - P;
+    if (mixed)
+      build_WH_mixed(s, nu, Pr.d_unodes, opt->refine, nullptr, Pr.d_WN);
+    else
+      build_WH_device(s, nu, Pr.d_unodes, Pr.d_WN, false);
+    launch_wh_expand(st, nc, nu, Pr.d_idx, Pr.d_wexp, Pr.d_WN, C.d_WH);
+    if (mixed) launch_narrow(s, C.d_WH, C.d_WH32, 9L * nc * nc);
+  } else if (mixed) {
     build_WH_mixed(s, nc, C.d_nodes_c, opt->refine, C.d_WH32, nullptr);
-  else if (!standard)
+  } else if (!standard) {
     build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
+  }
   mark(ev, 3);
   // directions updated before every local solve: proximity of the warm start
   if (per_constraint) launch_proximity<double>(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
@@ -702,7 +830,12 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   }
   mark(ev, 4);
   // corrective motion and integration (Eq. 20)
-  if (!standard) contact_force_solve(s, C.d_f, S.d_sol);             // A^-1 H^T f (last W_H's Z)
+  if (P > 0) {
+    launch_node_forces(s, nc, C.d_f, Pr.d_fu);                        // H_w^T f on the build's nodes
+    contact_force_solve(s, Pr.d_fu, S.d_sol);
+  } else if (!standard) {
+    contact_force_solve(s, C.d_f, S.d_sol);                           // A^-1 H^T f (last W_H's Z)
+  }
   launch_integrate(s);
   launch_store_forces(s, nc);   // and the time advance
   if (standard) launch_fill(s, C.d_WH, 9L * nc * nc, 0.0);           // no W_H in this scheme
@@ -722,7 +855,8 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     check_step(s, obs, opt);
     const int nc = opt->n_contacts;
     ensure_contact_buffers(s, nc);
-    ensure_rhs_capacity(s, nc);
+    ensure_pair_step(s, nc);
+    ensure_rhs_capacity(s, std::max(nc, s->pairs.count > 0 ? s->pairs.nu + nc - s->pairs.count : 0));
     if (opt->precision == ICR_FP32_IR) ensure_mixed(s);
     hipStream_t st = s->stream;
     auto &C = s->con;
@@ -835,6 +969,7 @@ icr_status icr_set_state(icr_scene *s, const double *q, const double *v, double 
     s->st.t = t;
     launch_set_ctx(s, nullptr, &t);
     launch_fill(s, s->st.d_node_force, (long)s->mesh.n, 0.0);   // a new trajectory: no warm start
+    if (s->pairs.count > 0) launch_fill(s, s->pairs.d_force, 3L * s->pairs.count, 0.0);
     return ICR_OK;
   });
 }

@@ -201,12 +201,45 @@ __device__ inline void contact_frame(const icr_obstacle &obs, double t0, double 
   delta[2] = tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2];
 }
 
+// Frame and gap of a pair contact between two bodies: the given normal n of
+// the second body's surface (fixed over the step), tangents by the axis
+// rule, normal gap n . p of the relative position p = x_1 - x_2, tangential
+// gap = relative tangential displacement over the step.
+__device__ inline void pair_frame(const double n[3], const double pc[3], const double ps[3], double F[3][3],
+                                  double delta[3]) {
+  int ax = 0;
+  double am = fabs(n[0]);
+  if (fabs(n[1]) < am) {
+    ax = 1;
+    am = fabs(n[1]);
+  }
+  if (fabs(n[2]) < am) ax = 2;
+  double en = n[ax];
+  double ta[3] = {-en * n[0], -en * n[1], -en * n[2]};
+  ta[ax] += 1.0;
+  double tn = sqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
+  ta[0] /= tn;
+  ta[1] /= tn;
+  ta[2] /= tn;
+  double tb[3] = {n[1] * ta[2] - n[2] * ta[1], n[2] * ta[0] - n[0] * ta[2], n[0] * ta[1] - n[1] * ta[0]};
+  double rel[3] = {pc[0] - ps[0], pc[1] - ps[1], pc[2] - ps[2]};
+  for (int a = 0; a < 3; ++a) {
+    F[0][a] = n[a];
+    F[1][a] = ta[a];
+    F[2][a] = tb[a];
+  }
+  delta[0] = n[0] * pc[0] + n[1] * pc[1] + n[2] * pc[2];
+  delta[1] = ta[0] * rel[0] + ta[1] * rel[1] + ta[2] * rel[2];
+  delta[2] = tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2];
+}
+
 // Frames C_k and gaps at p_{k-1}; d_k = delta - C_k (p - p_free); warm start
-// lambda = C_k f with f the previous world-frame force.
+// lambda = C_k f with f the previous world-frame force.  The first npair
+// contacts are pairs with normals pn.
 __global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const double *__restrict__ p,
                              const double *__restrict__ pfree, const double *__restrict__ pstart,
                              const double *__restrict__ fprev, double *__restrict__ C, double *__restrict__ dk,
-                             double *__restrict__ lam) {
+                             double *__restrict__ lam, int npair, const double *__restrict__ pn) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const icr_obstacle obs = ctx->obs;
@@ -214,7 +247,12 @@ __global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const doub
   double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
   double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
   double F[3][3], delta[3];
-  contact_frame(obs, t0, t1, pc, ps, F, delta);
+  if (c < npair) {
+    const double n[3] = {pn[3 * c], pn[3 * c + 1], pn[3 * c + 2]};
+    pair_frame(n, pc, ps, F, delta);
+  } else {
+    contact_frame(obs, t0, t1, pc, ps, F, delta);
+  }
   double dp[3] = {pc[0] - pfree[3 * c], pc[1] - pfree[3 * c + 1], pc[2] - pfree[3 * c + 2]};
   for (int r = 0; r < 3; ++r) {
     for (int a = 0; a < 3; ++a) C[9 * c + 3 * r + a] = F[r][a];
@@ -1578,10 +1616,14 @@ __global__ void k_zero(long n, double *__restrict__ x) {
 // Warm start of the next step (one workgroup): clear the forces of the
 // previous step's contact nodes (count and ids on the device), store this
 // step's world-frame forces on their nodes, keep their ids, advance the time.
+// Pair contacts (the first npair contacts) keep their own forces.
 __global__ __launch_bounds__(1024) void k_store_forces(int nc, const int *__restrict__ nodes,
                                                        const double *__restrict__ f, double *__restrict__ node_force,
                                                        int *__restrict__ prev_nodes, int *__restrict__ prev_nc,
-                                                       StepCtx *__restrict__ ctx) {
+                                                       StepCtx *__restrict__ ctx, int npair,
+                                                       const double *__restrict__ fpair_new,
+                                                       double *__restrict__ fpair) {
+  for (int e = threadIdx.x; e < 3 * npair; e += blockDim.x) fpair[e] = fpair_new[e];
   const int pn = *prev_nc;
   for (int c = threadIdx.x; c < pn; c += blockDim.x) {
     const int v = prev_nodes[c];
@@ -1622,8 +1664,10 @@ __global__ void k_stamp(unsigned long long *ts, int slot) { ts[slot] = wall_cloc
 
 void launch_select_contacts(icr_scene *s, int nc) {
   auto &C = s->con;
-  k_select<<<1, 1024, 0, s->stream>>>(C.count, C.d_cand, s->st.d_qfree, s->st.d_q, s->st.d_ctx, nc, C.d_mu_node,
-                                      s->st.d_node_force, C.d_nodes_c, C.d_mu, C.d_pfree, C.d_pstart, C.d_f);
+  const int P = s->pairs.count;   // pair contacts come first; the obstacle contacts follow them
+  k_select<<<1, 1024, 0, s->stream>>>(C.count, C.d_cand, s->st.d_qfree, s->st.d_q, s->st.d_ctx, nc - P,
+                                      C.d_mu_node, s->st.d_node_force, C.d_nodes_c + P, C.d_mu + P,
+                                      C.d_pfree + 3L * P, C.d_pstart + 3L * P, C.d_f + 3L * P);
   ICR_LAUNCH_CHECK();
 }
 
@@ -1631,7 +1675,80 @@ void launch_directions(icr_scene *s, int nc, bool first) {
   auto &C = s->con;
   const double *p = first ? C.d_pfree : C.d_p;
   k_directions<<<cdiv(nc, 128), 128, 0, s->stream>>>(nc, s->st.d_ctx, p, C.d_pfree, C.d_pstart, C.d_f, C.d_C,
-                                                     C.d_dk, C.d_lam);
+                                                     C.d_dk, C.d_lam, s->pairs.count, s->pairs.d_normal);
+  ICR_LAUNCH_CHECK();
+}
+
+// Pair contacts 0..P-1 of a step: p_free = H q_free, p_start = H q over their
+// slots, friction, warm start from the pair's previous force, node id -1;
+// and the node list of the W_H build: the pairs' distinct nodes, then the
+// step's obstacle contact nodes (contacts P..nc-1).
+__global__ void k_pair_points(int P, int nc, int nup, const int *__restrict__ slot_node,
+                              const double *__restrict__ w, const double *__restrict__ qf,
+                              const double *__restrict__ q, const double *__restrict__ mu_pair,
+                              const double *__restrict__ fpair, const int *__restrict__ pair_nodes,
+                              int *__restrict__ nodes_c, double *__restrict__ mu_c, double *__restrict__ pfree,
+                              double *__restrict__ pstart, double *__restrict__ finit, int *__restrict__ unodes) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < P) {
+    double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+      const int v = slot_node[4 * t + k];
+      if (v < 0) continue;
+      const double wk = w[4 * t + k];
+      for (int x = 0; x < 3; ++x) {
+        a[x] = fma(wk, qf[3 * v + x], a[x]);
+        b[x] = fma(wk, q[3 * v + x], b[x]);
+      }
+    }
+    for (int x = 0; x < 3; ++x) {
+      pfree[3 * t + x] = a[x];
+      pstart[3 * t + x] = b[x];
+      finit[3 * t + x] = fpair[3 * t + x];
+    }
+    mu_c[t] = mu_pair[t];
+    nodes_c[t] = -1;
+  }
+  if (t < nup) unodes[t] = pair_nodes[t];
+  if (t >= nup && t < nup + nc - P) unodes[t] = nodes_c[P + t - nup];
+}
+
+// Force on every node of the W_H build (H_w^T f): a pair node sums weight x
+// force over the pair slots that name it (CSR in slot order), an obstacle
+// contact's node takes that contact's force.
+__global__ void k_node_forces(int nup, int nu, int P, const int *__restrict__ csr_ptr,
+                              const int *__restrict__ csr_slot, const double *__restrict__ w,
+                              const double *__restrict__ f, double *__restrict__ fu) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nu) return;
+  double a[3] = {0, 0, 0};
+  if (u < nup) {
+    for (int e = csr_ptr[u]; e < csr_ptr[u + 1]; ++e) {
+      const int sl = csr_slot[e], c = sl / 4;
+      for (int x = 0; x < 3; ++x) a[x] = fma(w[sl], f[3 * c + x], a[x]);
+    }
+  } else {
+    const int c = P + u - nup;
+    for (int x = 0; x < 3; ++x) a[x] = f[3 * c + x];
+  }
+  for (int x = 0; x < 3; ++x) fu[3 * u + x] = a[x];
+}
+
+void launch_pair_points(icr_scene *s, int nc) {
+  auto &C = s->con;
+  auto &Pr = s->pairs;
+  const int n = std::max(Pr.count, Pr.nu + nc - Pr.count);
+  k_pair_points<<<cdiv(n, 256), 256, 0, s->stream>>>(Pr.count, nc, Pr.nu, Pr.d_slot_node, Pr.d_w, s->st.d_qfree,
+                                                     s->st.d_q, Pr.d_mu, Pr.d_force, Pr.d_nodes, C.d_nodes_c,
+                                                     C.d_mu, C.d_pfree, C.d_pstart, C.d_f, Pr.d_unodes);
+  ICR_LAUNCH_CHECK();
+}
+
+void launch_node_forces(icr_scene *s, int nc, const double *f, double *fu) {
+  auto &Pr = s->pairs;
+  const int nu = Pr.nu + nc - Pr.count;
+  k_node_forces<<<cdiv(nu, 256), 256, 0, s->stream>>>(Pr.nu, nu, Pr.count, Pr.d_csr_ptr, Pr.d_csr_slot, Pr.d_w,
+                                                      f, fu);
   ICR_LAUNCH_CHECK();
 }
 
@@ -1752,8 +1869,10 @@ void launch_standard_proximity(icr_scene *s, int nc) {
 
 void launch_store_forces(icr_scene *s, int nc) {
   auto &S = s->st;
-  k_store_forces<<<1, 1024, 0, s->stream>>>(nc, s->con.d_nodes_c, s->con.d_f, S.d_node_force, S.d_prev_nodes,
-                                            S.d_prev_nc, S.d_ctx);
+  const int P = s->pairs.count;
+  k_store_forces<<<1, 1024, 0, s->stream>>>(nc - P, s->con.d_nodes_c + P, s->con.d_f + 3L * P, S.d_node_force,
+                                            S.d_prev_nodes, S.d_prev_nc, S.d_ctx, P, s->con.d_f,
+                                            s->pairs.d_force);
   ICR_LAUNCH_CHECK();
 }
 

@@ -824,6 +824,11 @@ void launch_wh_expand(hipStream_t st, int nc, int nu, const int *idx, const doub
   ICR_LAUNCH_CHECK();
 }
 
+void launch_narrow(icr_scene *s, const double *x, float *y, long n) {
+  k_to_float<<<(unsigned)std::min<long>(1024, (n + 255) / 256), 256, 0, s->stream>>>(n, x, y);
+  ICR_LAUNCH_CHECK();
+}
+
 void launch_widen(icr_scene *s, const float *x, double *y, long n) {
   k_to_double<<<(unsigned)std::min<long>(1024, (n + 255) / 256), 256, 0, s->stream>>>(n, x, y);
   ICR_LAUNCH_CHECK();
@@ -1096,9 +1101,15 @@ void build_WH_mixed(icr_scene *s, int nc, const int *node_ids, int refine, float
                                                          F.d_Z, (int)m, F.d_Wp);
     ICR_LAUNCH_CHECK();
   }
-  if (WH32) wh_finish<float>(s, nc, WH32);
+  const int nt = cdiv(m, 64);
+  k_wp_mirror<<<nt * (nt + 1) / 2, 256, 0, st>>>((int)m, F.d_Wp);
+  ICR_LAUNCH_CHECK();
+  if (WH32) {
+    k_wh_unpermute<float><<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH32);
+    ICR_LAUNCH_CHECK();
+  }
   if (WH64) {
-    k_wh_unpermute<double><<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH64);   // Wp already mirrored
+    k_wh_unpermute<double><<<(unsigned)m, 256, 0, st>>>(nc, F.d_pos, F.d_Wp, WH64);
     ICR_LAUNCH_CHECK();
   }
 }

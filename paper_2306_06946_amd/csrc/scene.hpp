@@ -137,6 +137,28 @@ struct Contacts {
   Arena arena;
 };
 
+// Pair contacts between two bodies (icr_set_pairs): points of body 1
+// against points of body 2, p = x_1 - x_2 (weights of body-2 nodes
+// negative), each with a fixed normal; they come first in every step's
+// contact list.
+struct Pairs {
+  int count = 0;            // pairs
+  int nu = 0;               // their distinct nodes
+  std::vector<int> nodes;   // those nodes, ascending
+  std::vector<int> idx;     // per slot: index into nodes, or -1
+  std::vector<double> w;    // per slot weight (0 for unused slots)
+  int *d_slot_node = nullptr;   // [count*4] node id or -1
+  double *d_w = nullptr, *d_normal = nullptr, *d_mu = nullptr, *d_force = nullptr;
+  int *d_nodes = nullptr, *d_csr_ptr = nullptr, *d_csr_slot = nullptr;   // node -> slots naming it
+  Arena arena;
+  // per step size (n_contacts): node list of the W_H build, expansion maps,
+  // nodal W_N, node forces
+  int step_nc = 0;
+  int *d_unodes = nullptr, *d_idx = nullptr;
+  double *d_wexp = nullptr, *d_WN = nullptr, *d_fu = nullptr;
+  Arena step_arena;
+};
+
 // Per-step parameters kept in device memory, so a captured step graph can be
 // replayed: the obstacle and the time at the start of the step.
 struct StepCtx {
@@ -185,6 +207,7 @@ struct icr_scene {
   icr::Mesh mesh;
   icr::Factor fac;
   icr::Contacts con;
+  icr::Pairs pairs;
   icr::State st;
   icr::Arena mesh_arena, fac_arena, state_arena;
   // mapped contacts of icr_build_WH: distinct nodes, slot indices, nodal W_N
@@ -224,6 +247,7 @@ void contact_force_solve(icr_scene *s, const double *f, double *x);
 void ensure_rhs_capacity(icr_scene *s, int nc);
 void launch_fill(icr_scene *s, double *x, long n, double v);
 void launch_widen(icr_scene *s, const float *x, double *y, long n);   // y = (double) x
+void launch_narrow(icr_scene *s, const double *x, float *y, long n);  // y = (float) x
 // W_H = H A^-1 H^T, or J A^-1 J^T with J = C H when per-contact frames
 // [nc*9] are given (the standard rebuild of Algorithm 2).
 void build_WH_device(icr_scene *s, int nc, const int *node_ids, double *WH, bool validate,
@@ -282,6 +306,10 @@ void launch_proximity(hipStream_t st, int nc, const TW *WH, const double *p_free
 // World-frame forces of this step's contacts become the next step's warm
 // start (previous contacts cleared), then the step time advances.
 void launch_store_forces(icr_scene *s, int nc);
+// pair contacts of a step (first pairs.count contacts) and the node list of its W_H build
+void launch_pair_points(icr_scene *s, int nc);
+// fu = H_w^T f on the nodes of the step's W_H build
+void launch_node_forces(icr_scene *s, int nc, const double *f, double *fu);
 void launch_standard_proximity(icr_scene *s, int nc);
 
 }  // namespace icr

@@ -78,6 +78,7 @@ _SIGS = {
                                              C.POINTER(_D)]),
     "icr_proximity_update": (C.c_int, [_P, _I, _P, _P, _P, _D, _P]),
     "icr_set_candidates": (C.c_int, [_P, _I, _P, _P]),
+    "icr_set_pairs": (C.c_int, [_P, _I, _P, _P, _P, _P]),
     "icr_step": (C.c_int, [_P, C.POINTER(Obstacle), C.POINTER(StepOpts), C.POINTER(StepReport)]),
     "icr_reserve": (C.c_int, [_P, _I, _I]),
     "icr_get_state": (C.c_int, [_P, _P, _P, C.POINTER(_D)]),
@@ -216,6 +217,13 @@ class Scene:
         nodes = np.ascontiguousarray(nodes, dtype=np.int32)
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         self._check(self.L.icr_set_candidates(self._h, len(nodes), _np_ptr(nodes), _np_ptr(mu)))
+
+    def set_pairs(self, ids, weights, normals, mu):
+        ids = np.ascontiguousarray(ids, dtype=np.int32).reshape(-1, 4)
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1, 4)
+        nrm = np.ascontiguousarray(normals, dtype=np.float64).reshape(-1, 3)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        self._check(self.L.icr_set_pairs(self._h, len(ids), _np_ptr(ids), _np_ptr(w), _np_ptr(nrm), _np_ptr(mu)))
 
     # -- hot-path calls ------------------------------------------------------
     def build_WH(self, node_ids, WH, weights=None):
@@ -380,5 +388,8 @@ def scene_from_dict(sc, stream=None):
     s = Scene(stream)
     s.assemble(sc)
     s.factor()
+    if sc.get("pairs") is not None:
+        pr = sc["pairs"]
+        s.set_pairs(pr["ids"], pr["w"], pr["normals"], pr["mu"])
     s.set_candidates(sc["candidates"], sc["cand_mu"])
     return s

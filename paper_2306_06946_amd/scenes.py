@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-CONFIGS = ("tiny", "medium", "precision", "serving", "stress")
+CONFIGS = ("tiny", "medium", "precision", "serving", "stress", "stacked", "stacked_small")
 
 
 def box_grid(nx: int, ny: int, nz: int, s: float, jitter: float, rng: np.random.Generator):
@@ -232,6 +232,35 @@ def make_scene(config: str, seed: int = 0) -> dict:
         obs = dict(kind="sphere", normal=np.zeros(3), c0=c0, vel=np.array([0.5, 0.0, 0.1]), radius=R)
         mu = np.full(len(cand), 0.5)
         sc.update(gravity=np.array([0.0, 0.0, -9.81]), n_contacts=3000, n_steps=5, n_newton=8)
+    elif config in ("stacked", "stacked_small"):
+        # two deformable bodies stacked along z (the stress configuration:
+        # 30x30 node layers, 14 for each body, 75 600 DOF), the lower one
+        # clamped at its bottom; 2400 interface points x_1 - x_2 on the
+        # interface edges (upper body = body 1), normal +z (the lower body's
+        # top surface); a sphere pressed into the upper body's top face and
+        # sliding along x at 0.5 m/s; 600 sphere contacts among the top-face
+        # nodes; 3000 contacts in all (m = 9000), mu = 0.5, 8 Newton
+        # iterations.  stacked_small: 8x8 layers, 5 + 5, 120 points + 16.
+        if config == "stacked":
+            nx, ny, nzl, nzu, npair, nsph = 30, 30, 14, 14, 2400, 600
+        else:
+            nx, ny, nzl, nzu, npair, nsph = 8, 8, 5, 5, 120, 16
+        nodes, tets, ijk, body, pairs = stacked_grids(nx, ny, nzl, nzu, s, 0.2, rng)
+        nz = nzl + nzu
+        E = np.full(len(tets), 1.0e4)
+        fixed = (ijk[:, 2] == 0) & (body == 0)
+        ztop = nzl + nzu - 2
+        cand = np.nonzero((ijk[:, 2] == ztop) & (body == 1))[0]
+        ids, w = interface_edge_points(nx, ny, pairs, npair, rng)
+        width = (nx - 1) * s
+        R = 0.6 * width
+        off = rng.uniform(-0.1, 0.1, size=2) * width
+        c0 = np.array([(nx - 1) * s / 2 + off[0], (ny - 1) * s / 2 + off[1], ztop * s + R - 0.2 * s])
+        obs = dict(kind="sphere", normal=np.zeros(3), c0=c0, vel=np.array([0.5, 0.0, -0.1]), radius=R)
+        mu = np.full(len(cand), 0.5)
+        sc.update(gravity=np.array([0.0, 0.0, -9.81]), n_contacts=npair + nsph, n_steps=5, n_newton=8,
+                  body=body, pairs=dict(ids=ids, w=w, normals=np.tile([0.0, 0.0, 1.0], (npair, 1)),
+                                        mu=np.full(npair, 0.5)))
     else:
         raise ValueError(f"unknown config {config!r}")
 

@@ -863,7 +863,8 @@ def _mixed_run(sc, precision, refine, steps=1):
     q, v, _ = s.get_state()
     torch.cuda.synchronize()
     out = dict(WH=res["WH"].cpu().numpy(), lam=res["lam"].cpu().numpy(), status=res["status"].cpu().numpy(),
-               p=res["p"].cpu().numpy(), q=q.cpu().numpy(), v=v.cpu().numpy(), sweeps=reps[-1]["sweeps"])
+               p=res["p"].cpu().numpy(), q=q.cpu().numpy(), v=v.cpu().numpy(), sweeps=reps[-1]["sweeps"],
+               f=res["f"].cpu().numpy(), node_ids=res["node_ids"].cpu().numpy())
     s.close()
     return out
 
@@ -916,3 +917,129 @@ def test_mixed_precision_benchmark_configuration(advance):
              + f" status differences {n_diff} sweeps {got['sweeps']}")
         if refine >= 1:
             assert errs["WH"] <= 1e-6 and errs["lam"] <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Two deformable bodies: pair contacts x_1 - x_2 on the interface (Eq. 6,
+# 16-17) with the obstacle contacts of the sphere on the upper body
+# ---------------------------------------------------------------------------
+
+def test_two_body_steps_match_oracle():
+    """Three steps of two stacked bodies (120 interface points on shared edges,
+    a rank-deficient W, plus 16 sphere contacts) with 30 fixed PGS sweeps, as
+    the oracle runs them (R19-R21): selection, q_free, W_H, sweeps,
+    classification, lambda, p, q, v at 1e-10, and the nodal forces H^T f."""
+    icr = _icr()
+    sc = make_scene("stacked_small", 0)
+    s = icr.scene_from_dict(sc)
+    sim = O.Simulation(sc)
+    nc = sc["n_contacts"]
+    P = len(sc["pairs"]["ids"])
+    m = 3 * nc
+    for k in range(3):
+        _say(f"[gpu] two bodies step {k}")
+        rep = s.step(sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"], graph=False)
+        rec = []
+        out = sim.step(record=rec, max_sweeps=30, tol=0.0)
+        res = s.step_results(nc, with_WH=True)
+        q, v, _ = s.get_state()
+        ids = res["node_ids"].cpu().numpy()
+        assert np.all(ids[:P] == -1) and np.array_equal(ids[P:], out["nodes_c"])
+        assert _rel(res["q_free"].cpu().numpy() - sim.q_rest, out["q_free"] - sim.q_rest) <= 1e-10
+        assert _rel(res["WH"].cpu().numpy().reshape(m, m), out["WH"]) <= 1e-10
+        _sweeps_match(rep, rec)
+        assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+        assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+        assert _rel(res["p"].cpu().numpy() - out["p_free"], out["p"] - out["p_free"]) <= 1e-10
+        assert _rel(q.cpu().numpy() - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+        assert _rel(v.cpu().numpy(), out["v"]) <= 1e-10
+        f = res["f"].cpu().numpy()
+        pr = sc["pairs"]
+        H = O.mapping_H(np.vstack([pr["ids"], np.c_[out["nodes_c"], -np.ones((nc - P, 3), int)]]), sim.n,
+                        np.vstack([pr["w"], np.c_[np.ones(nc - P), np.zeros((nc - P, 3))]]))
+        assert _rel(H.T @ f, H.T @ out["f"].ravel()) <= 1e-10
+        _say(f"[gpu] two bodies step {k}: status {np.bincount(rec[-1]['status'], minlength=3).tolist()}")
+    s.close()
+
+
+def test_two_body_pairs_only_and_mixed_precision():
+    """Pairs alone (no obstacle contact: n_contacts = pair count) against the
+    oracle, and the mixed-precision step with pairs against the FP64 path
+    (1 refinement step: 1e-6 on W_H, 1e-5 on lambda)."""
+    icr = _icr()
+    sc = make_scene("stacked_small", 1)
+    P = len(sc["pairs"]["ids"])
+    sc_p = dict(sc, n_contacts=P)
+    s = icr.scene_from_dict(sc_p)
+    sim = O.Simulation(sc_p)
+    _say("[gpu] two bodies, pairs only")
+    rep = s.step(sc["obstacle"], P, sc["n_newton"], 30, 0.0, sc["j_inner"], graph=False)
+    rec = []
+    out = sim.step(record=rec, max_sweeps=30, tol=0.0)
+    res = s.step_results(P, with_WH=True)
+    q, _, _ = s.get_state()
+    _sweeps_match(rep, rec)
+    assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+    assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+    assert _rel(q.cpu().numpy() - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+    s.close()
+    # mixed precision: W is rank deficient here, so lambda is not unique and
+    # the unique nodal force H^T f carries the 1e-5 bound
+    nc = sc["n_contacts"]
+    ref = _mixed_run(sc, icr.FP64, 0)
+    got = _mixed_run(sc, icr.FP32_IR, 1)
+    assert np.array_equal(got["node_ids"], ref["node_ids"])
+    pr = sc["pairs"]
+    ob = ref["node_ids"][P:]
+    H = O.mapping_H(np.vstack([pr["ids"], np.c_[ob, -np.ones((nc - P, 3), int)]]), 3 * len(sc["nodes"]),
+                    np.vstack([pr["w"], np.c_[np.ones(nc - P), np.zeros((nc - P, 3))]]))
+    e_wh, e_lam = _rel(got["WH"], ref["WH"]), _rel(got["lam"], ref["lam"])
+    e_nf = _rel(H.T @ got["f"], H.T @ ref["f"])
+    _say(f"[gpu] two bodies mixed refine=1: W_H {e_wh:.2e} lambda {e_lam:.2e} H^T f {e_nf:.2e} "
+         f"status differences {int(np.sum(got['status'] != ref['status']))}")
+    assert e_wh <= 1e-6 and e_nf <= 1e-5
+
+
+def test_two_body_config_at_full_size():
+    """The two-body configuration at full size (75 600 DOF, 2400 interface
+    points + 600 sphere contacts, W_H 9000 x 9000, 8 Newton x 30 sweeps): W_H
+    exactly symmetric and, through W_H x for seeded random x, equal to
+    H A^-1 H^T x by oracle solves; the Newton loop against the oracle's
+    Algorithm 3 on that W_H (sweeps, classification, lambda, p)."""
+    icr = _icr()
+    sc = make_scene("stacked", 0)
+    nc = sc["n_contacts"]
+    P = len(sc["pairs"]["ids"])
+    m = 3 * nc
+    _say("[gpu] stacked: assemble+factor, one step")
+    s = icr.scene_from_dict(sc)
+    rep = s.step(sc["obstacle"], nc, sc["n_newton"], 30, 0.0, sc["j_inner"], graph=False)
+    res = s.step_results(nc, with_WH=True)
+    WH = res["WH"].cpu().numpy().reshape(m, m)
+    assert np.array_equal(WH, WH.T)
+    _say("[gpu] stacked: oracle solves")
+    asm = O.assemble(sc)
+    fac = O.CholeskyFactor(asm["A"])
+    q0 = sc["nodes"].ravel()
+    dv, q_free, _ = O.free_motion(asm, fac, sc, q0, np.zeros_like(q0), q0)
+    nodes = O.select_contacts(q_free, dict(sc, n_contacts=nc - P), sc["h"])
+    ids_all = res["node_ids"].cpu().numpy()
+    assert np.array_equal(ids_all[P:], nodes)
+    pr = sc["pairs"]
+    ids = np.vstack([pr["ids"], np.c_[nodes, -np.ones((nc - P, 3), int)]])
+    w = np.vstack([pr["w"], np.c_[np.ones(nc - P), np.zeros((nc - P, 3))]])
+    H = O.mapping_H(ids, asm["n"], w)
+    xs = np.random.default_rng(8).standard_normal((m, 2))
+    assert _rel(WH @ xs, H @ fac.solve(H.T @ xs)) <= 1e-10
+    _say("[gpu] stacked: oracle Newton loop on the checked W_H")
+    p_free, p_start = H @ q_free, H @ q0
+    mu = np.concatenate([pr["mu"], sc["cand_mu"][np.searchsorted(sc["candidates"], nodes)]])
+    rec = []
+    O.newton_fast(WH, p_free, p_start, sc["obstacle"], 0.0, sc["h"], mu, sc["h"], np.zeros(m), sc["n_newton"], 30,
+                  0.0, sc["j_inner"], record=rec, margins=True, pair_normals=pr["normals"])
+    _newton_report("stacked", rec, None)
+    _sweeps_match(rep, rec)
+    assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+    assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+    assert _rel(res["p"].cpu().numpy() - p_free, rec[-1]["p"] - p_free) <= 1e-10
+    s.close()

@@ -697,3 +697,69 @@ def test_two_body_WH_is_the_sum_of_the_bodies_compliances():
         assert np.all(np.sign(w[:, :2]) > 0) and np.all(np.sign(w[:, 2:]) < 0)
         ref += Hb @ np.linalg.inv(Ab) @ Hb.T
     assert np.linalg.norm(WH - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+# Pair contacts between two bodies (R19-R21)
+# ---------------------------------------------------------------------------
+
+def test_pair_forces_act_equal_and_opposite_on_the_two_bodies():
+    """H^T f of the pair contacts (Eq. 16: c_1 = J_1^T lambda, c_2 = -J_2^T lambda)
+    sums to the total pair force over body 1's nodes and to minus it over
+    body 2's, per axis, after a step of two stacked bodies."""
+    sc = make_scene("stacked_small", 0)
+    sim = O.Simulation(sc)
+    out = sim.step(max_sweeps=30, tol=0.0)
+    pr = sc["pairs"]
+    P = len(pr["ids"])
+    H = O.mapping_H(pr["ids"], sim.n, pr["w"])
+    g = (H.T @ out["f"][:P].ravel()).reshape(-1, 3)
+    tot = out["f"][:P].sum(axis=0)
+    assert np.linalg.norm(tot) > 0
+    up, lo = sc["body"] == 1, sc["body"] == 0
+    assert np.allclose(g[up].sum(axis=0), tot, rtol=1e-12, atol=1e-15 * np.abs(tot).max())
+    assert np.allclose(g[lo].sum(axis=0), -tot, rtol=1e-12, atol=1e-15 * np.abs(tot).max())
+
+
+def test_pair_contacts_only_reach_the_newton_fixed_point_at_once():
+    """Pairs alone have fixed frames and affine gaps (R20), so every Newton
+    iteration after the first solves the same problem: p_k = p_1 for k >= 2.
+    Node-to-node pairs on distinct interface node pairs keep W full rank, so
+    PGS converges (interface points on shared edges make W rank deficient
+    and its iterates converge only slowly)."""
+    sc = make_scene("stacked_small", 1)
+    rng = np.random.default_rng(9)
+    from paper_2306_06946_amd.scenes import stacked_grids
+    _, _, _, _, prs = stacked_grids(8, 8, 5, 5, 0.01, 0.2, np.random.default_rng(1))
+    pick = rng.choice(len(prs), 20, replace=False)
+    ids = np.full((20, 4), -1)
+    ids[:, 0], ids[:, 1] = prs[pick, 1], prs[pick, 0]
+    w = np.zeros((20, 4))
+    w[:, 0], w[:, 1] = 1.0, -1.0
+    sc = dict(sc, n_contacts=20, pairs=dict(ids=ids, w=w, normals=np.tile([0.0, 0.0, 1.0], (20, 1)),
+                                            mu=np.full(20, 0.5)))
+    sim = O.Simulation(sc)
+    rec = []
+    sim.step(record=rec, max_sweeps=400, tol=1e-13)
+    assert rec[0]["eps"] <= 1e-13 and np.sum(rec[0]["status"] != 0) > 0
+    for r in rec[1:]:   # at the PGS tolerance: later iterations only refine the same solution
+        assert np.linalg.norm(r["p"] - rec[0]["p"]) <= 1e-9 * np.linalg.norm(rec[0]["p"])
+
+
+def test_single_frictionless_pair_closed_form():
+    """One pair, mu = 0: lambda_n = max(0, -delta_n / (h^2 W_nn)) (the
+    Signorini closed form on the pair's normal), lambda_t = 0."""
+    sc = make_scene("stacked_small", 2)
+    pr = dict(sc["pairs"])
+    pr = dict(ids=pr["ids"][:1], w=pr["w"][:1], normals=pr["normals"][:1], mu=np.zeros(1))
+    sc = dict(sc, pairs=pr, n_contacts=1)
+    sim = O.Simulation(sc)
+    rec = []
+    out = sim.step(record=rec, max_sweeps=5, tol=0.0)
+    r = rec[0]
+    h = sc["h"]
+    lam_n = max(0.0, -r["d"][0] / (h * h * r["W"][0, 0]))
+    assert lam_n > 0
+    assert math.isclose(r["lam"][0], lam_n, rel_tol=1e-12)
+    assert r["lam"][1] == 0.0 and r["lam"][2] == 0.0
+    del out
