@@ -362,7 +362,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic seeded scene (jittered grid tet mesh, rigid sphere); no paper dataset exists",
+        "data": ("synthetic seeded scene (jittered grid tet mesh, rigid sphere"
+                 + (", two stacked bodies with interface pair contacts" if sc.get("pairs") is not None else "")
+                 + "); no paper dataset exists"),
         "config": {"workload": f"{args.config}: {sc['grid'][0]}x{sc['grid'][1]}x{sc['grid'][2]} node grid, "
                                f"{3 * len(sc['nodes'])} DOF, {nc} contacts (W_H {m}x{m}), {n_newton} Newton x "
                                f"{args.sweeps} PGS sweeps, FP64",
@@ -375,6 +377,10 @@ def main():
         "status_counts": [reps[-1]["n_separate"], reps[-1]["n_stick"], reps[-1]["n_slip"]],
         "roofline": roof,
     }
+    has_pairs = sc.get("pairs") is not None
+    if has_pairs and (args.standard_steps > 0 or args.per_constraint_steps > 0):
+        log("[bench] pair contacts run the fast scheme only: standard and per-constraint legs skipped")
+        args.standard_steps = args.per_constraint_steps = 0
     if args.standard_steps > 0:
         # same trajectory: a second scene runs the standard scheme (warm-up,
         # then a restart from the initial state) and its steps are compared
