@@ -1110,7 +1110,7 @@ __device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds 
 // in the lanes' registers, forces, records and statuses in LDS; no barrier is
 // taken inside the sweep.
 template <int NS, int J>
-__device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
+__device__ __forceinline__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int ln = threadIdx.x & 63;
   double g[NS][3];
 #pragma unroll
@@ -1143,7 +1143,7 @@ __device__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int
 // barrier follows, then every chain wave runs the same local solve and
 // updates its own rows (the other waves only take the barriers).
 template <int J>
-__device__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
+__device__ __forceinline__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
   const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const bool chain = w < Q;
   const long colstride = (long)(128 * Q) * (PGS_BLK / 2);   // double2 per contact column (nsp = 128 Q)
