@@ -79,6 +79,31 @@ def profiled_traffic(kernel):
     return None
 
 
+def profiled_issue(kernel):
+    """Single-wave issue check of `kernel` from the committed rocprofv3 SQ
+    counters (profiles/pgs_issue_precision.md, line `issue_check <kernel>
+    <VALU instructions per launch> <busy cycles per launch> <cycles per FP64
+    VALU instruction> <source hash>`), or None when the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pgs_issue_precision.md")
+    src = os.path.join(ROOT, "paper_2306_06946_amd", "csrc", "k_contact.hip")
+    try:
+        lines = open(path).read().splitlines()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    for ln in lines:
+        f = ln.strip().strip("`").split()
+        if len(f) == 6 and f[0] == "issue_check" and f[1] == kernel and f[5] == digest:
+            valu, busy, cpi = float(f[2]), float(f[3]), float(f[4])
+            return {"valu_insts_per_launch": valu, "busy_cycles_per_launch": busy, "cycles_per_valu": cpi,
+                    "issue_bound_cycles": valu * cpi, "frac": valu * cpi / busy,
+                    "note": "one wave's dependent chain: FP64 VALU issue of the launch's instructions "
+                            "against its busy cycles (profiles/pgs_issue_precision.md)"}
+    return None
+
+
 def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
     """Serving mix through icr_server: closed-loop saturation with 1, 4 and
     `slots` slots, then Poisson arrivals at `rate` steps/s over `seconds` on
@@ -343,8 +368,14 @@ def main():
     roof["kernel"] = {"pgs": "k_pgs_active", "build_WH": "k_rhs_*", "update_W": "k_update_W"}[dom]
     roof["frac"] = roof["achieved"] / roof["peak"]
     # the counters were taken on the precision workload at the default sweep count
-    roof["traffic"] = (profiled_traffic(roof["kernel"]) if args.config == "precision" and args.sweeps == 30
-                       else None)
+    on_profiled = args.config == "precision" and args.sweeps == 30
+    roof["traffic"] = profiled_traffic(roof["kernel"]) if on_profiled else None
+    if dom == "pgs":
+        # SURVEY's unit for PGS is the bytes a dense sweep streams (m^2 * 8 per
+        # sweep); the kernel sweeps the active set in LDS and registers and is
+        # bound by its sequential contact chain, so the HBM fraction is nominal
+        roof["basis"] = "nominal: dense-sweep bytes 30 x m^2 x 8 per launch; the kernel is a latency-bound chain"
+        roof["latency"] = profiled_issue("k_pgs_active") if on_profiled else None
     out = {
         "metric": ("time-steps/sec (W_H build + Newton W updates) at "
                    + ("60k" if args.config == "precision" else f"{3 * len(sc['nodes']) / 1000:.1f}k")
