@@ -184,7 +184,7 @@ icr_status icr_solve_contacts(icr_scene *s, int32_t n_c, const double *W, const 
  * icr_solve_contacts without a scene.  Same arguments, kernels and results;
  * the call allocates nothing and enqueues its work on `stream` (hipStream_t
  * as void*, NULL = the null stream) of the current device.  Its work buffers
- * live in one static device array of the library, about 21 MB per GPU, held
+ * live in one static device array of the library, about 32 MB per GPU, held
  * until the process ends; every call on a GPU shares that GPU's array, so
  * calls that overlap on one GPU (other streams, other host threads) race.
  * n_c <= 1024.  Errors are return codes only (no scene holds a message):

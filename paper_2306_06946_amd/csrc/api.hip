@@ -83,7 +83,17 @@ void ensure_contact_buffers(icr_scene *s, int nc) {
   C.pgs.nS = C.arena.alloc<int>(1);
   C.pgs.rec = C.arena.alloc<double>(pgs_rec_elems(nc));
   C.pgs.gS = C.arena.alloc<double>(pgs_rec_elems(nc));
-  C.pgs.ctl = C.arena.alloc<int>(2);
+  C.pgs.ctl = C.arena.alloc<int>(4);
+  if (nc > kPgsWaveMax) {
+    C.pgs.recAll = C.arena.alloc<double>((size_t)nc * kPgsRecWidth);
+    C.pgs.Wblk = C.arena.alloc<double>(pgs_coop_blk_elems(nc));
+    C.pgs.dl = C.arena.alloc<double>(2 * 3 * kPgsCoopB);
+    C.pgs.chg = C.arena.alloc<int>(2 * kPgsCoopB);
+    C.pgs.csync = C.arena.alloc<int>(kPgsCoopSync);
+  } else {
+    C.pgs.recAll = C.pgs.Wblk = C.pgs.dl = nullptr;
+    C.pgs.chg = C.pgs.csync = nullptr;
+  }
   pgs_prepare();
   C.d_status = C.arena.alloc<int8_t>(nc);
   C.d_sweeps = C.arena.alloc<int>(kMaxNewton);

@@ -3,6 +3,8 @@
 // gaps (Eq. 7, 10, 26), the fast compliance update W = C W_H C^T (Eq. 28),
 // projected Gauss-Seidel (Eq. 18-19, Algorithm 1), and the proximity update
 // p_k = p_free + h^2 W_H C_k^T lambda_k (Eq. 31).
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 #include <mutex>
 
@@ -1011,6 +1013,7 @@ struct PgsLds {
   unsigned char inS[PGS_MAX_NC];
   double Rmin;   // settle threshold of the set: B below it settles every skipped contact
   int nS, flag, stop, nu, zflag, settled;
+  int cprog, cflag;   // block Gauss-Seidel: contacts done by the chain, next block staged
 };
 
 static_assert(sizeof(PgsLds) <= 160 * 1024, "active-set PGS state must fit one CU's LDS");
@@ -1058,7 +1061,7 @@ __device__ inline void chain_rec(ChainRec &c, const PgsLds &L, int i) {
 // they are used.
 template <int K, int NS, int J>
 __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], const ChainRec &c,
-                                  double (&g)[NS][3], PgsLds &L, int j_inner, int ln) {
+                                  double (&g)[NS][3], PgsLds &L, int j_inner, int ln, int o) {
   const int li = i & 63;
   double rc[19];
 #pragma unroll
@@ -1070,11 +1073,11 @@ __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], co
   dd[2] = readlane_f64(g[K][2], li);
   const Local rs = local_solve_rec<J>(rc, dd, j_inner);
   if (ln == 0) {
-    double *lp = L.rec + PGS_RW * i + 19;
+    double *lp = L.rec + PGS_RW * (i + o) + 19;
     lp[0] = rs.l[0];
     lp[1] = rs.l[1];
     lp[2] = rs.l[2];
-    L.stS[i] = (unsigned char)rs.st;
+    L.stS[i + o] = (unsigned char)rs.st;
   }
   const double d0 = rs.l[0] - lo0, d1 = rs.l[1] - lo1, d2 = rs.l[2] - lo2;
 #pragma unroll
@@ -1088,51 +1091,60 @@ __device__ inline void chain_step(int i, const double2 (&X)[NS][PGS_BLK / 2], co
 
 // Contacts 64K .. 64K+63 of the sweep; blocks of the next two contacts and the
 // record of the next one are in flight while the current one is solved.
-// Loads past the end re-read the last contact (unused).
-template <int K, int NS, int J>
-__device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln,
+// Loads past the end re-read the last contact (unused).  The set's records,
+// statuses and gaps start at contact o of the LDS arrays.  PUB: after every
+// two contacts lane 0 publishes how many are done in L.cprog (LDS operations
+// of one wave complete in order, so a reader that sees the count sees the
+// forces; the compiler fence keeps the stores in that order).
+template <int K, int NS, int J, bool PUB>
+__device__ inline void chain_slot(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln, int o,
                                   double (&g)[NS][3], double2 (&A)[NS][PGS_BLK / 2], double2 (&B)[NS][PGS_BLK / 2],
                                   ChainRec &rA, ChainRec &rB) {
   const int last = nS - 1, end = min(nS, 64 * K + 64);
   for (int i = 64 * K; i < end; i += 2) {
-    chain_rec(rB, L, min(i + 1, last));
-    chain_step<K, NS, J>(i, A, rA, g, L, j_inner, ln);
+    chain_rec(rB, L, min(i + 1, last) + o);
+    chain_step<K, NS, J>(i, A, rA, g, L, j_inner, ln, o);
     chain_load<NS>(A, Wb, min(i + 2, last), ln);
     if (i + 1 < end) {
-      chain_rec(rA, L, min(i + 2, last));
-      chain_step<K, NS, J>(i + 1, B, rB, g, L, j_inner, ln);
+      chain_rec(rA, L, min(i + 2, last) + o);
+      chain_step<K, NS, J>(i + 1, B, rB, g, L, j_inner, ln, o);
     }
     chain_load<NS>(B, Wb, min(i + 3, last), ln);
+    if constexpr (PUB) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (ln == 0) __hip_atomic_store(&L.cprog, min(i + 2, end), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
 }
 
 // Sequential sweep over S by wave 0 alone: gaps of S (without own term) live
 // in the lanes' registers, forces, records and statuses in LDS; no barrier is
 // taken inside the sweep.
-template <int NS, int J>
-__device__ __forceinline__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
+template <int NS, int J, bool PUB = false>
+__device__ __forceinline__ void chain_wave(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner,
+                                           int o = 0) {
   const int ln = threadIdx.x & 63;
   double g[NS][3];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int c = ln + 64 * k;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) g[k][q] = c < nS ? L.gS[3 * c + q] : 0.0;
+    for (int q = 0; q < 3; ++q) g[k][q] = c < nS ? L.gS[3 * (c + o) + q] : 0.0;
   }
   const int last = nS - 1;
   double2 A[NS][PGS_BLK / 2], B[NS][PGS_BLK / 2];
   ChainRec rA, rB;
   chain_load<NS>(A, Wb, 0, ln);
   chain_load<NS>(B, Wb, min(1, last), ln);
-  chain_rec(rA, L, 0);
-  chain_slot<0, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
-  if constexpr (NS > 1) chain_slot<1, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB);
+  chain_rec(rA, L, o);
+  chain_slot<0, NS, J, PUB>(nS, Wb, L, j_inner, ln, o, g, A, B, rA, rB);
+  if constexpr (NS > 1) chain_slot<1, NS, J, PUB>(nS, Wb, L, j_inner, ln, o, g, A, B, rA, rB);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const int c = ln + 64 * k;
     if (c < nS) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[k][q];
+      for (int q = 0; q < 3; ++q) L.gS[3 * (c + o) + q] = g[k][q];
     }
   }
 }
@@ -1602,6 +1614,453 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const TW *__restr
   }
 }
 
+// ---- large active sets: block Gauss-Seidel over the whole GPU --------------
+//
+// When the active set outgrows the register chains (k_pgs_active hands over
+// with ctl[0] = 1 and the sweep to resume in ctl[1]), the remaining sweeps
+// run here, with the iterates of the sequential sweep: the contacts are
+// taken in blocks of 128 in index order, and every block's force changes
+// reach the gaps of all contacts, g += W~[:, block] dlambda (rows of the
+// exactly symmetric W stand for its columns), before those contacts' turn.
+// One cooperative launch with no grid barrier inside the sweeps:
+//  - workgroup 0 (the lead) runs the chain of a block in wave 0 (the register
+//    chain of the active-set kernel, which skips nothing: separated contacts
+//    are solved and stay at zero); meanwhile waves 1-3 and 5-7 add the
+//    block's force changes to the gaps of the NEXT block as the chain
+//    publishes them, and wave 4 stages the next block's records and forces
+//    in the other half of the LDS arrays.  So the next chain starts without
+//    waiting for the rest of the GPU.
+//  - the other workgroups push each published block's changes into all other
+//    gap rows (64-row chunks, each chunk always owned by the same workgroup),
+//    one block behind the lead, and report the last block they finished.
+// The lead reads the next block's gaps only after every pushing workgroup
+// finished the block before the current one, and reuses a block's change
+// list (double-buffered) only after all of them read it.  Launched only when
+// the stream is not being captured (else k_pgs_single continues).
+constexpr int COOP_B = kPgsCoopB;   // contacts per block
+constexpr int COOP_NT = PGS_NT;     // threads per workgroup
+constexpr int COOP_MAXG = 128;      // workgroups of the launch at most
+static_assert(3 * COOP_B == 6 * 64, "a block's gap rows are six 64-row chunks");
+static_assert(COOP_NT == 512, "lead workgroup: chain wave, staging wave, six follower waves");
+// sync words: [0] last published block, [1] stop, [2..3] changed contacts per
+// list buffer, [4] a wait gave up, [8 + w] last block pushed by workgroup w
+constexpr int COOP_SYNC_PUB = 0, COOP_SYNC_STOP = 1, COOP_SYNC_CNT = 2, COOP_SYNC_ERR = 4, COOP_SYNC_PROG = 8;
+// Every wait is bounded (polls of device memory / of LDS, seconds in all,
+// far beyond any legitimate wait): a wait that gives up sets the error word,
+// every workgroup stops, and the call reports eps = NaN (not converged).
+constexpr int COOP_SPIN_DEV = 1 << 22, COOP_SPIN_LDS = 1 << 24;
+static_assert(COOP_SYNC_PROG + COOP_MAXG <= kPgsCoopSync, "sync words");
+struct CoopArgs {
+  int nc;
+  const void *W;
+  const double *d, *mu;
+  double h2;
+  double *lam;
+  int8_t *status;
+  int max_sweeps;
+  double tol;
+  int j_inner;
+  int *sweeps_out;
+  double *eps_out;
+  const int *ctl;    // [0] handover, [1] first sweep
+  double *g;         // [3 nc] gaps with the own term
+  double *recAll;    // [nc * PGS_RW] records
+  double *Wblk;      // [nblocks * COOP_B * COOP_B * PGS_BLK] blocked diagonal couplings
+  double *dl;        // [2][3 COOP_B] force changes of the last two blocks
+  int *chg;          // [2][COOP_B] their changed contacts (block-local)
+  int *sync;         // [kPgsCoopSync] sync words
+};
+
+// Loads of data another workgroup of the launch wrote go to the
+// device-coherent level, past this compute unit's own cache.
+__device__ inline double ld_dev(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_dev(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_dev(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline int ld_wg(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void st_wg(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+// y[r] = base[r] + h2 sum_k sum_a M[(3 c_k + a) m + r] v[3 k + a] for the rows
+// of the 64-row chunks first, first + stride, ... outside [skip_lo, skip_hi):
+// wave v takes list entries v, v + 8, ... (four at a time, twelve loads in
+// flight); the eight partial sums are added in wave order.  W streams
+// through with non-temporal loads, so that it does not evict the blocked
+// couplings the chain reads.
+template <class TW>
+__device__ void coop_rows(int m, const TW *__restrict__ M, const int *list, int nlist, const double *vals,
+                          int cbase, const double *base, double h2, double *y, double *part, int first, int stride,
+                          int skip_lo, int skip_hi) {
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  constexpr int NW = COOP_NT / 64;
+  const int nchunk = (m + 63) / 64;
+  for (int ch = first; ch < nchunk; ch += stride) {
+    if (ch >= skip_lo && ch < skip_hi) continue;
+    const int r = 64 * ch + ln;
+    double a = 0.0;
+    if (r < m) {
+      for (int k = wv; k < nlist; k += 4 * NW) {
+        double x[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int kk = k + NW * q;
+          const long c3 = 3L * (cbase + list[kk < nlist ? kk : k]);
+#pragma unroll
+          for (int t = 0; t < 3; ++t) x[q][t] = kk < nlist ? (double)__builtin_nontemporal_load(M + (c3 + t) * m + r) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int kk = k + NW * q;
+          if (kk < nlist) {
+            const double *vk = vals + 3 * kk;
+            a = fma(x[q][0], vk[0], a);
+            a = fma(x[q][1], vk[1], a);
+            a = fma(x[q][2], vk[2], a);
+          }
+        }
+      }
+    }
+    part[wv * 64 + ln] = a;
+    __syncthreads();
+    if (wv == 0 && r < m) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += part[w * 64 + ln];
+      y[r] = ld_dev(base + r) + h2 * t;
+    }
+    __syncthreads();
+  }
+}
+
+// Own-term-free gap of row e of the block staged at contact o of the LDS
+// arrays: g - w lambda, w the contact's 3x3 block (record entries 0-5 =
+// w00 w01 w02 w11 w12 w22), lambda its current force (entries 19-21).
+__device__ inline double coop_own_free(const PgsLds &L, int o, int e, double g) {
+  const double *rc = L.rec + PGS_RW * (o + e / 3);
+  const int r = e % 3;
+  const double w0 = r == 0 ? rc[0] : (r == 1 ? rc[1] : rc[2]);
+  const double w1 = r == 0 ? rc[1] : (r == 1 ? rc[3] : rc[4]);
+  const double w2 = r == 0 ? rc[2] : (r == 1 ? rc[4] : rc[5]);
+  return g - (w0 * rc[19] + w1 * rc[20] + w2 * rc[21]);
+}
+
+// Lead workgroup (see above).
+template <class TW>
+__device__ void coop_lead(const CoopArgs &a, PgsLds &L, int sweep0) {
+  const TW *__restrict__ W = static_cast<const TW *>(a.W);
+  const int nc = a.nc, m = 3 * nc, nb = (nc + COOP_B - 1) / COOP_B;
+  const double h2 = a.h2;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const long blk_elems = (long)COOP_B * COOP_B * PGS_BLK;
+  const int G = gridDim.x;
+  const int total = (a.max_sweeps - sweep0) * nb;   // blocks to sweep
+  int sweep = sweep0;
+  double eps = 0.0;
+  if (total > 0) {
+    // block 0 staged at contact 0 of the LDS arrays
+    {
+      const int nB = min(COOP_B, nc);
+      for (int e = tid; e < nB * 19; e += COOP_NT) L.rec[PGS_RW * (e / 19) + e % 19] = a.recAll[PGS_RW * (e / 19) + e % 19];
+      for (int e = tid; e < 3 * nB; e += COOP_NT) {
+        const double v = a.lam[e];
+        L.rec[PGS_RW * (e / 3) + 19 + e % 3] = v;
+        L.lamS0[e] = v;
+      }
+      __syncthreads();
+      for (int e = tid; e < 3 * nB; e += COOP_NT) L.gS[e] = coop_own_free(L, 0, e, ld_dev(a.g + e));
+      if (tid == 0) {
+        L.cprog = 0;
+        L.cflag = 0;
+        L.stop = 0;
+      }
+      __syncthreads();
+    }
+    double dsum = 0.0, nl2 = 0.0;   // wave 0: sums of the sweep
+    for (int s = 0; s < total; ++s) {
+      const int b = s % nb, bn = (b + 1) % nb, p = s & 1;
+      const int o = p ? COOP_B : 0, o1 = COOP_B - o;
+      const int c0 = COOP_B * b, nB = min(COOP_B, nc - c0), nsp = pgs_wave_pad(nB);
+      const int cn0 = COOP_B * bn, nBn = min(COOP_B, nc - cn0);
+      if (wv == 0) {
+        const double *Wb = a.Wblk + (long)b * blk_elems;
+        if (a.j_inner == 8) {
+          if (nsp == 64)
+            chain_wave<1, 8, true>(nB, Wb, L, a.j_inner, o);
+          else
+            chain_wave<2, 8, true>(nB, Wb, L, a.j_inner, o);
+        } else {
+          if (nsp == 64)
+            chain_wave<1, 0, true>(nB, Wb, L, a.j_inner, o);
+          else
+            chain_wave<2, 0, true>(nB, Wb, L, a.j_inner, o);
+        }
+      } else if (wv == 4) {
+        // stage the next block's records and forces (unchanged by this chain)
+        for (int e = ln; e < nBn * 19; e += 64)
+          L.rec[PGS_RW * (o1 + e / 19) + e % 19] = a.recAll[PGS_RW * (long)(cn0 + e / 19) + e % 19];
+        for (int e = ln; e < 3 * nBn; e += 64) {
+          const double v = a.lam[3 * cn0 + e];
+          L.rec[PGS_RW * (o1 + e / 3) + 19 + e % 3] = v;
+          L.lamS0[3 * o1 + e] = v;
+        }
+        // every pushing workgroup finished block s - 1: the next block's gap
+        // rows hold all earlier changes, and list buffer p ^ 1 is free
+        for (int spin = 0;; ++spin) {
+          bool ok = true;
+          for (int w = 1 + ln; w < G; w += 64) ok &= ld_dev(a.sync + COOP_SYNC_PROG + w) >= s - 1;
+          if (__ballot(!ok) == 0ull) break;
+          if (spin == COOP_SPIN_DEV) {
+            if (ln == 0) st_dev(a.sync + COOP_SYNC_ERR, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (ln == 0) st_wg(&L.cflag, 1);
+      }
+      // waves 1-3, 5-7: row f of the next block, f < 3 nBn
+      const bool follower = wv != 0 && wv != 4;
+      const int f = (wv < 4 ? wv - 1 : wv - 2) * 64 + ln;
+      double acc = 0.0, gold = 0.0;
+      bool have_g = false;
+      if (follower) {
+        const bool act = f < 3 * nBn;
+        const long row = 3L * cn0 + (act ? f : 0);
+        for (int i = 0; i < nB; i += 4) {
+          double x[4][3];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const long c3 = 3L * (c0 + min(i + q, nB - 1));
+#pragma unroll
+            for (int t = 0; t < 3; ++t) x[q][t] = (double)__builtin_nontemporal_load(W + (c3 + t) * m + row);
+          }
+          const int need = min(i + 4, nB);
+          for (int spin = 0; ld_wg(&L.cprog) < need; ++spin) {
+            if (spin == COOP_SPIN_LDS) {
+              st_dev(a.sync + COOP_SYNC_ERR, 1);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (i + q < nB) {
+              const double *rc = L.rec + PGS_RW * (o + i + q) + 19;
+              const double *l0 = L.lamS0 + 3 * (o + i + q);
+              acc = fma(x[q][0], rc[0] - l0[0], acc);
+              acc = fma(x[q][1], rc[1] - l0[1], acc);
+              acc = fma(x[q][2], rc[2] - l0[2], acc);
+            }
+          }
+          if (!have_g && ld_wg(&L.cflag) != 0) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            gold = act ? ld_dev(a.g + row) : 0.0;
+            have_g = true;
+          }
+        }
+        if (!have_g) {
+          for (int spin = 0; ld_wg(&L.cflag) == 0; ++spin) {
+            if (spin == COOP_SPIN_LDS) {
+              st_dev(a.sync + COOP_SYNC_ERR, 1);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          gold = act ? ld_dev(a.g + row) : 0.0;
+        }
+      }
+      __syncthreads();
+      if (wv == 0) {
+        // new forces and statuses out, the changed contacts listed
+        int cnt = 0;
+        for (int i0 = 0; i0 < nB; i0 += 64) {
+          const int i = i0 + ln;
+          double d0 = 0.0, d1 = 0.0, d2 = 0.0, q2 = 0.0;
+          if (i < nB) {
+            const double *rc = L.rec + PGS_RW * (o + i);
+            d0 = rc[19] - L.lamS0[3 * (o + i)];
+            d1 = rc[20] - L.lamS0[3 * (o + i) + 1];
+            d2 = rc[21] - L.lamS0[3 * (o + i) + 2];
+            q2 = rc[19] * rc[19] + rc[20] * rc[20] + rc[21] * rc[21];
+            a.lam[3 * (c0 + i)] = rc[19];
+            a.lam[3 * (c0 + i) + 1] = rc[20];
+            a.lam[3 * (c0 + i) + 2] = rc[21];
+            a.status[c0 + i] = (int8_t)L.stS[o + i];
+          }
+          const bool ch = (d0 != 0.0) | (d1 != 0.0) | (d2 != 0.0);
+          const unsigned long long bal = __ballot(ch);
+          if (ch) {
+            const int k = cnt + __popcll(bal & ((1ull << ln) - 1ull));
+            a.chg[COOP_B * p + k] = i;
+            a.dl[3 * COOP_B * p + 3 * k] = d0;
+            a.dl[3 * COOP_B * p + 3 * k + 1] = d1;
+            a.dl[3 * COOP_B * p + 3 * k + 2] = d2;
+          }
+          cnt += __popcll(bal);
+          double sq = d0 * d0 + d1 * d1 + d2 * d2;
+          for (int w = 32; w > 0; w >>= 1) {
+            sq += __shfl_xor(sq, w, 64);
+            q2 += __shfl_xor(q2, w, 64);
+          }
+          dsum += sq;   // same order every time
+          nl2 += q2;
+        }
+        if (ln == 0) a.sync[COOP_SYNC_CNT + p] = cnt;
+        int stop = 0;
+        if (b == nb - 1) {
+          // end of the sweep: eps = |lambda_i - lambda_{i-1}| / |lambda_i|
+          const double diff = sqrt(dsum), nl = sqrt(nl2);
+          eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
+          ++sweep;
+          stop = (eps <= a.tol || sweep >= a.max_sweeps) ? 1 : 0;
+          dsum = nl2 = 0.0;
+        }
+        if (ld_dev(a.sync + COOP_SYNC_ERR) != 0) stop = 1;
+        if (ln == 0) {
+          L.stop = stop;
+          if (stop) a.sync[COOP_SYNC_STOP] = 1;
+        }
+      } else if (follower && f < 3 * nBn) {
+        const double gn = gold + h2 * acc;
+        a.g[3L * cn0 + f] = gn;
+        L.gS[3 * o1 + f] = coop_own_free(L, o1, f, gn);
+      }
+      __threadfence();
+      if (tid == 0) {
+        L.cprog = 0;
+        L.cflag = 0;
+      }
+      __syncthreads();
+      if (tid == 0) st_dev(a.sync + COOP_SYNC_PUB, s);
+      if (L.stop) break;
+    }
+  } else if (tid == 0) {
+    a.sync[COOP_SYNC_STOP] = 1;
+    __threadfence();
+    st_dev(a.sync + COOP_SYNC_PUB, 0);
+  }
+  if (tid == 0) {
+    *a.sweeps_out = sweep;
+    if (ld_dev(a.sync + COOP_SYNC_ERR) != 0)
+      *a.eps_out = NAN;
+    else if (total > 0)
+      *a.eps_out = eps;
+  }
+}
+
+// Pushing workgroups: block s's changes into every owned chunk of gap rows
+// outside the next block, in block order, until the lead stops.
+template <class TW>
+__device__ void coop_push(const CoopArgs &a, PgsLds &L) {
+  const TW *__restrict__ W = static_cast<const TW *>(a.W);
+  const int nc = a.nc, m = 3 * nc, nb = (nc + COOP_B - 1) / COOP_B;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  for (int s = 0;; ++s) {
+    if (tid == 0) {
+      int stop = 0;
+      for (int spin = 0; ld_dev(a.sync + COOP_SYNC_PUB) < s && (stop = ld_dev(a.sync + COOP_SYNC_STOP)) == 0; ++spin) {
+        if (spin == COOP_SPIN_DEV) {
+          st_dev(a.sync + COOP_SYNC_ERR, 1);
+          stop = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!stop) stop = ld_dev(a.sync + COOP_SYNC_STOP);
+      L.stop = stop;
+    }
+    __syncthreads();
+    if (L.stop) break;
+    const int b = s % nb, bn = (b + 1) % nb, p = s & 1;
+    const int nchg = ld_dev(a.sync + COOP_SYNC_CNT + p);
+    for (int e = tid; e < nchg; e += COOP_NT) L.ulist[e] = ld_dev(a.chg + COOP_B * p + e);
+    for (int e = tid; e < 3 * nchg; e += COOP_NT) L.lamSet[e] = ld_dev(a.dl + 3 * COOP_B * p + e);
+    __syncthreads();
+    if (nchg > 0)
+      coop_rows<TW>(m, W, L.ulist, nchg, L.lamSet, COOP_B * b, a.g, a.h2, a.g, L.lamS, blockIdx.x - 1, G - 1, 6 * bn,
+                    6 * bn + 6);
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) st_dev(a.sync + COOP_SYNC_PROG + blockIdx.x, s);
+  }
+}
+
+template <class TW>
+__global__ __launch_bounds__(COOP_NT) void k_pgs_coop(CoopArgs a) {
+  extern __shared__ double lds_raw[];
+  PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  // control words written by the active-set kernel (an earlier launch)
+  if (a.ctl[0] == 0) return;   // uniform: the active-set kernel finished the call
+  const int sweep0 = a.ctl[1];
+  const TW *__restrict__ W = static_cast<const TW *>(a.W);
+  const int nc = a.nc, m = 3 * nc;
+  const double h2 = a.h2;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int nb = (nc + COOP_B - 1) / COOP_B;
+  const long blk_elems = (long)COOP_B * COOP_B * PGS_BLK;
+  const long gthreads = (long)gridDim.x * COOP_NT, gt = (long)blockIdx.x * COOP_NT + tid;
+  // ---- set-up, all workgroups: sync words, records, blocked couplings, gaps
+  // at the resume state
+  if (gt < kPgsCoopSync)
+    a.sync[gt] = (gt == COOP_SYNC_STOP || gt == COOP_SYNC_CNT || gt == COOP_SYNC_CNT + 1 || gt == COOP_SYNC_ERR) ? 0 : -1;
+  for (long c = gt; c < nc; c += gthreads) {
+    double wb[3][3];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) wb[p][q] = h2 * (double)W[(3 * c + p) * m + 3 * c + q];
+    double tmp[19];
+    make_record(wb, a.mu[c], tmp);
+    for (int q = 0; q < 19; ++q) a.recAll[PGS_RW * c + q] = tmp[q];
+  }
+  for (long e = gt; e < (long)nb * blk_elems; e += gthreads) {
+    const int b = (int)(e / blk_elems);
+    const long r = e % blk_elems;
+    const int c0 = COOP_B * b, nB = min(COOP_B, nc - c0), nsp = pgs_wave_pad(nB);
+    const int j = (int)(r % PGS_BLK);
+    const long ic = r / PGS_BLK;
+    const int c = (int)(ic % nsp), i = (int)(ic / nsp);
+    double v = 0.0;
+    if (i < nB && j < 9 && c < nB && c != i) v = h2 * (double)W[(3L * (c0 + c) + j / 3) * m + 3L * (c0 + i) + j % 3];
+    if (i < nB) a.Wblk[(long)b * blk_elems + ((long)i * nsp + c) * PGS_BLK + j] = v;
+  }
+  {
+    // contacts with a force, in every workgroup's LDS (order is fixed); the
+    // running count is a wave-uniform register (the ballot is uniform)
+    if (wv == 0) {
+      int cnt = 0;
+      for (int c0 = 0; c0 < nc; c0 += 64) {
+        const int c = c0 + ln;
+        const bool nz = c < nc && (a.lam[3 * c] != 0.0 || a.lam[3 * c + 1] != 0.0 || a.lam[3 * c + 2] != 0.0);
+        const unsigned long long bal = __ballot(nz);
+        if (nz) L.ulist[cnt + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+        cnt += __popcll(bal);
+      }
+      if (ln == 0) L.nu = cnt;
+    }
+    __syncthreads();
+    const int nl = L.nu;
+    // the force values in the order of the list, in LDS (reuses the set's gap area)
+    double *vals = L.lamSet;
+    double *part = L.lamS;
+    for (int q0 = 0; q0 < nl; q0 += PGS_S3 / 3) {
+      const int nq = min(PGS_S3 / 3, nl - q0);
+      for (int e = tid; e < 3 * nq; e += COOP_NT) vals[e] = a.lam[3 * L.ulist[q0 + e / 3] + e % 3];
+      __syncthreads();
+      coop_rows<TW>(m, W, L.ulist + q0, nq, vals, 0, q0 == 0 ? a.d : a.g, h2, a.g, part, blockIdx.x, gridDim.x, 0, 0);
+    }
+    if (nl == 0)
+      for (long r = gt; r < m; r += gthreads) a.g[r] = a.d[r];
+  }
+  __threadfence();
+  grid.sync();
+  if (blockIdx.x == 0)
+    coop_lead<TW>(a, L, sweep0);
+  else
+    coop_push<TW>(a, L);
+}
+
 __global__ void k_world_force(int nc, const double *__restrict__ C, const double *__restrict__ lam,
                               double *__restrict__ f) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1776,10 +2235,22 @@ void launch_pgs(hipStream_t st, int nc, const TW *W, const double *d, const doub
                                                 sweeps_dev, eps_dev, wk.Wss, wk.gnSet, wk.swn, wk.ctl, wk.Sidx,
                                                 wk.nS, wk.rec, wk.gS);
   ICR_LAUNCH_CHECK();
-  // continues only if the active set outgrew the compact path
-  k_pgs_single<TW><<<1, 1024, pgs_single_lds(nc), st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev,
-                                   eps_dev, wk.ctl);
-  ICR_LAUNCH_CHECK();
+  // continues only if the active set outgrew the compact path: block
+  // Gauss-Seidel over the whole GPU, or (under stream capture, or without
+  // its buffers) the single-workgroup sweep
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  ICR_HIP(hipStreamIsCapturing(st, &cap));
+  const int G = coop_grid();
+  if (nc > PGS_WAVE_MAX && wk.Wblk != nullptr && G > 1 && cap == hipStreamCaptureStatusNone) {
+    CoopArgs a{nc, W, d, mu, h * h, lam, status, max_sweeps, tol, j_inner, sweeps_dev, eps_dev, wk.ctl, wk.g,
+               wk.recAll, wk.Wblk, wk.dl, wk.chg, wk.csync};
+    void *args[] = {&a};
+    ICR_HIP(hipLaunchCooperativeKernel((const void *)k_pgs_coop<TW>, dim3(G), dim3(COOP_NT), args, sizeof(PgsLds), st));
+  } else {
+    k_pgs_single<TW><<<1, 1024, pgs_single_lds(nc), st>>>(nc, W, d, nullptr, mu, h * h, lam, status, max_sweeps, tol,
+                                                          j_inner, sweeps_dev, eps_dev, wk.ctl);
+    ICR_LAUNCH_CHECK();
+  }
 }
 template void launch_pgs<double>(hipStream_t, int, const double *, const double *, const double *, double, double *,
                                  int8_t *, int, double, int, int *, double *, const PgsWork &);
@@ -1793,6 +2264,16 @@ void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const
   k_pgs_pc<<<1, 1024, pgs_pc_lds(nc), st>>>(nc, ctx, WH, p, pstart, mu, h * h, f, Cm, lam, status, max_sweeps, tol,
                                            j_inner, sweeps_dev, eps_dev);
   ICR_LAUNCH_CHECK();
+}
+
+namespace {
+int g_coop_grid[64];   // per device: workgroups of the cooperative PGS launch (0 = not available)
+}
+
+int coop_grid() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  return g_coop_grid[dev];
 }
 
 void pgs_prepare() {
@@ -1814,6 +2295,20 @@ void pgs_prepare() {
                               (int)pgs_single_lds(PGS_MAX_NC)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_pc, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pgs_pc_lds(PGS_MAX_NC)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_coop<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PgsLds)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_coop<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PgsLds)));
+  // cooperative launch: at most one workgroup per compute unit (its LDS),
+  // 128 workgroups at most (enough to stream the gap updates)
+  int coop = 0, cus = 0, per_cu = 0;
+  g_coop_grid[dev & 63] = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pgs_coop<double>, COOP_NT,
+                                                   sizeof(PgsLds)) == hipSuccess &&
+      per_cu > 0)
+    g_coop_grid[dev & 63] = std::min(128, per_cu * cus);
   done |= bit;
 }
 

@@ -10,7 +10,10 @@
 // device shares that device's copy, so calls that overlap on one GPU race.
 // Nothing in it has to start at zero: within a call, each kernel writes the
 // part of the array that a later kernel reads (start gaps, first active set,
-// its records and coupling blocks, the control words, sweeps and eps).
+// its records and coupling blocks, the control words, sweeps and eps).  A
+// set that outgrows the register chains continues in the block Gauss-Seidel
+// over the whole GPU, whose buffers are part of the array too (under stream
+// capture, in the single-workgroup sweep).
 #include <mutex>
 
 #include "scene.hpp"
@@ -31,12 +34,17 @@ constexpr size_t kOffSwn = kOffGnSet + align32(kNoAllocMaxContacts);
 constexpr size_t kOffRec = kOffSwn + align32(kNoAllocMaxContacts);
 constexpr size_t kOffGS = kOffRec + align32(pgs_rec_elems(kNoAllocMaxContacts));
 constexpr size_t kOffEps = kOffGS + align32(pgs_rec_elems(kNoAllocMaxContacts));   // eps [1]
-constexpr size_t kOffInts = kOffEps + 32;                                          // ints below
-constexpr size_t kIntSidx = 0, kIntNS = kNoAllocMaxContacts, kIntCtl = kIntNS + 1, kIntSweeps = kIntCtl + 2;
-constexpr size_t kInts = kIntSweeps + 1;
+// block Gauss-Seidel of sets beyond the register chains
+constexpr size_t kOffRecAll = kOffEps + 32;                                         // records of all contacts
+constexpr size_t kOffWblk = kOffRecAll + align32((size_t)kNoAllocMaxContacts * kPgsRecWidth);
+constexpr size_t kOffDl = kOffWblk + align32(pgs_coop_blk_elems(kNoAllocMaxContacts));
+constexpr size_t kOffInts = kOffDl + align32(2 * 3 * kPgsCoopB);                   // ints below
+constexpr size_t kIntSidx = 0, kIntNS = kNoAllocMaxContacts, kIntCtl = kIntNS + 1, kIntSweeps = kIntCtl + 4,
+                 kIntChg = kIntSweeps + 1, kIntSync = kIntChg + 2 * kPgsCoopB;
+constexpr size_t kInts = kIntSync + kPgsCoopSync;
 constexpr size_t kScratchDoubles = kOffInts + align32((kInts + 1) / 2);
 
-// About 21 MB per GPU, held until the process ends.
+// About 32 MB per GPU, held until the process ends.
 __device__ __align__(256) double scratch[kScratchDoubles];
 
 std::mutex g_mtx;
@@ -84,6 +92,11 @@ extern "C" icr_status icr_solve_contacts_noalloc(void *stream, int32_t n_c, cons
     wk.Sidx = ints + kIntSidx;
     wk.nS = ints + kIntNS;
     wk.ctl = ints + kIntCtl;
+    wk.recAll = base + kOffRecAll;
+    wk.Wblk = base + kOffWblk;
+    wk.dl = base + kOffDl;
+    wk.chg = ints + kIntChg;
+    wk.csync = ints + kIntSync;
     int *sweeps_dev = ints + kIntSweeps;
     double *eps_dev = base + kOffEps;
     pgs_prepare();

@@ -116,7 +116,13 @@ struct PgsWork {
   double *gnSet = nullptr, *swn = nullptr;   // per contact: normal gap at the set's start state, sqrt(W~_nn)
   int *Sidx = nullptr, *nS = nullptr;         // first active set (ascending contact ids) and its size
   double *rec = nullptr, *gS = nullptr;       // its records and gaps (sets of at most 128 contacts)
-  int *ctl = nullptr;
+  int *ctl = nullptr;                         // 4 control words
+  // block Gauss-Seidel of sets beyond the chains (only when n_c > 512; NULL:
+  // the single-workgroup sweep continues instead)
+  // (records of all contacts, blocked diagonal couplings, the change lists of
+  // two blocks, sync words)
+  double *recAll = nullptr, *Wblk = nullptr, *dl = nullptr;
+  int *chg = nullptr, *csync = nullptr;
 };
 
 struct Contacts {
@@ -286,7 +292,15 @@ constexpr inline size_t pgs_wss_elems(int nc) {
 }
 // doubles of the prepared records (and gaps) of a first active set
 constexpr inline size_t pgs_rec_elems(int nc) { return (size_t)(nc < kPgsWaveMax ? nc : kPgsWaveMax) * kPgsRecWidth; }
+// Block Gauss-Seidel over the whole GPU (sets beyond kPgsWaveMax contacts):
+// blocks of kPgsCoopB contacts, each block's couplings padded like a wave set.
+constexpr int kPgsCoopB = 128;
+constexpr int kPgsCoopSync = 256;   // ints of sync words
+constexpr inline size_t pgs_coop_blk_elems(int nc) {
+  return (size_t)((nc + kPgsCoopB - 1) / kPgsCoopB) * kPgsCoopB * kPgsCoopB * kPgsBlk;
+}
 void pgs_prepare();   // kernel attributes (dynamic LDS), once per device; call outside graph capture
+int coop_grid();      // workgroups of the cooperative large-set PGS on this device (0: not available)
 void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
                                const double *pstart, const double *mu, double h, double *f, double *Cm,
                                double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,

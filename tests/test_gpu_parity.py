@@ -1043,3 +1043,26 @@ def test_two_body_config_at_full_size():
     assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
     assert _rel(res["p"].cpu().numpy() - p_free, rec[-1]["p"] - p_free) <= 1e-10
     s.close()
+
+
+def test_two_body_full_size_mixed_precision():
+    """The two-body configuration at full size in ICR_FP32_IR: every one of
+    its 3000 contacts is active, so its PGS runs the block Gauss-Seidel over
+    the whole GPU on FP32 couplings.  Against the FP64 path of the same GPU
+    (checked against the oracle above): refined errors within 1e-6 on W_H and
+    1e-5 on p and on q - q_rest (both fixed by H^T f, unique even where the
+    pair forces are not); raw FP32 errors reported."""
+    icr = _icr()
+    sc = make_scene("stacked", 0)
+    _say("[gpu] stacked FP64 reference step")
+    ref = _mixed_run(sc, icr.FP64, 0)
+    q0 = sc["nodes"].ravel()
+    for refine in (0, 1):
+        _say(f"[gpu] stacked mixed refine={refine}")
+        got = _mixed_run(sc, icr.FP32_IR, refine)
+        errs = {k: _rel(got[k], ref[k]) for k in ("WH", "lam", "p")}
+        errs["q"] = _rel(got["q"] - q0, ref["q"] - q0)
+        _say(f"[gpu] stacked refine={refine}: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items())
+             + f" sweeps {got['sweeps']}")
+        if refine >= 1:
+            assert errs["WH"] <= 1e-6 and errs["p"] <= 1e-5 and errs["q"] <= 1e-5
