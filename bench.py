@@ -104,10 +104,11 @@ def profiled_issue(kernel):
     return None
 
 
-def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
+def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0, group=8, max_wait_ms=0.0):
     """Serving mix through icr_server: closed-loop saturation with 1, 4 and
-    `slots` slots, then Poisson arrivals at `rate` steps/s over `seconds` on
-    `slots` slots."""
+    `slots` slots (Newton loops of the requests started together batched into
+    one launch), the same at `slots` slots without batching, then Poisson
+    arrivals at `rate` steps/s over `seconds` on `slots` slots, batched."""
     import torch
     from paper_2306_06946_amd import icr
     from paper_2306_06946_amd.scenes import make_scene
@@ -123,10 +124,11 @@ def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
     out = {"scenes": n_scenes, "nodes": [len(sc["nodes"]) for sc in scs], "contacts": [sc["n_contacts"] for sc in scs],
            "pgs_sweeps": sweeps, "hbm_budget_bytes": 200 << 30}
 
-    def closed_loop(slots, window):
+    def closed_loop(slots, window, batching=True):
         # every scene keeps one request outstanding; count completions in a
         # fixed time window (fast scenes complete more steps than slow ones)
-        srv = icr.Server(hbm_budget=200 << 30, slots=slots)
+        srv = icr.Server(hbm_budget=200 << 30, slots=slots, batching=group if batching else 0,
+                         max_wait_ms=max_wait_ms)
         ids = [srv.admit(s) for s in scenes]
         lat = []
         ts = time.perf_counter()
@@ -155,17 +157,20 @@ def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
         for s in scenes:
             s.set_stream(torch.cuda.current_stream().cuda_stream)
         lat = np.array(lat)
-        return dict(slots=slots, window_s=window, steps=int(n_in_window), steps_per_s=n_in_window / el,
-                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                    admitted_bytes=int(used))
+        return dict(slots=slots, batching=batching, window_s=window, steps=int(n_in_window),
+                    steps_per_s=n_in_window / el, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), admitted_bytes=int(used))
 
     out["hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES")
+    out["group"] = group
+    out["max_wait_ms"] = max_wait_ms
     for k in sorted({1, 4, slots}):
         out[f"closed_loop_{k}_slot" + ("s" if k > 1 else "")] = closed_loop(k, seconds)
+    out[f"closed_loop_{slots}_slots_unbatched"] = closed_loop(slots, seconds, batching=False)
     cap = out[f"closed_loop_{slots}_slot" + ("s" if slots > 1 else "")]["steps_per_s"]
     log("[bench] serving closed loop: " + ", ".join(
-        f"{v['slots']} slots {v['steps_per_s']:.0f} steps/s" for k, v in out.items() if k.startswith("closed_loop"))
-        + f" (hardware queues {out['hw_queues']})")
+        f"{v['slots']} slots{'' if v['batching'] else ' unbatched'} {v['steps_per_s']:.0f} steps/s"
+        for k, v in out.items() if k.startswith("closed_loop")) + f" (hardware queues {out['hw_queues']})")
     if rate <= 0:
         rate = 0.7 * cap   # an offered load the slots can carry
     # open loop: Poisson arrivals, random scene per arrival
@@ -173,7 +178,7 @@ def serving_leg(n_scenes, rate, sweeps, slots, seconds=2.0):
     n_req = int(rate * seconds)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     which = rng.integers(0, n_scenes, size=n_req)
-    srv = icr.Server(hbm_budget=200 << 30, slots=slots)
+    srv = icr.Server(hbm_budget=200 << 30, slots=slots, batching=group, max_wait_ms=max_wait_ms)
     ids = [srv.admit(s) for s in scenes]
     lat = []
     k = 0
@@ -274,6 +279,11 @@ def main():
                     help="Poisson arrival rate (steps/s, all scenes); 0 = 70%% of the measured capacity")
     ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="length of each closed-loop window and of the Poisson run")
+    ap.add_argument("--serving-group", type=int, default=8,
+                    help="requests per slot and round of the serving mix, their Newton loops in one launch "
+                         "(0: one whole step per slot)")
+    ap.add_argument("--serving-max-wait", type=float, default=0.0,
+                    help="ms a short serving group waits for more requests while a slot runs")
     ap.add_argument("--serving-slots", type=int, default=16,
                     help="server slots (streams) of the serving mix; HIP gets as many hardware queues (1..32)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
@@ -508,7 +518,8 @@ def main():
         }
     if args.serving > 0:
         out["serving"] = serving_leg(args.serving, args.serving_rate, args.sweeps, args.serving_slots,
-                                     seconds=args.serving_seconds)
+                                     seconds=args.serving_seconds, group=args.serving_group,
+                                     max_wait_ms=args.serving_max_wait)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (the oracle's first step)...")
         out["cpu_baseline"] = cpu_baseline(sc, args.sweeps)

@@ -340,13 +340,20 @@ icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int3
  * Serving: many independent scenes stepped concurrently on one GPU.
  *
  * A server holds admitted scenes (each keeps its factor, W_H buffers and
- * warm start resident) and a FIFO of step requests.  icr_server_poll launches
- * queued requests on free slots -- one HIP stream per slot, one request in
- * flight per slot and per scene -- as soon as a slot frees up (continuous
- * admission), and returns the requests that completed.  Requests of one
- * scene run in submission order; those of different scenes overlap on the
- * device.  A request runs exactly icr_step(scene, obstacle, opts, NULL) on
- * the slot's stream, so its results equal the same step run alone.
+ * warm start resident) and a FIFO of step requests.  icr_server_poll starts
+ * queued requests on free slots (one HIP stream per slot) as soon as a slot
+ * frees up (continuous admission), and returns the requests that completed.
+ * The startable requests (the oldest queued ones whose scenes have nothing
+ * in flight) are spread evenly over the free slots, at most `group` per slot
+ * (icr_server_set_batching); a slot runs its group in its stream's order: the requests whose Newton loops allow it
+ * (fast scheme, ICR_FP64, no pair contacts, at most 512 contacts, untimed)
+ * run their steps up to the Newton loop, then all their Newton loops
+ * (Algorithm 3, steps 1-4) in one persistent launch with one workgroup per
+ * scene, then the rest of their steps; other requests run icr_step(scene,
+ * obstacle, opts, NULL) whole.  The slot is free again when its whole group
+ * completed.  Requests of one scene run in submission order; those of
+ * different scenes overlap on the device.  Either way a request's results
+ * are bit for bit those of the same step run alone.
  * Scenes are admitted against a device-memory budget: admission first
  * allocates every buffer the scene's steps use (icr_reserve for the contacts
  * reserved before, else for its candidate count) and charges the scene's
@@ -376,6 +383,18 @@ typedef struct {
 icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots);
 void icr_server_destroy(icr_server *srv); /* waits for the requests in flight */
 const char *icr_server_last_error(const icr_server *srv);
+/* group in [1, 64] (8 by default): requests a slot takes per round, their
+ * Newton loops batched into one launch where the step allows it; group = 0:
+ * one request per slot, run as icr_step whole (the Newton loop then runs as
+ * the scene's own kernels, in a captured graph when opts.graph is set).  The
+ * batched loop computes every value as the per-scene kernels do, in the same
+ * order, so both forms give identical results.  With group > 1 and
+ * max_wait_ms > 0 (0 by default: start at once), fewer startable requests
+ * than `group` wait until the oldest of them has waited max_wait_ms, or until
+ * no slot runs.  Applies to
+ * the rounds that start after the call.  ICR_E_ARG for group outside
+ * [0, 64] or a negative or non-finite max_wait_ms. */
+icr_status icr_server_set_batching(icr_server *srv, int32_t group, double max_wait_ms);
 
 /* Admit a factored scene with candidates set; *scene_id receives its id.
  * Synchronises the device once (the scene's set-up work must be complete

@@ -759,18 +759,20 @@ void check_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt)
 // 6 + 4k + j for Newton iteration k); stamps work the same in a replayed
 // graph.  Every argument that changes from step to step lives in device
 // memory, so the sequence can be captured once and replayed.
-void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
+constexpr int kStampStep = 0, kStampNewton = 6;   // phase stamps of a timed step
+
+// The step up to its Newton loop: free motion, contacts, W_H (Algorithm 3
+// before step 1).
+void enqueue_pre(icr_scene *s, const icr_step_opts *opt) {
   hipStream_t st = s->stream;
   auto &C = s->con;
   auto &S = s->st;
-  const double h = s->mesh.h;
-  const int nc = opt->n_contacts, nk = opt->n_newton;
+  const int nc = opt->n_contacts;
   const bool standard = opt->scheme == 1;
-  const bool per_constraint = opt->scheme == 2;
   auto mark = [&](int base, int i) {
     if (opt->timing) launch_stamp(s, base + i);
   };
-  const int ev = 0, kev = 6;
+  const int ev = kStampStep;
   mark(ev, 0);
   // free motion (Eq. 5, 12)
   launch_free_rhs(s, S.d_q, S.d_v, S.d_b);
@@ -798,6 +800,22 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
     build_WH_device(s, nc, C.d_nodes_c, C.d_WH, false);
   }
   mark(ev, 3);
+}
+
+// Algorithm 3's Newton loop (steps 1-4), or its variants.
+void enqueue_newton(icr_scene *s, const icr_step_opts *opt) {
+  hipStream_t st = s->stream;
+  auto &C = s->con;
+  auto &S = s->st;
+  const double h = s->mesh.h;
+  const int nc = opt->n_contacts, nk = opt->n_newton;
+  const bool standard = opt->scheme == 1;
+  const bool per_constraint = opt->scheme == 2;
+  const bool mixed = opt->precision == ICR_FP32_IR;
+  auto mark = [&](int base, int i) {
+    if (opt->timing) launch_stamp(s, base + i);
+  };
+  const int kev = kStampNewton;
   // directions updated before every local solve: proximity of the warm start
   if (per_constraint) launch_proximity<double>(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);
   for (int k = 0; k < nk; ++k) {
@@ -838,6 +856,21 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
     }
     mark(kev, 4 * k + 3);
   }
+}
+
+// The step after its Newton loop: corrective motion, integration (Eq. 20),
+// the warm start of the next step.
+void enqueue_post(icr_scene *s, const icr_step_opts *opt) {
+  auto &C = s->con;
+  auto &S = s->st;
+  const int nc = opt->n_contacts;
+  const bool standard = opt->scheme == 1;
+  auto &Pr = s->pairs;
+  const int P = Pr.count;
+  auto mark = [&](int base, int i) {
+    if (opt->timing) launch_stamp(s, base + i);
+  };
+  const int ev = kStampStep;
   mark(ev, 4);
   // corrective motion and integration (Eq. 20)
   if (P > 0) {
@@ -852,6 +885,37 @@ void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
   mark(ev, 5);
 }
 
+void enqueue_step(icr_scene *s, const icr_step_opts *opt) {
+  enqueue_pre(s, opt);
+  enqueue_newton(s, opt);
+  enqueue_post(s, opt);
+}
+
+// icr_step's checks, buffers and per-step device parameters.
+void step_prepare(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt) {
+  check_step(s, obs, opt);
+  const int nc = opt->n_contacts;
+  ensure_contact_buffers(s, nc);
+  ensure_pair_step(s, nc);
+  ensure_rhs_capacity(s, std::max(nc, s->pairs.count > 0 ? s->pairs.nu + nc - s->pairs.count : 0));
+  if (opt->precision == ICR_FP32_IR) ensure_mixed(s);
+  auto &S = s->st;
+  if (!S.obs_valid || std::memcmp(&S.obs_host, obs, sizeof(icr_obstacle)) != 0) {
+    launch_set_ctx(s, obs, nullptr);
+    S.obs_host = *obs;
+    S.obs_valid = true;
+  }
+}
+
+// The host's record of an enqueued step.
+void step_account(icr_scene *s, const icr_step_opts *opt) {
+  auto &S = s->st;
+  S.t = S.t + s->mesh.h;
+  s->stepped = true;
+  s->last_nc = opt->n_contacts;
+  s->last_mixed = opt->precision == ICR_FP32_IR;
+}
+
 bool same_opts(const icr_step_opts &a, const icr_step_opts &b) {
   return a.n_contacts == b.n_contacts && a.n_newton == b.n_newton && a.max_sweeps == b.max_sweeps &&
          a.j_inner == b.j_inner && a.tol == b.tol && a.timing == b.timing && a.scheme == b.scheme &&
@@ -862,21 +926,12 @@ bool same_opts(const icr_step_opts &a, const icr_step_opts &b) {
 
 icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, icr_step_report *rep) {
   return guarded(s, [&] {
-    check_step(s, obs, opt);
+    step_prepare(s, obs, opt);
     const int nc = opt->n_contacts;
-    ensure_contact_buffers(s, nc);
-    ensure_pair_step(s, nc);
-    ensure_rhs_capacity(s, std::max(nc, s->pairs.count > 0 ? s->pairs.nu + nc - s->pairs.count : 0));
-    if (opt->precision == ICR_FP32_IR) ensure_mixed(s);
     hipStream_t st = s->stream;
     auto &C = s->con;
     auto &S = s->st;
     const int nk = opt->n_newton;
-    if (!S.obs_valid || std::memcmp(&S.obs_host, obs, sizeof(icr_obstacle)) != 0) {
-      launch_set_ctx(s, obs, nullptr);
-      S.obs_host = *obs;
-      S.obs_valid = true;
-    }
     if (opt->graph) {
       auto &G = s->sg;
       if (!G.valid || G.epoch != s->epoch || !same_opts(G.key, *opt)) {
@@ -905,10 +960,7 @@ icr_status icr_step(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *
     } else {
       enqueue_step(s, opt);
     }
-    S.t = S.t + s->mesh.h;
-    s->stepped = true;
-    s->last_nc = nc;
-    s->last_mixed = opt->precision == ICR_FP32_IR;
+    step_account(s, opt);
     if (rep) {
       std::memset(rep, 0, sizeof(*rep));
       rep->t = S.t;
@@ -1042,6 +1094,76 @@ icr_status icr_analyze(const double *nodes, int32_t N, const int32_t *tets, int3
 }  // extern "C"
 
 namespace icr {
+
+size_t newton_task_bytes() { return sizeof(NewtonTask); }
+
+bool newton_batchable(const icr_scene *s, const icr_step_opts *opt) {
+  return s && opt && opt->scheme == 0 && opt->precision == ICR_FP64 && !opt->timing && s->pairs.count == 0 &&
+         opt->n_contacts >= 1 && opt->n_contacts <= kPgsWaveMax;
+}
+
+icr_status step_begin(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, void *task) {
+  return guarded(s, [&] {
+    if (!task) throw ArgError("step_begin: task is NULL");
+    step_prepare(s, obs, opt);
+    if (!newton_batchable(s, opt)) throw ArgError("step_begin: this step's Newton loop cannot run batched");
+    enqueue_pre(s, opt);
+    auto &C = s->con;
+    NewtonTask t{};
+    t.nc = opt->n_contacts;
+    t.n_newton = opt->n_newton;
+    t.max_sweeps = opt->max_sweeps;
+    t.j_inner = opt->j_inner;
+    t.tol = opt->tol;
+    t.h = s->mesh.h;
+    t.ctx = s->st.d_ctx;
+    t.WH = C.d_WH;
+    t.pfree = C.d_pfree;
+    t.pstart = C.d_pstart;
+    t.mu = C.d_mu;
+    t.W = C.d_W;
+    t.p = C.d_p;
+    t.f = C.d_f;
+    t.C = C.d_C;
+    t.dk = C.d_dk;
+    t.lam = C.d_lam;
+    t.eps = C.d_eps;
+    t.g = C.pgs.g;
+    t.Wss = C.pgs.Wss;
+    t.gnSet = C.pgs.gnSet;
+    t.swn = C.pgs.swn;
+    t.status = C.d_status;
+    t.sweeps = C.d_sweeps;
+    t.ctl = C.pgs.ctl;
+    std::memcpy(task, &t, sizeof t);
+    return ICR_OK;
+  });
+}
+
+icr_status step_end(icr_scene *s, const icr_step_opts *opt) {
+  return guarded(s, [&] {
+    enqueue_post(s, opt);
+    step_account(s, opt);
+    return ICR_OK;
+  });
+}
+
+icr_status newton_batch(void *stream, const void *tasks, const int *idx, int n, std::string &msg) {
+  try {
+    if (!tasks || !idx || n < 1 || n > kNewtonBatchMax) throw ArgError("newton_batch: 1..64 tasks");
+    NewtonBatchIdx b{};
+    b.n = n;
+    for (int i = 0; i < n; ++i) b.idx[i] = idx[i];
+    launch_newton_batch((hipStream_t)stream, static_cast<const NewtonTask *>(tasks), b);
+    return ICR_OK;
+  } catch (const ArgError &e) {
+    msg = e.what();
+    return ICR_E_ARG;
+  } catch (const std::exception &e) {
+    msg = e.what();
+    return ICR_E_HIP;
+  }
+}
 
 icr_status check_step_request(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, std::string &msg) {
   const icr_status st = guarded(s, [&] {

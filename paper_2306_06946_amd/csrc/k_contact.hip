@@ -267,9 +267,8 @@ __global__ void k_directions(int nc, const StepCtx *__restrict__ ctx, const doub
 // transpose of block (b, a) from the same inputs (W_H is exactly symmetric),
 // so W is exactly symmetric.
 template <class TW>
-__global__ void k_update_W(int nc, const TW *__restrict__ WH, const double *__restrict__ C, TW *__restrict__ W) {
-  long blk = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= (long)nc * nc) return;
+__device__ __forceinline__ void update_W_block(int nc, const TW *__restrict__ WH, const double *__restrict__ C,
+                                               TW *__restrict__ W, long blk) {
   const int a = (int)(blk / nc), b = (int)(blk % nc);
   const long m = 3L * nc;
   const bool lower = a >= b;
@@ -300,6 +299,12 @@ __global__ void k_update_W(int nc, const TW *__restrict__ WH, const double *__re
         v = lower ? R[i][j] : R[j][i];
       W[(3L * a + i) * m + 3L * b + j] = (TW)v;
     }
+}
+
+template <class TW>
+__global__ void k_update_W(int nc, const TW *__restrict__ WH, const double *__restrict__ C, TW *__restrict__ W) {
+  const long blk = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk < (long)nc * nc) update_W_block(nc, WH, C, W, blk);
 }
 
 // ---- local solver (Signorini + Coulomb cone) --------------------------------
@@ -1329,27 +1334,27 @@ __global__ __launch_bounds__(256) void k_pgs_gather(int nc, const TW *__restrict
   }
 }
 
+// The sequential kernel's body, for one workgroup of PGS_NT threads with the
+// state L in its LDS (k_pgs_active, and each scene's workgroup of the batched
+// Newton loop).  npre: size of the set prepared by k_pgs_gather (preSidx,
+// preRec, preGS); a value above PGS_WAVE_MAX builds the first set here, from
+// g0, gnSet and swn.
 template <class TW>
-__global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const TW *__restrict__ W,
-                                                       const double *__restrict__ d, const double *__restrict__ g0,
-                                                       const double *__restrict__ mu, double h2,
-                                                       double *__restrict__ lam, int8_t *__restrict__ status,
-                                                       int max_sweeps, double tol, int j_inner,
-                                                       int *__restrict__ sweeps_out, double *__restrict__ eps_out,
-                                                       double *__restrict__ Wss, double *__restrict__ gnSet,
-                                                       const double *__restrict__ swn, int *__restrict__ ctl,
-                                                       const int *__restrict__ preSidx, const int *__restrict__ preN,
-                                                       const double *__restrict__ preRec,
-                                                       const double *__restrict__ preGS) {
-  extern __shared__ double lds_raw[];
-  PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
+__device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__restrict__ W,
+                                                const double *__restrict__ d, const double *__restrict__ g0,
+                                                const double *__restrict__ mu, double h2, double *__restrict__ lam,
+                                                int8_t *__restrict__ status, int max_sweeps, double tol,
+                                                int j_inner, int *__restrict__ sweeps_out,
+                                                double *__restrict__ eps_out, double *__restrict__ Wss,
+                                                double *__restrict__ gnSet, const double *__restrict__ swn,
+                                                int *__restrict__ ctl, const int *__restrict__ preSidx, int npre,
+                                                const double *__restrict__ preRec, const double *__restrict__ preGS) {
   const int m = 3 * nc;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   for (int c = tid; c < nc; c += PGS_NT) {
     bool nzc = lam[3 * c] != 0.0 || lam[3 * c + 1] != 0.0 || lam[3 * c + 2] != 0.0;
     L.inS[c] = (nzc || g0[3 * c] < 0.0) ? 1 : 0;
   }
-  const int npre = *preN;   // set prepared by k_pgs_gather
   if (tid == 0) {
     L.stop = 0;
     L.zflag = 0;
@@ -1611,6 +1616,167 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const TW *__restr
   if (tid == 0) {
     *sweeps_out = sweep;
     *eps_out = eps;
+  }
+}
+
+template <class TW>
+__global__ __launch_bounds__(PGS_NT) void k_pgs_active(int nc, const TW *__restrict__ W,
+                                                       const double *__restrict__ d, const double *__restrict__ g0,
+                                                       const double *__restrict__ mu, double h2,
+                                                       double *__restrict__ lam, int8_t *__restrict__ status,
+                                                       int max_sweeps, double tol, int j_inner,
+                                                       int *__restrict__ sweeps_out, double *__restrict__ eps_out,
+                                                       double *__restrict__ Wss, double *__restrict__ gnSet,
+                                                       const double *__restrict__ swn, int *__restrict__ ctl,
+                                                       const int *__restrict__ preSidx, const int *__restrict__ preN,
+                                                       const double *__restrict__ preRec,
+                                                       const double *__restrict__ preGS) {
+  extern __shared__ double lds_raw[];
+  PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
+  pgs_active_body<TW>(L, nc, W, d, g0, mu, h2, lam, status, max_sweeps, tol, j_inner, sweeps_out, eps_out, Wss,
+                      gnSet, swn, ctl, preSidx, *preN, preRec, preGS);
+}
+
+// ---- batched Newton loops: one workgroup per scene --------------------------
+//
+// y[i] = x0[i] + h2 sum over the contacts c with a non-zero block of v
+// (ascending) of M[(3c + a) m + i] v[3c + a], by one workgroup (M symmetric,
+// rows of M read for its columns).  The order of every sum is that of
+// k_sym_gemv_sparse (one 64-row block at a time, wave w takes list entries
+// w, w + 8, ..., the eight partial sums added in wave order), so the result
+// is bit-for-bit the per-scene kernel's.  The contacts taken are those with
+// a non-zero block of nzv (the forces lambda, also when v is f = C^T lambda,
+// as there); list (LDS) receives them, part (LDS) holds 8 x 64 partial sums.
+template <class TM>
+__device__ void wg_sym_gemv_sparse(int nc, const TM *__restrict__ M, const double *__restrict__ x0,
+                                   const double *__restrict__ v, const double *__restrict__ nzv, double h2,
+                                   double *__restrict__ y, int *list, int *count, double *part) {
+  static_assert(PGS_NT == SG_NT, "the per-scene kernel's wave count");
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const long m = 3L * nc;
+  if (wv == 0) {
+    int cnt = 0;
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+      const int c = c0 + ln;
+      const bool nz = c < nc && block_nonzero(nzv, c);
+      const unsigned long long bal = __ballot(nz);
+      if (nz) list[cnt + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+      cnt += __popcll(bal);
+    }
+    if (ln == 0) *count = cnt;
+  }
+  __syncthreads();
+  const int n = *count;
+  for (long i0 = 0; i0 < m; i0 += 64) {
+    const long i = i0 + ln;
+    double s = 0.0;
+    if (i < m) {
+#pragma unroll 4
+      for (int q = wv; q < n; q += SG_NW) {
+        const long r = 3L * list[q];
+        s = fma((double)M[r * m + i], v[r], s);
+        s = fma((double)M[(r + 1) * m + i], v[r + 1], s);
+        s = fma((double)M[(r + 2) * m + i], v[r + 2], s);
+      }
+    }
+    part[wv * 64 + ln] = s;
+    __syncthreads();
+    if (wv == 0 && i < m) {
+      double t = 0.0;
+      for (int w = 0; w < SG_NW; ++w) t += part[w * 64 + ln];
+      y[i] = x0[i] + h2 * t;
+    }
+    __syncthreads();
+  }
+}
+
+// Algorithm 3's Newton loop (steps 1-4) of one scene per workgroup: frames
+// and gaps at the last proximity (the warm start in the new frames), W_k =
+// C_k W_H C_k^T, the PGS start gaps g0 = d + W~ lambda, the active-set PGS
+// (the sequential kernel's body; the first set is built in place), and the
+// world forces f = C^T lambda with the proximity p = p_free + h^2 W_H f
+// (Eq. 31).  Every value is computed as the per-scene kernels compute it, in
+// the same order, so a step's results do not depend on the path it took.
+// The task table as the device reads it: the same layout with every pointer
+// in the global address space, so that the code inlined below uses global
+// loads and their counters (a pointer read from memory is otherwise generic).
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+struct NewtonTaskG {
+  int nc, n_newton, max_sweeps, j_inner;
+  double tol, h;
+  gptr<const StepCtx> ctx;
+  gptr<const double> WH, pfree, pstart, mu;
+  gptr<double> W, p, f, C, dk, lam, eps;
+  gptr<double> g, Wss, gnSet, swn;
+  gptr<int8_t> status;
+  gptr<int> sweeps, ctl;
+};
+static_assert(sizeof(NewtonTaskG) == sizeof(NewtonTask) && offsetof(NewtonTaskG, ctl) == offsetof(NewtonTask, ctl),
+              "device view of the task table");
+
+__global__ __launch_bounds__(PGS_NT) void k_newton_batch(const NewtonTask *__restrict__ tasks, NewtonBatchIdx ids) {
+  extern __shared__ double lds_raw[];
+  PgsLds &L = *reinterpret_cast<PgsLds *>(lds_raw);
+  const NewtonTaskG &tg = reinterpret_cast<const NewtonTaskG *>(tasks)[ids.idx[blockIdx.x]];
+  struct {
+    int nc, n_newton, max_sweeps, j_inner;
+    double tol, h;
+    const StepCtx *ctx;
+    const double *WH, *pfree, *pstart, *mu;
+    double *W, *p, *f, *C, *dk, *lam, *eps;
+    int8_t *status;
+    int *sweeps;
+  } t{tg.nc, tg.n_newton, tg.max_sweeps, tg.j_inner, tg.tol, tg.h, (const StepCtx *)tg.ctx,
+      (const double *)tg.WH, (const double *)tg.pfree, (const double *)tg.pstart, (const double *)tg.mu,
+      (double *)tg.W, (double *)tg.p, (double *)tg.f, (double *)tg.C, (double *)tg.dk, (double *)tg.lam,
+      (double *)tg.eps, (int8_t *)tg.status, (int *)tg.sweeps};
+  struct {
+    double *g, *Wss, *gnSet, *swn;
+    int *ctl;
+  } w{(double *)tg.g, (double *)tg.Wss, (double *)tg.gnSet, (double *)tg.swn, (int *)tg.ctl};
+  const int nc = t.nc, tid = threadIdx.x;
+  const long m = 3L * nc;
+  const double h2 = t.h * t.h;
+  for (int k = 0; k < t.n_newton; ++k) {
+    // step 1: frames and gaps at p_{k-1} (p_free for the first iteration)
+    {
+      const icr_obstacle obs = t.ctx->obs;
+      const double t0 = t.ctx->t0, t1 = t.ctx->t0 + t.ctx->h;
+      const double *p = (k == 0) ? t.pfree : t.p;
+      for (int c = tid; c < nc; c += PGS_NT) {
+        double pc[3] = {p[3 * c], p[3 * c + 1], p[3 * c + 2]};
+        double ps[3] = {t.pstart[3 * c], t.pstart[3 * c + 1], t.pstart[3 * c + 2]};
+        double F[3][3], delta[3];
+        contact_frame(obs, t0, t1, pc, ps, F, delta);
+        double dp[3] = {pc[0] - t.pfree[3 * c], pc[1] - t.pfree[3 * c + 1], pc[2] - t.pfree[3 * c + 2]};
+        for (int r = 0; r < 3; ++r) {
+          for (int a = 0; a < 3; ++a) t.C[9 * c + 3 * r + a] = F[r][a];
+          t.dk[3 * c + r] = delta[r] - (F[r][0] * dp[0] + F[r][1] * dp[1] + F[r][2] * dp[2]);
+          t.lam[3 * c + r] = F[r][0] * t.f[3 * c] + F[r][1] * t.f[3 * c + 1] + F[r][2] * t.f[3 * c + 2];
+        }
+      }
+    }
+    __syncthreads();
+    // step 2: W_k = C_k W_H C_k^T
+    for (long blk = tid; blk < (long)nc * nc; blk += PGS_NT) update_W_block(nc, t.WH, t.C, t.W, blk);
+    __syncthreads();
+    // PGS start gaps and the per-contact set data
+    wg_sym_gemv_sparse<double>(nc, t.W, t.dk, t.lam, t.lam, h2, w.g, L.ulist, &L.nu, L.lamS);
+    for (int c = tid; c < nc; c += PGS_NT) {
+      w.gnSet[c] = w.g[3 * c];
+      w.swn[c] = sqrt(h2 * t.W[(3L * c) * m + 3L * c]);
+    }
+    __syncthreads();
+    // step 3: PGS
+    pgs_active_body<double>(L, nc, t.W, t.dk, w.g, t.mu, h2, t.lam, t.status, t.max_sweeps, t.tol, t.j_inner,
+                            t.sweeps + k, t.eps + k, w.Wss, w.gnSet, w.swn, w.ctl, nullptr, PGS_WAVE_MAX + 1,
+                            nullptr, nullptr);
+    __syncthreads();
+    // step 4: world forces and the proximity update (Eq. 31)
+    for (long e = tid; e < m; e += PGS_NT) t.f[e] = world_force(t.C, t.lam, e / 3, (int)(e % 3));
+    __syncthreads();
+    wg_sym_gemv_sparse<double>(nc, t.WH, t.pfree, t.f, t.lam, h2, t.p, L.ulist, &L.nu, L.lamS);
   }
 }
 
@@ -2297,6 +2463,8 @@ void pgs_prepare() {
                               (int)pgs_pc_lds(PGS_MAX_NC)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_coop<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_newton_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PgsLds)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_coop<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
   // cooperative launch: at most one workgroup per compute unit (its LDS),
@@ -2310,6 +2478,13 @@ void pgs_prepare() {
       per_cu > 0)
     g_coop_grid[dev & 63] = std::min(128, per_cu * cus);
   done |= bit;
+}
+
+void launch_newton_batch(hipStream_t st, const NewtonTask *tasks, const NewtonBatchIdx &ids) {
+  if (ids.n < 1 || ids.n > kNewtonBatchMax) throw std::runtime_error("batched Newton loop: 1..64 scenes");
+  pgs_prepare();
+  k_newton_batch<<<ids.n, PGS_NT, sizeof(PgsLds), st>>>(tasks, ids);
+  ICR_LAUNCH_CHECK();
 }
 
 void launch_world_force(hipStream_t st, int nc, const double *Cm, const double *lam, double *f) {

@@ -165,12 +165,32 @@ struct Pairs {
   Arena step_arena;
 };
 
+
 // Per-step parameters kept in device memory, so a captured step graph can be
 // replayed: the obstacle and the time at the start of the step.
 struct StepCtx {
   icr_obstacle obs;
   double t0;
   double h;
+};
+
+// One scene's Newton loop in the batched launch (k_newton_batch): sizes, its
+// step options and device pointers into the scene (fast scheme, FP64, no
+// pair contacts, n_c <= kPgsWaveMax).
+struct NewtonTask {
+  int nc, n_newton, max_sweeps, j_inner;
+  double tol, h;
+  const StepCtx *ctx;
+  const double *WH, *pfree, *pstart, *mu;
+  double *W, *p, *f, *C, *dk, *lam, *eps;
+  double *g, *Wss, *gnSet, *swn;   // PGS work (PgsWork of the scene)
+  int8_t *status;
+  int *sweeps, *ctl;
+};
+constexpr int kNewtonBatchMax = 64;   // scenes per batched launch
+struct NewtonBatchIdx {               // the table entries of one launch
+  int n;
+  int idx[kNewtonBatchMax];
 };
 
 struct State {
@@ -300,6 +320,9 @@ constexpr inline size_t pgs_coop_blk_elems(int nc) {
   return (size_t)((nc + kPgsCoopB - 1) / kPgsCoopB) * kPgsCoopB * kPgsCoopB * kPgsBlk;
 }
 void pgs_prepare();   // kernel attributes (dynamic LDS), once per device; call outside graph capture
+// The Newton loops of the scenes tasks[ids.idx[0..n)] (device table), one
+// workgroup each, in one launch on stream st.
+void launch_newton_batch(hipStream_t st, const NewtonTask *tasks, const NewtonBatchIdx &ids);
 int coop_grid();      // workgroups of the cooperative large-set PGS on this device (0: not available)
 void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
                                const double *pstart, const double *mu, double h, double *f, double *Cm,

@@ -1,11 +1,19 @@
 // Serving runtime: admitted scenes, a FIFO of step requests and a fixed set
-// of slots (one HIP stream each).  A request is icr_step(scene, obstacle,
-// opts, NULL) enqueued on the slot's stream, followed by a copy of its PGS
-// eps values into the slot's pinned host buffer (the step's convergence
-// status) and an event that marks its completion.
+// of slots (one HIP stream each).  The startable requests (the oldest of
+// idle scenes) are spread over the free slots, up to the group size per
+// slot, and each slot runs its group in its stream's order: with batching on, every request whose Newton loop
+// can run batched (fast scheme, FP64, no pair contacts, at most 512
+// contacts) enqueues its step up to the Newton loop, one launch runs all
+// their Newton loops (one workgroup per scene, k_newton_batch), then each
+// finishes its step; other requests run icr_step whole.  Each request ends
+// with a copy of its PGS eps values into its pinned host buffer (the step's
+// convergence status) and an event that marks its completion; the slot is
+// free again once its whole group completed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <stdexcept>
@@ -42,15 +50,23 @@ struct SceneEntry {
   int queued = 0;
 };
 
-struct Slot {
-  hipStream_t stream = nullptr;
+constexpr int kEpsSlots = 256;   // Newton iterations per step at most
+constexpr int kGroupMax = 64;    // requests per slot and round at most (one batched launch)
+
+struct Member {                  // one request of a slot's group
   hipEvent_t done = nullptr;
-  double *eps = nullptr;   // pinned host: eps of every Newton iteration of the request
-  bool running = false;
+  double *eps = nullptr;         // pinned host: eps of every Newton iteration of the request
+  bool pending = false;          // in flight, not yet reported
   Request req;
 };
 
-constexpr int kEpsSlots = 256;   // Newton iterations per step at most
+struct Slot {
+  hipStream_t stream = nullptr;
+  void *task = nullptr;          // pinned host: the group's Newton tasks (kGroupMax entries)
+  Member mem[kGroupMax];
+  int n = 0;                     // requests of the current group
+  bool running = false;          // a group is in flight
+};
 
 struct ServerError : std::runtime_error {
   icr_status code;
@@ -65,6 +81,10 @@ void hip_check(hipError_t e, const char *what) {
 
 struct icr_server {
   int64_t budget = 0, used = 0;
+  int group = 8;             // requests per slot and round; 0: one whole step per slot (no batching)
+  double max_wait_ms = 0.0;  // a short group waits this long for more requests while another slot runs
+  void *d_tasks = nullptr;   // device table of Newton tasks, kGroupMax entries per slot
+  size_t task_bytes = 0;
   std::vector<Slot> slots;
   std::vector<SceneEntry> scenes;
   std::deque<Request> queue;
@@ -98,52 +118,127 @@ SceneEntry &entry(icr_server *srv, int id) {
   return srv->scenes[id];
 }
 
-// Start queued requests on free slots: the oldest request whose scene is idle.
-// A request whose launch fails becomes a completion with the failing status
-// (its scene stays usable) and the slot takes the next request.
+// A request whose launch failed becomes a completion with the failing
+// status; whatever was enqueued on the slot stream finishes before the scene
+// goes back to its own stream, and the scene stays usable.
+void fail_request(icr_server *srv, Slot &sl, const Request &r, icr_status st) {
+  SceneEntry &se = srv->scenes[r.scene];
+  (void)hipStreamSynchronize(sl.stream);
+  (void)icr_set_stream(se.s, se.own_stream);
+  se.busy = false;
+  icr_completion c{};
+  c.tag = r.tag;
+  c.scene = r.scene;
+  c.status = st;
+  c.latency_ms = c.queue_ms = ms_since(r.t_submit, Clock::now());
+  srv->failed.push_back(c);
+}
+
+// Take a group for every free slot and enqueue it (see the top of the file).
+// The startable requests (the oldest of idle scenes) are spread evenly over
+// the free slots, at most `group` per slot: short rounds while the load is
+// light, full launches under load.  With max_wait_ms > 0, fewer startable
+// requests than a full group wait until the oldest of them has waited that
+// long, or until no slot runs.
 void launch_ready(icr_server *srv) {
-  for (auto &sl : srv->slots) {
-    while (!sl.running) {
-      auto it = srv->queue.begin();
-      while (it != srv->queue.end() && srv->scenes[it->scene].busy) ++it;
-      if (it == srv->queue.end()) return;
-      Request r = *it;
-      srv->queue.erase(it);
-      SceneEntry &se = srv->scenes[r.scene];
-      se.queued--;
-      icr_status st = icr_set_stream(se.s, sl.stream);
-      if (st == ICR_OK) st = icr_step(se.s, &r.obs, &r.opt, nullptr);
-      if (st == ICR_OK) st = icr::enqueue_eps_readback(se.s, r.opt.n_newton, sl.eps);
-      if (st != ICR_OK) {
-        // whatever was enqueued on the slot stream finishes before the
-        // scene goes back to its own stream
-        (void)hipStreamSynchronize(sl.stream);
-        (void)icr_set_stream(se.s, se.own_stream);
-        icr_completion c{};
-        c.tag = r.tag;
-        c.scene = r.scene;
-        c.status = st;
-        c.latency_ms = c.queue_ms = ms_since(r.t_submit, Clock::now());
-        srv->failed.push_back(c);
+  const int gmax = srv->group > 0 ? srv->group : 1;
+  int nfree = 0;
+  for (const Slot &sl : srv->slots) nfree += sl.running ? 0 : 1;
+  if (nfree == 0) return;
+  int ready = 0;
+  const Request *oldest = nullptr;
+  std::vector<char> seen(srv->scenes.size(), 0);
+  for (const Request &r : srv->queue)
+    if (!srv->scenes[r.scene].busy && !seen[r.scene]) {
+      seen[r.scene] = 1;
+      if (!oldest) oldest = &r;
+      if (++ready >= nfree * gmax) break;
+    }
+  if (ready == 0) return;
+  if (srv->group > 1 && srv->max_wait_ms > 0 && ready < gmax && nfree < (int)srv->slots.size() &&
+      ms_since(oldest->t_submit, Clock::now()) < srv->max_wait_ms)
+    return;
+  const int per_slot = std::min(gmax, (ready + nfree - 1) / nfree);
+  for (int k = 0; k < (int)srv->slots.size(); ++k) {
+    Slot &sl = srv->slots[k];
+    if (sl.running) continue;
+    std::vector<Request> grp;
+    for (auto it = srv->queue.begin(); it != srv->queue.end() && (int)grp.size() < per_slot;) {
+      if (srv->scenes[it->scene].busy) {
+        ++it;
         continue;
       }
-      hip_check(hipEventRecord(sl.done, sl.stream), "hipEventRecord");
-      r.t_launch = Clock::now();
-      sl.req = r;
-      sl.running = true;
-      se.busy = true;
+      srv->scenes[it->scene].busy = true;
+      srv->scenes[it->scene].queued--;
+      grp.push_back(*it);
+      it = srv->queue.erase(it);
     }
+    if (grp.empty()) return;
+    sl.n = 0;
+    std::vector<int> batched;   // member indices whose Newton loops run in the group's launch
+    auto task_of = [&](int j) { return static_cast<char *>(sl.task) + (size_t)j * srv->task_bytes; };
+    // whole steps, and the batched steps up to their Newton loops
+    for (const Request &r : grp) {
+      SceneEntry &se = srv->scenes[r.scene];
+      const int j = sl.n;
+      icr_status st = icr_set_stream(se.s, sl.stream);
+      const bool b = srv->group > 0 && icr::newton_batchable(se.s, &r.opt);
+      if (b) {
+        if (st == ICR_OK) st = icr::step_begin(se.s, &r.obs, &r.opt, task_of(j));
+        if (st == ICR_OK) {
+          void *dst = static_cast<char *>(srv->d_tasks) + ((size_t)k * kGroupMax + j) * srv->task_bytes;
+          if (hipMemcpyAsync(dst, task_of(j), srv->task_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+            st = ICR_E_HIP;
+        }
+      } else {
+        if (st == ICR_OK) st = icr_step(se.s, &r.obs, &r.opt, nullptr);
+        if (st == ICR_OK) st = icr::enqueue_eps_readback(se.s, r.opt.n_newton, sl.mem[j].eps);
+        if (st == ICR_OK && hipEventRecord(sl.mem[j].done, sl.stream) != hipSuccess) st = ICR_E_HIP;
+      }
+      if (st != ICR_OK) {
+        fail_request(srv, sl, r, st);
+        continue;
+      }
+      Member &m = sl.mem[j];
+      m.req = r;
+      m.req.t_launch = Clock::now();
+      m.pending = !b;   // a batched member is pending once its step is complete
+      if (b) batched.push_back(j);
+      sl.n++;
+    }
+    if (!batched.empty()) {
+      std::vector<int> idx(batched.size());
+      for (size_t q = 0; q < batched.size(); ++q) idx[q] = k * kGroupMax + batched[q];
+      std::string msg;
+      const icr_status bst = icr::newton_batch(sl.stream, srv->d_tasks, idx.data(), (int)idx.size(), msg);
+      for (int j : batched) {
+        Member &m = sl.mem[j];
+        SceneEntry &se = srv->scenes[m.req.scene];
+        icr_status st = bst;
+        if (st == ICR_OK) st = icr::step_end(se.s, &m.req.opt);
+        if (st == ICR_OK) st = icr::enqueue_eps_readback(se.s, m.req.opt.n_newton, m.eps);
+        if (st == ICR_OK && hipEventRecord(m.done, sl.stream) != hipSuccess) st = ICR_E_HIP;
+        if (st != ICR_OK) {
+          fail_request(srv, sl, m.req, st);
+          continue;
+        }
+        m.pending = true;
+      }
+    }
+    int live = 0;
+    for (int j = 0; j < sl.n; ++j) live += sl.mem[j].pending ? 1 : 0;
+    sl.running = live > 0;
   }
 }
 
 // Status of a completed request: ICR_WARN_NOT_CONVERGED when tol > 0 and a
 // Newton iteration's PGS ended with eps > tol (tol = 0 asks for a fixed
 // sweep count: no convergence test), else ICR_OK.
-int32_t step_status(const Slot &sl) {
-  const icr_step_opts &o = sl.req.opt;
+int32_t step_status(const Member &m) {
+  const icr_step_opts &o = m.req.opt;
   if (!(o.tol > 0)) return ICR_OK;
   for (int k = 0; k < o.n_newton; ++k)
-    if (!(sl.eps[k] <= o.tol)) return ICR_WARN_NOT_CONVERGED;
+    if (!(m.eps[k] <= o.tol)) return ICR_WARN_NOT_CONVERGED;
   return ICR_OK;
 }
 
@@ -159,10 +254,19 @@ icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots
   if (!srv) return ICR_E_OOM;
   srv->budget = hbm_budget;
   srv->slots.resize(slots);
+  srv->task_bytes = icr::newton_task_bytes();   // the table's entry stride, as the kernel indexes it
+  if (hipMalloc(&srv->d_tasks, srv->task_bytes * kGroupMax * slots) != hipSuccess) {
+    srv->d_tasks = nullptr;
+    icr_server_destroy(srv);
+    return ICR_E_HIP;
+  }
   for (auto &sl : srv->slots) {
-    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void **)&sl.eps, sizeof(double) * kEpsSlots, hipHostMallocDefault) != hipSuccess) {
+    bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+              hipHostMalloc(&sl.task, srv->task_bytes * kGroupMax, hipHostMallocDefault) == hipSuccess;
+    for (int j = 0; ok && j < kGroupMax; ++j)
+      ok = hipEventCreateWithFlags(&sl.mem[j].done, hipEventDisableTiming) == hipSuccess &&
+           hipHostMalloc((void **)&sl.mem[j].eps, sizeof(double) * kEpsSlots, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
       icr_server_destroy(srv);
       return ICR_E_HIP;
     }
@@ -174,19 +278,35 @@ icr_status icr_server_create(icr_server **out, int64_t hbm_budget, int32_t slots
 void icr_server_destroy(icr_server *srv) {
   if (!srv) return;
   for (auto &sl : srv->slots) {
-    if (sl.running && sl.done) (void)hipEventSynchronize(sl.done);
-    if (sl.running) {
-      SceneEntry &se = srv->scenes[sl.req.scene];
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    for (int j = 0; j < sl.n; ++j) {
+      Member &m = sl.mem[j];
+      if (!m.pending) continue;
+      SceneEntry &se = srv->scenes[m.req.scene];
       if (se.s) (void)icr_set_stream(se.s, se.own_stream);
     }
-    if (sl.done) (void)hipEventDestroy(sl.done);
+    for (auto &m : sl.mem) {
+      if (m.done) (void)hipEventDestroy(m.done);
+      if (m.eps) (void)hipHostFree(m.eps);
+    }
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.eps) (void)hipHostFree(sl.eps);
+    if (sl.task) (void)hipHostFree(sl.task);
   }
+  if (srv->d_tasks) (void)hipFree(srv->d_tasks);
   delete srv;
 }
 
 const char *icr_server_last_error(const icr_server *srv) { return srv ? srv->err.c_str() : "null server"; }
+
+icr_status icr_server_set_batching(icr_server *srv, int32_t group, double max_wait_ms) {
+  return guarded_srv(srv, [&] {
+    if (group < 0 || group > kGroupMax) throw ServerError(ICR_E_ARG, "group size in [0, 64]");
+    if (!(max_wait_ms >= 0.0) || !std::isfinite(max_wait_ms)) throw ServerError(ICR_E_ARG, "max_wait_ms >= 0");
+    srv->group = group;
+    srv->max_wait_ms = max_wait_ms;
+    return ICR_OK;
+  });
+}
 
 icr_status icr_server_admit(icr_server *srv, icr_scene *scene, int32_t *scene_id) {
   return guarded_srv(srv, [&] {
@@ -289,27 +409,34 @@ icr_status icr_server_poll(icr_server *srv, icr_completion *out, int32_t cap, in
       bool any_running = false;
       for (auto &sl : srv->slots) {
         if (!sl.running) continue;
-        if (n >= cap) {
-          any_running = true;
-          continue;
+        int live = 0;
+        for (int j = 0; j < sl.n; ++j) {
+          Member &m = sl.mem[j];
+          if (!m.pending) continue;
+          if (n >= cap) {
+            live++;
+            continue;
+          }
+          const hipError_t q = hipEventQuery(m.done);
+          if (q == hipErrorNotReady) {
+            live++;
+            continue;
+          }
+          hip_check(q, "hipEventQuery");
+          const auto now = Clock::now();
+          icr_completion &c = out[n++];
+          c.tag = m.req.tag;
+          c.scene = m.req.scene;
+          c.status = step_status(m);
+          c.latency_ms = ms_since(m.req.t_submit, now);
+          c.queue_ms = ms_since(m.req.t_submit, m.req.t_launch);
+          SceneEntry &se = srv->scenes[m.req.scene];
+          (void)icr_set_stream(se.s, se.own_stream);   // its request is complete on the slot stream
+          se.busy = false;
+          m.pending = false;
         }
-        const hipError_t q = hipEventQuery(sl.done);
-        if (q == hipErrorNotReady) {
-          any_running = true;
-          continue;
-        }
-        hip_check(q, "hipEventQuery");
-        const auto now = Clock::now();
-        icr_completion &c = out[n++];
-        c.tag = sl.req.tag;
-        c.scene = sl.req.scene;
-        c.status = step_status(sl);
-        c.latency_ms = ms_since(sl.req.t_submit, now);
-        c.queue_ms = ms_since(sl.req.t_submit, sl.req.t_launch);
-        SceneEntry &se = srv->scenes[sl.req.scene];
-        (void)icr_set_stream(se.s, se.own_stream);   // its request is complete on the slot stream
-        se.busy = false;
-        sl.running = false;
+        sl.running = live > 0;
+        any_running = any_running || sl.running;
       }
       if (n > 0) launch_ready(srv);   // freed slots take the next requests at once
       if (n > 0 || !wait || n >= cap || (!any_running && srv->queue.empty() && srv->failed.empty())) break;
@@ -320,7 +447,8 @@ icr_status icr_server_poll(icr_server *srv, icr_completion *out, int32_t cap, in
     *n_out = n;
     if (pending_out) {
       int p = (int)srv->queue.size() + (int)srv->failed.size();
-      for (auto &sl : srv->slots) p += sl.running ? 1 : 0;
+      for (auto &sl : srv->slots)
+        for (int j = 0; j < sl.n; ++j) p += sl.mem[j].pending ? 1 : 0;
       *pending_out = p;
     }
     return ICR_OK;

@@ -2,6 +2,7 @@
 // public C ABI (host declarations only; defined in api.hip).
 #pragma once
 
+#include <cstddef>
 #include <string>
 
 #include "icr.h"
@@ -28,5 +29,21 @@ void *scene_stream(const icr_scene *s);
 
 // Whether the buffers of an ICR_FP32_IR step are allocated for the reserved contacts.
 bool mixed_reserved(const icr_scene *s);
+
+// Batched Newton loops (the serving path).  A step whose Newton loop can run
+// in the batched launch (fast scheme, FP64, no pair contacts, 1..512
+// contacts, untimed): newton_batchable.  step_begin applies icr_step's
+// checks and enqueues the step up to its Newton loop on the scene's stream,
+// and writes the scene's task (newton_task_bytes() bytes, the device table
+// entry) to `task`; newton_batch runs the Newton loops of the table entries
+// idx[0..n) (n <= 64; entry k at byte k * newton_task_bytes() of the device
+// table `tasks`) in one launch on `stream`, after every step_begin of
+// those scenes completed (the caller orders the streams); step_end enqueues
+// the rest of the step on the scene's stream after the batch.
+size_t newton_task_bytes();
+bool newton_batchable(const icr_scene *s, const icr_step_opts *opt);
+icr_status step_begin(icr_scene *s, const icr_obstacle *obs, const icr_step_opts *opt, void *task);
+icr_status step_end(icr_scene *s, const icr_step_opts *opt);
+icr_status newton_batch(void *stream, const void *tasks, const int *idx, int n, std::string &msg);
 
 }  // namespace icr

@@ -88,6 +88,7 @@ _SIGS = {
     "icr_server_create": (C.c_int, [C.POINTER(_P), C.c_int64, _I]),
     "icr_server_destroy": (None, [_P]),
     "icr_server_last_error": (C.c_char_p, [_P]),
+    "icr_server_set_batching": (C.c_int, [_P, _I, C.c_double]),
     "icr_server_admit": (C.c_int, [_P, _P, C.POINTER(_I)]),
     "icr_server_evict": (C.c_int, [_P, _I]),
     "icr_server_used": (C.c_int, [_P, C.POINTER(C.c_int64)]),
@@ -327,7 +328,10 @@ def _obstacle(obstacle):
 class Server:
     """Serving runtime over many admitted scenes (wraps an icr_server handle)."""
 
-    def __init__(self, hbm_budget, slots=4):
+    def __init__(self, hbm_budget, slots=4, batching=8, max_wait_ms=0.0):
+        """batching: requests per slot and round with batched Newton loops
+        (True = 8), or 0 / False for one whole icr_step per slot; a short
+        group waits up to max_wait_ms for more requests while a slot runs."""
         self.L = lib()
         h = C.c_void_p()
         st = self.L.icr_server_create(C.byref(h), int(hbm_budget), int(slots))
@@ -335,6 +339,8 @@ class Server:
             raise IcrError(st, "icr_server_create failed")
         self._h = h
         self._scenes = {}
+        group = 8 if batching is True else int(batching)
+        self._check(self.L.icr_server_set_batching(self._h, group, float(max_wait_ms)))
 
     def _check(self, st):
         if st != OK:

@@ -1,7 +1,8 @@
 """Serving runtime (icr_server_*): many scenes stepped concurrently.
 
 - a request served in the mix gives bit-for-bit the result of the same step
-  run alone (the server only chooses the stream and the moment);
+  run alone (the server chooses the stream and the moment, and runs the
+  Newton loops of the requests it starts together in one batched launch);
 - steps of one scene complete in submission order;
 - admission against the device-memory budget, eviction;
 - scenes of the serving mix (plane or sphere, 10-500 contacts) against the
@@ -46,7 +47,11 @@ def _run_alone(sc, steps):
     return q.cpu(), v.cpu(), lam.cpu(), t
 
 
-def test_mixed_equals_alone():
+@pytest.mark.parametrize("batching", [True, False])
+def test_mixed_equals_alone(batching):
+    """Steps served in the mix (their Newton loops batched into one launch,
+    or each scene's step whole on its slot) equal the same steps run alone,
+    bit for bit."""
     icr = _icr()
     scs = [make_scene("serving", sd) for sd in SEEDS]
     steps = 3
@@ -54,8 +59,8 @@ def test_mixed_equals_alone():
     for sc in scs:
         _say(f"[gpu] serving alone seed={sc['seed']} nodes={len(sc['nodes'])} nc={sc['n_contacts']}")
         alone.append(_run_alone(sc, steps))
-    _say("[gpu] serving mixed")
-    srv = icr.Server(hbm_budget=64 << 30, slots=4)
+    _say(f"[gpu] serving mixed, batching={batching}")
+    srv = icr.Server(hbm_budget=64 << 30, slots=4, batching=batching)
     scenes = [icr.scene_from_dict(sc) for sc in scs]
     ids = [srv.admit(s) for s in scenes]
     tag = 0
