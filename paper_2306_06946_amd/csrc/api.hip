@@ -822,8 +822,9 @@ void enqueue_newton(icr_scene *s, const icr_step_opts *opt) {
     if (per_constraint) {
       mark(kev, 4 * k);
       mark(kev, 4 * k + 1);
-      launch_pgs_per_constraint(st, nc, S.d_ctx, C.d_WH, C.d_p, C.d_pstart, C.d_mu, h, C.d_f, C.d_C, C.d_lam,
-                                C.d_status, opt->max_sweeps, opt->tol, opt->j_inner, C.d_sweeps + k, C.d_eps + k);
+      launch_pgs_per_constraint(st, nc, S.d_ctx, C.d_WH, C.d_pfree, C.d_p, C.d_pstart, C.d_mu, h, C.d_f, C.d_C,
+                                C.d_lam, C.d_status, opt->max_sweeps, opt->tol, opt->j_inner, C.d_sweeps + k,
+                                C.d_eps + k, C.pgs);
       mark(kev, 4 * k + 2);
       launch_proximity<double>(st, nc, C.d_WH, C.d_pfree, C.d_f, h, C.d_p);  // Eq. 31
       mark(kev, 4 * k + 3);

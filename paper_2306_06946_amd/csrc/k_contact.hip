@@ -858,7 +858,14 @@ __global__ __launch_bounds__(1024) void k_pgs_pc(int nc, const StepCtx *__restri
                                                  double h2, double *__restrict__ f, double *__restrict__ C,
                                                  double *__restrict__ lam, int8_t *__restrict__ status,
                                                  int max_sweeps, double tol, int j_inner, int *__restrict__ sweeps_out,
-                                                 double *__restrict__ eps_out) {
+                                                 double *__restrict__ eps_out, const int *__restrict__ ctl) {
+  // resume mode: continue where the register-chain kernel handed over (or
+  // do nothing); pin then holds the proximity of the hand-over state
+  int first_sweep = 0;
+  if (ctl != nullptr) {
+    if (ctl[0] == 0) return;
+    first_sweep = ctl[1];
+  }
   extern __shared__ double lds_P[];
   double *P = lds_P;
   __shared__ double bc[3];
@@ -874,7 +881,7 @@ __global__ __launch_bounds__(1024) void k_pgs_pc(int nc, const StepCtx *__restri
   __syncthreads();
   int sweep = 0;
   double eps = 0.0, dsum = 0.0;
-  for (sweep = 0; sweep < max_sweeps; ++sweep) {
+  for (sweep = first_sweep; sweep < max_sweeps; ++sweep) {
     dsum = 0.0;
     int a = 0;
     while (true) {
@@ -1780,6 +1787,455 @@ __global__ __launch_bounds__(PGS_NT) void k_newton_batch(const NewtonTask *__res
   }
 }
 
+// ---- directions updated before every local solve, on the register chain ----
+//
+// The per-constraint Gauss-Seidel (R18, k_pgs_pc) with the structure of
+// k_pgs_active: only contacts with a force or a negative normal gap can
+// change (a contact with no force whose gap at its turn is >= 0 stays
+// separated: a no-op), so the sweep runs over the set S of those contacts
+// alone.  Wave 0 holds their proximities P (world frame) in registers; at
+// contact a's turn it takes its frame and gap at P_a, the block
+// W~_aa = h^2 C_a W_H,aa C_a^T, the gap without the own force, the local
+// solve and f_a = C_a^T lambda_a with the same arithmetic as k_pgs_pc, then
+// every lane adds h^2 W_H(own rows, a) (f_a - f_a^old) to its proximities.
+// After a sweep every contact c outside S is verified to have been a no-op:
+// its proximity at its turn is P_c^set + h^2 sum_{b in S} W_H,cb
+// (f_b^turn - f_b^set) (forces of S contacts before c in this sweep, after
+// it from the previous sweep); the signed distance is 1-Lipschitz and
+// |h^2 W_H,cb| <= h sqrt(tr W_H,cc) h sqrt(tr W_H,bb) for the PSD W_H, so
+// phi_set(c) > h sqrt(tr W_H,cc) B with
+// B = sum_b h sqrt(tr W_H,bb) max(|f_b^new - f_b^set|, |f_b^old - f_b^set|)
+// settles c, and the others get their exact proximity and gap.  A violation
+// adds the contact to S and restarts the sweep from its start state; a set
+// beyond 128 contacts hands over to k_pgs_pc (ctl[0] = 1, the sweep in
+// ctl[1], the proximity of the hand-over state in Pset).
+constexpr int PCA_MAX = 128;   // contacts of S in the single-wave chain
+constexpr int PCA_RW = 26;     // record of a contact of S, see PcaLds
+struct PcaLds {
+  double P[3 * PCA_MAX];       // proximity of S (the chain's registers between sweeps)
+  // per contact of S: 0-5 W_H,aa (w00 w01 w02 w11 w12 w22), 6 mu, 7-9 p_start,
+  // 10-12 lambda, 13-21 frame rows, 22-24 world force f, 25 unused
+  double rec[PCA_MAX * PCA_RW];
+  double f0[3 * PCA_MAX];      // forces of S at the sweep's start
+  double fset[3 * PCA_MAX];    // ... at the set's start state
+  double part[8 * 64];         // partial sums of the proximity product
+  double red[48];
+  int Sidx[PCA_MAX];
+  unsigned char stS[PCA_MAX];
+  int wcount[64];
+  int ulist[PGS_MAX_NC];
+  unsigned char inS[PGS_MAX_NC];
+  int nS, flag, stop, nu;
+};
+static_assert(sizeof(PcaLds) <= 160 * 1024, "per-constraint chain state must fit one CU's LDS");
+
+struct PcaRec {
+  double2 r2[PCA_RW / 2];
+  __device__ double operator[](int q) const { return (q & 1) ? r2[q >> 1].y : r2[q >> 1].x; }
+};
+__device__ inline void pca_rec(PcaRec &c, const PcaLds &L, int i) {
+  const double2 *rp = reinterpret_cast<const double2 *>(L.rec + PCA_RW * i);
+#pragma unroll
+  for (int q = 0; q < PCA_RW / 2; ++q) c.r2[q] = rp[q];
+}
+
+// contact_frame with one division per normalisation (a reciprocal and
+// three products, within an ulp of the three divisions): the frame of every
+// visit of the chain.
+__device__ inline void contact_frame_rcp(const icr_obstacle &obs, double t0, double t1, const double pc[3],
+                                         const double ps[3], double F[3][3], double delta[3]) {
+  double n[3], phi;
+  {
+#pragma clang fp contract(off)
+    const double c[3] = {obs.c0[0] + obs.vel[0] * t1, obs.c0[1] + obs.vel[1] * t1, obs.c0[2] + obs.vel[2] * t1};
+    const double r0 = pc[0] - c[0], r1 = pc[1] - c[1], r2 = pc[2] - c[2];
+    if (obs.kind == 1) {
+      const double dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+      const double id = 1.0 / dist;
+      n[0] = r0 * id;
+      n[1] = r1 * id;
+      n[2] = r2 * id;
+      phi = dist - obs.radius;
+    } else {
+      n[0] = obs.normal[0];
+      n[1] = obs.normal[1];
+      n[2] = obs.normal[2];
+      phi = r0 * obs.normal[0] + r1 * obs.normal[1] + r2 * obs.normal[2];
+    }
+  }
+  int ax = 0;
+  double am = fabs(n[0]);
+  if (fabs(n[1]) < am) {
+    ax = 1;
+    am = fabs(n[1]);
+  }
+  if (fabs(n[2]) < am) ax = 2;
+  const double en = n[ax];
+  double ta[3] = {-en * n[0], -en * n[1], -en * n[2]};
+  ta[ax] += 1.0;
+  const double itn = 1.0 / sqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
+  ta[0] *= itn;
+  ta[1] *= itn;
+  ta[2] *= itn;
+  const double tb[3] = {n[1] * ta[2] - n[2] * ta[1], n[2] * ta[0] - n[0] * ta[2], n[0] * ta[1] - n[1] * ta[0]};
+  double rel[3];
+  for (int a = 0; a < 3; ++a) {
+    const double uo = (obs.c0[a] + obs.vel[a] * t1) - (obs.c0[a] + obs.vel[a] * t0);
+    rel[a] = pc[a] - ps[a] - uo;
+  }
+  for (int a = 0; a < 3; ++a) {
+    F[0][a] = n[a];
+    F[1][a] = ta[a];
+    F[2][a] = tb[a];
+  }
+  delta[0] = phi;
+  delta[1] = ta[0] * rel[0] + ta[1] * rel[1] + ta[2] * rel[2];
+  delta[2] = tb[0] * rel[0] + tb[1] * rel[1] + tb[2] * rel[2];
+}
+
+// One visit of the chain: contact i, its proximity in lane i % 64, slot K.
+template <int K, int NS, int J>
+__device__ inline void pca_step(int i, const double2 (&X)[NS][PGS_BLK / 2], const PcaRec &c, double (&g)[NS][3],
+                                PcaLds &L, int j_inner, int ln, const icr_obstacle &obs, double t0, double t1,
+                                double h2) {
+  const int li = i & 63;
+  const double pa[3] = {readlane_f64(g[K][0], li), readlane_f64(g[K][1], li), readlane_f64(g[K][2], li)};
+  const double ps[3] = {c[7], c[8], c[9]};
+  double F[3][3], delta[3];
+  contact_frame_rcp(obs, t0, t1, pa, ps, F, delta);
+  const double wh[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+  double B[3][3];   // W_H,aa C_a^T
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) B[a][b] = wh[a][0] * F[b][0] + wh[a][1] * F[b][1] + wh[a][2] * F[b][2];
+  double w[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) w[a][b] = h2 * (F[a][0] * B[0][b] + F[a][1] * B[1][b] + F[a][2] * B[2][b]);
+  for (int a = 0; a < 3; ++a)   // exactly symmetric block
+    for (int b = 0; b < a; ++b) w[b][a] = w[a][b];
+  const double fo[3] = {c[22], c[23], c[24]};
+  double lr[3], dd[3];
+  for (int a = 0; a < 3; ++a) lr[a] = F[a][0] * fo[0] + F[a][1] * fo[1] + F[a][2] * fo[2];
+  for (int a = 0; a < 3; ++a) dd[a] = delta[a] - (w[a][0] * lr[0] + w[a][1] * lr[1] + w[a][2] * lr[2]);
+  double rc[PGS_RW];
+  make_record(w, c[6], rc);
+  const Local r = local_solve_rec<J>(rc, dd, j_inner);
+  double fn[3], df[3];
+  for (int q = 0; q < 3; ++q) {
+    fn[q] = F[0][q] * r.l[0] + F[1][q] * r.l[1] + F[2][q] * r.l[2];
+    df[q] = fn[q] - fo[q];
+  }
+  if (ln == 0) {
+    double *lp = L.rec + PCA_RW * i;
+    for (int q = 0; q < 3; ++q) {
+      lp[10 + q] = r.l[q];
+      lp[22 + q] = fn[q];
+      for (int k = 0; k < 3; ++k) lp[13 + 3 * q + k] = F[q][k];
+    }
+    L.stS[i] = (unsigned char)r.st;
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double b[9] = {X[k][0].x, X[k][0].y, X[k][1].x, X[k][1].y, X[k][2].x,
+                         X[k][2].y, X[k][3].x, X[k][3].y, X[k][4].x};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[k][a] = fma(b[3 * a + 2], df[2], fma(b[3 * a + 1], df[1], fma(b[3 * a], df[0], g[k][a])));
+  }
+}
+
+template <int K, int NS, int J>
+__device__ inline void pca_slot(int nS, const double *__restrict__ Wb, PcaLds &L, int j_inner, int ln,
+                                double (&g)[NS][3], double2 (&A)[NS][PGS_BLK / 2], double2 (&B)[NS][PGS_BLK / 2],
+                                PcaRec &rA, PcaRec &rB, const icr_obstacle &obs, double t0, double t1, double h2) {
+  const int last = nS - 1, end = min(nS, 64 * K + 64);
+  for (int i = 64 * K; i < end; i += 2) {
+    pca_rec(rB, L, min(i + 1, last));
+    pca_step<K, NS, J>(i, A, rA, g, L, j_inner, ln, obs, t0, t1, h2);
+    chain_load<NS>(A, Wb, min(i + 2, last), ln);
+    if (i + 1 < end) {
+      pca_rec(rA, L, min(i + 2, last));
+      pca_step<K, NS, J>(i + 1, B, rB, g, L, j_inner, ln, obs, t0, t1, h2);
+    }
+    chain_load<NS>(B, Wb, min(i + 3, last), ln);
+  }
+}
+
+template <int NS, int J>
+__device__ __forceinline__ void pca_chain(int nS, const double *__restrict__ Wb, PcaLds &L, int j_inner,
+                                          const icr_obstacle &obs, double t0, double t1, double h2) {
+  const int ln = threadIdx.x & 63;
+  double g[NS][3];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int c = ln + 64 * k;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[k][q] = c < nS ? L.P[3 * c + q] : 0.0;
+  }
+  const int last = nS - 1;
+  double2 A[NS][PGS_BLK / 2], B[NS][PGS_BLK / 2];
+  PcaRec rA, rB;
+  chain_load<NS>(A, Wb, 0, ln);
+  chain_load<NS>(B, Wb, min(1, last), ln);
+  pca_rec(rA, L, 0);
+  pca_slot<0, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB, obs, t0, t1, h2);
+  if constexpr (NS > 1) pca_slot<1, NS, J>(nS, Wb, L, j_inner, ln, g, A, B, rA, rB, obs, t0, t1, h2);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int c = ln + 64 * k;
+    if (c < nS) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) L.P[3 * c + q] = g[k][q];
+    }
+  }
+}
+
+// Exact proximity of a contact c outside S at its turn in the last sweep,
+// by one wave (all lanes return it): Pset_c + h^2 sum_{b in S} W_H,cb
+// (f_b^turn - f_b^set).
+__device__ inline void pca_turn_proximity(int c, int nS, int m, const double *__restrict__ WH,
+                                          const double *__restrict__ Pset, double h2, const PcaLds &L, int ln,
+                                          double pt[3]) {
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int q = ln; q < 3 * nS; q += 64) {
+    const int b = L.Sidx[q / 3];
+    const double fnew = L.rec[PCA_RW * (q / 3) + 22 + q % 3];
+    const double d = ((b < c) ? fnew : L.f0[q]) - L.fset[q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a[r] = fma(h2 * WH[(3L * c + r) * m + 3L * b + q % 3], d, a[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    for (int o = 32; o > 0; o >>= 1) a[r] += __shfl_xor(a[r], o, 64);
+    pt[r] = Pset[3 * c + r] + a[r];
+  }
+}
+
+__global__ __launch_bounds__(PGS_NT) void k_pgs_pca(int nc, const StepCtx *__restrict__ ctx,
+                                                    const double *__restrict__ WH, const double *__restrict__ pfree,
+                                                    const double *__restrict__ pin, const double *__restrict__ pstart,
+                                                    const double *__restrict__ mu, double h2, double *__restrict__ f,
+                                                    double *__restrict__ C, double *__restrict__ lam,
+                                                    int8_t *__restrict__ status, int max_sweeps, double tol,
+                                                    int j_inner, int *__restrict__ sweeps_out,
+                                                    double *__restrict__ eps_out, double *__restrict__ Wss,
+                                                    double *__restrict__ Pset, double *__restrict__ gnSet,
+                                                    double *__restrict__ swn, int *__restrict__ ctl) {
+  extern __shared__ double lds_raw[];
+  PcaLds &L = *reinterpret_cast<PcaLds *>(lds_raw);
+  const int m = 3 * nc;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const icr_obstacle obs = ctx->obs;
+  const double t0 = ctx->t0, t1 = ctx->t0 + ctx->h;
+  for (int c = tid; c < nc; c += PGS_NT) {
+    const long d = 3L * c;
+    swn[c] = sqrt(h2 * (WH[d * m + d] + WH[(d + 1) * m + d + 1] + WH[(d + 2) * m + d + 2]));
+    L.inS[c] = 0;
+  }
+  for (int e = tid; e < m; e += PGS_NT) Pset[e] = pin[e];
+  if (tid == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    L.stop = 0;
+  }
+  __syncthreads();
+  int sweep = 0, nS = 0, nsp = 64;
+  double eps = 0.0;
+  bool need_build = true, first = true;
+  while (sweep < max_sweeps) {
+    if (need_build) {
+      // proximity of the set's start state (given for the first set)
+      if (!first) wg_sym_gemv_sparse<double>(nc, WH, pfree, f, f, h2, Pset, L.ulist, &L.nu, L.part);
+      // normal gaps there; members: a force, a negative gap, or an earlier violation
+      for (int c = tid; c < nc; c += PGS_NT) {
+        const double pc[3] = {Pset[3 * c], Pset[3 * c + 1], Pset[3 * c + 2]};
+        const double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
+        double F[3][3], delta[3];
+        contact_frame(obs, t0, t1, pc, ps, F, delta);
+        gnSet[c] = delta[0];
+        const bool nz = f[3 * c] != 0.0 || f[3 * c + 1] != 0.0 || f[3 * c + 2] != 0.0;
+        if (nz || delta[0] < 0.0) L.inS[c] = 1;
+      }
+      __syncthreads();
+      const int nwin = (nc + 63) / 64;
+      for (int w = wv; w < nwin; w += PGS_NW) {
+        const int c = 64 * w + ln;
+        const unsigned long long bal = __ballot(c < nc && L.inS[c]);
+        if (ln == 0) L.wcount[w] = __popcll(bal);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < nwin; ++w) {
+          const int t = L.wcount[w];
+          L.wcount[w] = acc;
+          acc += t;
+        }
+        L.nS = acc;
+      }
+      __syncthreads();
+      nS = L.nS;
+      if (nS > PCA_MAX) {   // hand over: f and Pset hold the sweep-start state
+        if (tid == 0) {
+          ctl[0] = 1;
+          ctl[1] = sweep;
+        }
+        return;
+      }
+      for (int w = wv; w < nwin; w += PGS_NW) {
+        const int c = 64 * w + ln;
+        const bool in = c < nc && L.inS[c];
+        const unsigned long long bal = __ballot(in);
+        if (in) L.Sidx[L.wcount[w] + __popcll(bal & ((1ull << ln) - 1ull))] = c;
+      }
+      __syncthreads();
+      nsp = pgs_wave_pad(nS);
+      for (int i = tid; i < nS; i += PGS_NT) {
+        const long d = 3L * L.Sidx[i];
+        double *rc = L.rec + PCA_RW * i;
+        rc[0] = WH[d * m + d];
+        rc[1] = WH[d * m + d + 1];
+        rc[2] = WH[d * m + d + 2];
+        rc[3] = WH[(d + 1) * m + d + 1];
+        rc[4] = WH[(d + 1) * m + d + 2];
+        rc[5] = WH[(d + 2) * m + d + 2];
+        rc[6] = mu[L.Sidx[i]];
+        for (int q = 0; q < 3; ++q) {
+          rc[7 + q] = pstart[d + q];
+          rc[22 + q] = f[d + q];
+        }
+      }
+      for (int r = tid; r < 3 * nS; r += PGS_NT) {
+        const long e = 3L * L.Sidx[r / 3] + r % 3;
+        L.P[r] = Pset[e];
+        L.fset[r] = f[e];
+      }
+      // h^2 W_H,SS blocked [i][c] (rows of contact c, columns of contact i),
+      // diagonal blocks included
+      const long nel = (long)nS * nsp * PGS_BLK;
+      for (long e = tid; e < nel; e += PGS_NT) {
+        const int j = (int)(e % PGS_BLK);
+        const long ic = e / PGS_BLK;
+        const int cc = (int)(ic % nsp), i = (int)(ic / nsp);
+        double v = 0.0;
+        if (j < 9 && cc < nS) v = h2 * WH[(3L * L.Sidx[cc] + j / 3) * m + 3L * L.Sidx[i] + j % 3];
+        Wss[e] = v;
+      }
+      __threadfence_block();
+      __syncthreads();
+      need_build = false;
+      first = false;
+    }
+    // ---- one sweep over S from its start state
+    for (int r = tid; r < 3 * nS; r += PGS_NT) L.f0[r] = L.rec[PCA_RW * (r / 3) + 22 + r % 3];
+    if (tid == 0) {
+      L.flag = 0;
+      L.nu = 0;
+    }
+    __syncthreads();
+    if (nS > 0 && wv == 0) {
+      if (j_inner == 8) {
+        if (nsp == 64)
+          pca_chain<1, 8>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+        else
+          pca_chain<2, 8>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+      } else {
+        if (nsp == 64)
+          pca_chain<1, 0>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+        else
+          pca_chain<2, 0>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+      }
+    }
+    __syncthreads();
+    // eps = |f_i - f_{i-1}| / |f_i| (forces outside S stay zero), and B
+    double dpart = 0.0, bpart = 0.0, npart = 0.0;
+    for (int i = tid; i < nS; i += PGS_NT) {
+      const double *rc = L.rec + PCA_RW * i;
+      double dnew = 0.0, dold = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double fn = rc[22 + q], fo = L.f0[3 * i + q], fs = L.fset[3 * i + q];
+        dpart += (fn - fo) * (fn - fo);
+        npart += fn * fn;
+        dnew += (fn - fs) * (fn - fs);
+        dold += (fo - fs) * (fo - fs);
+      }
+      bpart += sqrt(h2 * (rc[0] + rc[3] + rc[5])) * sqrt(fmax(dnew, dold));
+    }
+    block_sum3(dpart, bpart, npart, L.red);
+    if (tid == 0) {
+      const double diff = sqrt(dpart), nf = sqrt(npart);
+      eps = nf > 0.0 ? diff / nf : (diff == 0.0 ? 0.0 : INFINITY);
+      L.stop = (eps <= tol) ? 1 : 0;
+      L.red[0] = bpart * (1.0 + 1e-12);
+    }
+    __syncthreads();
+    const double Bb = L.red[0];
+    // ---- verify the skipped contacts
+    for (int c = tid; c < nc; c += PGS_NT) {
+      if (L.inS[c]) continue;
+      const double g = gnSet[c], rb = swn[c] * Bb;
+      if (!(g - rb > 1e-13 * (fabs(g) + rb))) L.ulist[atomicAdd(&L.nu, 1)] = c;
+    }
+    __syncthreads();
+    const int nu = L.nu;
+    for (int u = wv; u < nu; u += PGS_NW) {
+      const int c = L.ulist[u];
+      double pt[3];
+      pca_turn_proximity(c, nS, m, WH, Pset, h2, L, ln, pt);
+      if (ln == 0) {
+        const double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
+        double F[3][3], delta[3];
+        contact_frame(obs, t0, t1, pt, ps, F, delta);
+        if (delta[0] < 0.0) {
+          L.inS[c] = 1;
+          L.flag = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (L.flag) {
+      // a skipped contact was not a no-op: restart the sweep with a larger S
+      for (int r = tid; r < 3 * nS; r += PGS_NT) f[3L * L.Sidx[r / 3] + r % 3] = L.f0[r];
+      need_build = true;
+      __threadfence_block();
+      __syncthreads();
+      continue;
+    }
+    ++sweep;
+    if (L.stop) break;
+  }
+  // ---- results: S from its records; the others separate, with the frame at
+  // their proximity at their turn in the last sweep
+  for (int r = tid; r < 3 * nS; r += PGS_NT) {
+    const long e = 3L * L.Sidx[r / 3] + r % 3;
+    const double *rc = L.rec + PCA_RW * (r / 3);
+    f[e] = rc[22 + r % 3];
+    lam[e] = rc[10 + r % 3];
+  }
+  for (int i = tid; i < nS; i += PGS_NT) {
+    const double *rc = L.rec + PCA_RW * i;
+    for (int q = 0; q < 9; ++q) C[9L * L.Sidx[i] + q] = rc[13 + q];
+    status[L.Sidx[i]] = (int8_t)L.stS[i];
+  }
+  for (int c = wv; c < nc; c += PGS_NW) {
+    if (L.inS[c]) continue;
+    double pt[3];
+    pca_turn_proximity(c, nS, m, WH, Pset, h2, L, ln, pt);
+    if (ln == 0) {
+      const double ps[3] = {pstart[3 * c], pstart[3 * c + 1], pstart[3 * c + 2]};
+      double F[3][3], delta[3];
+      contact_frame(obs, t0, t1, pt, ps, F, delta);
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) C[9L * c + 3 * r + q] = F[r][q];
+        lam[3 * c + r] = 0.0;
+      }
+      status[c] = (int8_t)ICR_SEPARATE;
+    }
+  }
+  if (tid == 0) {
+    *sweeps_out = sweep;
+    *eps_out = eps;
+  }
+}
+
 // ---- large active sets: block Gauss-Seidel over the whole GPU --------------
 //
 // When the active set outgrows the register chains (k_pgs_active hands over
@@ -2423,12 +2879,18 @@ template void launch_pgs<double>(hipStream_t, int, const double *, const double 
 template void launch_pgs<float>(hipStream_t, int, const float *, const double *, const double *, double, double *,
                                 int8_t *, int, double, int, int *, double *, const PgsWork &);
 
-void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
-                               const double *pstart, const double *mu, double h, double *f, double *Cm,
-                               double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
-                               double *eps_dev) {
-  k_pgs_pc<<<1, 1024, pgs_pc_lds(nc), st>>>(nc, ctx, WH, p, pstart, mu, h * h, f, Cm, lam, status, max_sweeps, tol,
-                                           j_inner, sweeps_dev, eps_dev);
+void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *pfree,
+                               const double *p, const double *pstart, const double *mu, double h, double *f,
+                               double *Cm, double *lam, int8_t *status, int max_sweeps, double tol, int j_inner,
+                               int *sweeps_dev, double *eps_dev, const PgsWork &wk) {
+  // the register chain over the contacts that can change, then (only if
+  // their set outgrew the chain) the one-workgroup sweep from that state
+  k_pgs_pca<<<1, PGS_NT, sizeof(PcaLds), st>>>(nc, ctx, WH, pfree, p, pstart, mu, h * h, f, Cm, lam, status,
+                                               max_sweeps, tol, j_inner, sweeps_dev, eps_dev, wk.Wss, wk.g, wk.gnSet,
+                                               wk.swn, wk.ctl);
+  ICR_LAUNCH_CHECK();
+  k_pgs_pc<<<1, 1024, pgs_pc_lds(nc), st>>>(nc, ctx, WH, wk.g, pstart, mu, h * h, f, Cm, lam, status, max_sweeps, tol,
+                                           j_inner, sweeps_dev, eps_dev, wk.ctl);
   ICR_LAUNCH_CHECK();
 }
 
@@ -2465,6 +2927,8 @@ void pgs_prepare() {
                               (int)sizeof(PgsLds)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_newton_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
+  ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_pca, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(PcaLds)));
   ICR_HIP(hipFuncSetAttribute((const void *)k_pgs_coop<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(PgsLds)));
   // cooperative launch: at most one workgroup per compute unit (its LDS),

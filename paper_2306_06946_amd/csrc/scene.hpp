@@ -324,10 +324,10 @@ void pgs_prepare();   // kernel attributes (dynamic LDS), once per device; call 
 // workgroup each, in one launch on stream st.
 void launch_newton_batch(hipStream_t st, const NewtonTask *tasks, const NewtonBatchIdx &ids);
 int coop_grid();      // workgroups of the cooperative large-set PGS on this device (0: not available)
-void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *p,
-                               const double *pstart, const double *mu, double h, double *f, double *Cm,
-                               double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,
-                               double *eps_dev);
+void launch_pgs_per_constraint(hipStream_t st, int nc, const StepCtx *ctx, const double *WH, const double *pfree,
+                               const double *p, const double *pstart, const double *mu, double h, double *f,
+                               double *Cm, double *lam, int8_t *status, int max_sweeps, double tol, int j_inner,
+                               int *sweeps_dev, double *eps_dev, const PgsWork &wk);
 template <class TW>
 void launch_pgs(hipStream_t st, int nc, const TW *W, const double *d, const double *mu, double h,
                 double *lam, int8_t *status, int max_sweeps, double tol, int j_inner, int *sweeps_dev,

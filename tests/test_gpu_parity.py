@@ -537,6 +537,36 @@ def test_per_constraint_directions_match_oracle(cfg, seed):
     s.close()
 
 
+def test_per_constraint_beyond_the_chain_matches_oracle():
+    """Directions updated before every local solve with all 200 contacts of
+    the medium scene changing (a plane pressed 2 mm into its bottom face): the
+    set outgrows the register chain, which hands the sweeps over to the
+    one-workgroup kernel; one step against the oracle."""
+    icr = _icr()
+    sc = make_scene("medium", 0)
+    sc["obstacle"] = dict(kind="plane", normal=np.array([0.0, 0.0, 1.0]), c0=np.array([0.07, 0.07, 0.002]),
+                          vel=np.array([0.0, 0.0, 0.02]), radius=0.0)
+    sc["max_sweeps"] = 30
+    nc = sc["n_contacts"]
+    s = icr.scene_from_dict(sc)
+    sim = O.Simulation(sc)
+    _say("[gpu] per-constraint directions, 200 changing contacts")
+    rep = s.step(sc["obstacle"], nc, sc["n_newton"], sc["max_sweeps"], sc["tol"], sc["j_inner"], per_constraint=True)
+    rec = []
+    out = sim.step(record=rec, per_constraint=True)
+    res = s.step_results(nc)
+    q, v, _ = s.get_state()
+    assert int(np.sum(rec[-1]["status"] != 0)) > 128
+    assert np.array_equal(res["node_ids"].cpu().numpy(), out["nodes_c"])
+    assert rep["sweeps"] == [r["sweeps"] for r in rec][:16]
+    assert np.array_equal(res["status"].cpu().numpy(), rec[-1]["status"])
+    assert _rel(res["lam"].cpu().numpy(), rec[-1]["lam"]) <= 1e-10
+    assert _rel(res["C"].cpu().numpy().reshape(-1, 3, 3), rec[-1]["C"]) <= 1e-12
+    assert _rel(res["p"].cpu().numpy() - out["p_free"], out["p"] - out["p_free"]) <= 1e-10
+    assert _rel(q.cpu().numpy() - sim.q_rest, out["q"] - sim.q_rest) <= 1e-10
+    s.close()
+
+
 def test_step_medium_matches_oracle():
     sc = make_scene("medium", 0)
     sc["max_sweeps"] = 100
