@@ -380,6 +380,25 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
   return out;
 }
 
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (full double precision for the well-scaled positive values used here).
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ inline double frsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+// One Newton step only: relative error about the square of the estimate's
+// (used inside the slip fixed point, whose iterates are renormalised anyway).
+__device__ inline double frsqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 // Per-contact record of the active-set PGS, computed once per active set from
 // the symmetric 3x3 block w of h^2 W_aa and mu (kappa = (w11 + w22) / 2):
 //   0-5  w00 w01 w02 w11 w12 w22      6-11 the same entries of -w^-1
@@ -387,12 +406,16 @@ __device__ Local local_solve(const double w[3][3], const double d[3], double mu,
 //   15   mu w01             16 mu w02             17 mu
 //   18   1 if w00 > mu |(w01, w02)| with margin (then den(u) > 0 on the unit
 //        circle and the slip pass needs no fallback), else 0
+// FAST (a record built inside a Gauss-Seidel visit, on its dependent chain):
+// the refined reciprocal for 1 / det and the margin test compared squared.
 constexpr int PGS_RW = kPgsRecWidth;   // record width: 19 entries, then the contact's current force (chain)
+template <bool FAST = false>
 __device__ inline void make_record(const double w[3][3], double mu, double *rec) {
   const double w00 = w[0][0], w01 = w[0][1], w02 = w[0][2], w11 = w[1][1], w12 = w[1][2], w22 = w[2][2];
   const double c00 = w11 * w22 - w12 * w12, c01 = w02 * w12 - w01 * w22, c02 = w01 * w12 - w02 * w11;
   const double c11 = w00 * w22 - w02 * w02, c12 = w01 * w02 - w00 * w12, c22 = w00 * w11 - w01 * w01;
-  const double idet = 1.0 / (w00 * c00 + w01 * c01 + w02 * c02);
+  const double det = w00 * c00 + w01 * c01 + w02 * c02;
+  const double idet = FAST ? frcp(det) : 1.0 / det;
   const double kap = 0.5 * (w11 + w22);
   rec[0] = w00;
   rec[1] = w01;
@@ -412,26 +435,12 @@ __device__ inline void make_record(const double w[3][3], double mu, double *rec)
   rec[15] = mu * w01;
   rec[16] = mu * w02;
   rec[17] = mu;
-  rec[18] = (w00 > 1.000001 * mu * sqrt(w01 * w01 + w02 * w02)) ? 1.0 : 0.0;
-}
-
-// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
-// (full double precision for the well-scaled positive values used here).
-__device__ inline double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return fma(fma(-x, r, 1.0), r, r);
-}
-__device__ inline double frsqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
-}
-// One Newton step only: relative error about the square of the estimate's
-// (used inside the slip fixed point, whose iterates are renormalised anyway).
-__device__ inline double frsqrt1(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  if (FAST) {
+    const double mm = 1.000001 * mu;   // w00 > mm |(w01, w02)| squared, w00 > 0
+    rec[18] = (w00 > 0.0 && w00 * w00 > (mm * mm) * (w01 * w01 + w02 * w02)) ? 1.0 : 0.0;
+  } else {
+    rec[18] = (w00 > 1.000001 * mu * sqrt(w01 * w01 + w02 * w02)) ? 1.0 : 0.0;
+  }
 }
 
 // Guarded slip pass (rare: the record's den > 0 guarantee fails, or |v| = 0
@@ -1839,9 +1848,10 @@ __device__ inline void pca_rec(PcaRec &c, const PcaLds &L, int i) {
   for (int q = 0; q < PCA_RW / 2; ++q) c.r2[q] = rp[q];
 }
 
-// contact_frame with one division per normalisation (a reciprocal and
-// three products, within an ulp of the three divisions): the frame of every
-// visit of the chain.
+// contact_frame with each normalisation by the refined reciprocal square
+// root of the squared length (the length itself is that square times it):
+// within an ulp or two of the square roots and divisions, and a short
+// dependent chain; the frame of every visit of the chain.
 __device__ inline void contact_frame_rcp(const icr_obstacle &obs, double t0, double t1, const double pc[3],
                                          const double ps[3], double F[3][3], double delta[3]) {
   double n[3], phi;
@@ -1850,12 +1860,12 @@ __device__ inline void contact_frame_rcp(const icr_obstacle &obs, double t0, dou
     const double c[3] = {obs.c0[0] + obs.vel[0] * t1, obs.c0[1] + obs.vel[1] * t1, obs.c0[2] + obs.vel[2] * t1};
     const double r0 = pc[0] - c[0], r1 = pc[1] - c[1], r2 = pc[2] - c[2];
     if (obs.kind == 1) {
-      const double dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-      const double id = 1.0 / dist;
+      const double d2 = r0 * r0 + r1 * r1 + r2 * r2;
+      const double id = frsqrt(d2);
       n[0] = r0 * id;
       n[1] = r1 * id;
       n[2] = r2 * id;
-      phi = dist - obs.radius;
+      phi = d2 * id - obs.radius;
     } else {
       n[0] = obs.normal[0];
       n[1] = obs.normal[1];
@@ -1873,7 +1883,7 @@ __device__ inline void contact_frame_rcp(const icr_obstacle &obs, double t0, dou
   const double en = n[ax];
   double ta[3] = {-en * n[0], -en * n[1], -en * n[2]};
   ta[ax] += 1.0;
-  const double itn = 1.0 / sqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
+  const double itn = frsqrt(ta[0] * ta[0] + ta[1] * ta[1] + ta[2] * ta[2]);
   ta[0] *= itn;
   ta[1] *= itn;
   ta[2] *= itn;
@@ -1917,7 +1927,7 @@ __device__ inline void pca_step(int i, const double2 (&X)[NS][PGS_BLK / 2], cons
   for (int a = 0; a < 3; ++a) lr[a] = F[a][0] * fo[0] + F[a][1] * fo[1] + F[a][2] * fo[2];
   for (int a = 0; a < 3; ++a) dd[a] = delta[a] - (w[a][0] * lr[0] + w[a][1] * lr[1] + w[a][2] * lr[2]);
   double rc[PGS_RW];
-  make_record(w, c[6], rc);
+  make_record<true>(w, c[6], rc);
   const Local r = local_solve_rec<J>(rc, dd, j_inner);
   double fn[3], df[3];
   for (int q = 0; q < 3; ++q) {
