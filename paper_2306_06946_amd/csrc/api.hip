@@ -242,6 +242,21 @@ void prepare_factor(icr_scene *s) {
       L.max_below_tiles = std::max(L.max_below_tiles, cdiv(b3, TILE));
     }
   }
+  // k-chunks of the forward single-RHS products: a level with fewer than 256
+  // row blocks of 64 splits each block's k range (of at least 256 per chunk)
+  // over up to 16 blocks
+  long long fwd_part = 0;
+  for (LevelInfo &L : F.levels) {
+    auto split = [&](int rows, int k) {
+      const int blocks = cdiv(rows, 64) * L.count;
+      if (rows <= 0 || blocks >= 256) return 1;
+      return std::max(1, std::min({16, cdiv(512, blocks), k / 256}));
+    };
+    L.fwd_split_diag = split(L.max_n3, L.max_n3);
+    L.fwd_split_off = split(L.max_b3, L.max_n3);
+    const long long rd = (long long)cdiv(L.max_n3, 64) * L.count, ro = (long long)cdiv(L.max_b3, 64) * L.count;
+    fwd_part = std::max({fwd_part, rd * L.fwd_split_diag, ro * L.fwd_split_off});
+  }
   std::vector<int> sup_of_node(m.N);
   for (int s_ = 0; s_ < ns; ++s_)
     for (int p = sym.col0[s_]; p < sym.col0[s_] + sym.ncol[s_]; ++p) sup_of_node[sym.perm[p]] = s_;
@@ -270,6 +285,7 @@ void prepare_factor(icr_scene *s) {
   F.d_x1 = A.alloc<double>(F.x1_elems);
   F.d_y = A.alloc<double>(2L * m.n);
   F.d_err = A.alloc<int>(1);
+  F.d_fwd_part = A.alloc<double>(std::max(1LL, fwd_part * 64));
   ICR_HIP(hipStreamSynchronize(st));
 }
 

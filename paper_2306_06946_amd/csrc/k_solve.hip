@@ -599,6 +599,27 @@ __device__ inline double fwd1_front(const SupDev &S, int i, const SupDev *__rest
   return v;
 }
 
+// Split-K single-RHS products (top tree levels, where a level has too few
+// 64-row blocks to fill the GPU): block x = row block * nsplit + chunk; each
+// block writes the sums over its chunk of k to part[(slot * nsplit + chunk)
+// * 64 + row] (slot = supernode of the level * row blocks + row block) and
+// k_fwd1_fin adds the nsplit partials in chunk order.  nsplit = 1: the row
+// block's sums are final.  Returns true when they are (wave 0: row sums).
+__device__ inline bool fwd1_split_store(double t, int rb, int nsplit, int nrb, double *__restrict__ part) {
+  if (nsplit == 1) return true;
+  const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int slot = blockIdx.y * nrb + rb, ks = blockIdx.x % nsplit;
+  if (ph == 0) part[((long)slot * nsplit + ks) * GV_R + r] = t;
+  return false;
+}
+
+// Chunk [ka, kb) of k in [0, kend) for chunk ks of nsplit (multiples of GV_P).
+__device__ inline void fwd1_chunk(int kend, int nsplit, int ks, int &ka, int &kb) {
+  const int kc = ((kend + nsplit - 1) / nsplit + GV_P - 1) / GV_P * GV_P;
+  ka = min(kend, ks * kc);
+  kb = min(kend, ka + kc);
+}
+
 // y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]; the front entries it needs
 // are assembled on the fly into LDS (GV_X at a time)
 __global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
@@ -606,25 +627,28 @@ __global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ s
                                                     const int *__restrict__ invmap_off, const int *__restrict__ invmap,
                                                     const int *__restrict__ perm, const double *__restrict__ b,
                                                     const double *__restrict__ linv, const double *__restrict__ x1,
-                                                    double *__restrict__ y) {
-  __shared__ double part[GV_P][GV_R + 1];
+                                                    double *__restrict__ y, int nsplit, double *__restrict__ part) {
+  __shared__ double ps[GV_P][GV_R + 1];
   __shared__ double xs[GV_X];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol;
-  const int i0 = GV_R * blockIdx.x;
+  const int rb = blockIdx.x / nsplit, i0 = GV_R * rb;
   if (i0 >= n3) return;   // uniform over the block
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
   const int kend = min(n3, i0 + GV_R);
+  int ka, kb;
+  fwd1_chunk(kend, nsplit, blockIdx.x % nsplit, ka, kb);
   double v = 0.0;
-  for (int kk = 0; kk < kend; kk += GV_X) {
-    const int kn = min(kend, kk + GV_X);
+  for (int kk = ka; kk < kb; kk += GV_X) {
+    const int kn = min(kb, kk + GV_X);
     __syncthreads();
     for (int k = kk + threadIdx.x; k < kn; k += 1024)
       xs[k - kk] = fwd1_front(S, k, sup, child, invmap_off, invmap, perm, b, x1);
     __syncthreads();
     v += gemv_part(linv + S.linv_off, n3, xs - kk, i, n3, kk, kn, ph);
   }
-  const double t = phase_sum(v, part);
+  const double t = phase_sum(v, ps);
+  if (!fwd1_split_store(t, rb, nsplit, gridDim.x / nsplit, part)) return;
   if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
 }
 
@@ -633,17 +657,42 @@ __global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ su
                                                    const int *__restrict__ child, const int *__restrict__ invmap_off,
                                                    const int *__restrict__ invmap, const int *__restrict__ perm,
                                                    const double *__restrict__ b, const double *__restrict__ front,
-                                                   const double *__restrict__ y, double *__restrict__ x1) {
-  __shared__ double part[GV_P][GV_R + 1];
+                                                   const double *__restrict__ y, double *__restrict__ x1, int nsplit,
+                                                   double *__restrict__ part) {
+  __shared__ double ps[GV_P][GV_R + 1];
   const SupDev S = sup[level_sup[blockIdx.y]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int i0 = GV_R * blockIdx.x;
+  const int rb = blockIdx.x / nsplit, i0 = GV_R * rb;
   if (i0 >= b3) return;
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
-  const double v = gemv_part(front + S.front_off + n3, f, y + 3 * S.col0, i, b3, 0, n3, ph);
-  const double t = phase_sum(v, part);
+  int ka, kb;
+  fwd1_chunk(n3, nsplit, blockIdx.x % nsplit, ka, kb);
+  const double v = gemv_part(front + S.front_off + n3, f, y + 3 * S.col0, i, b3, ka, kb, ph);
+  const double t = phase_sum(v, ps);
+  if (!fwd1_split_store(t, rb, nsplit, gridDim.x / nsplit, part)) return;
   if (ph == 0 && i < b3)
     x1[S.x1_off + n3 + i] = fwd1_front(S, n3 + i, sup, child, invmap_off, invmap, perm, b, x1) - t;
+}
+
+// The sums of split products (one wave per row block): off = 0 writes y of
+// the diagonal product, off = 1 the below rows of x1.
+__global__ __launch_bounds__(64) void k_fwd1_fin(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
+                                                 const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                                 const int *__restrict__ invmap, const int *__restrict__ perm,
+                                                 const double *__restrict__ b, int off, int nsplit,
+                                                 const double *__restrict__ part, double *__restrict__ y,
+                                                 double *__restrict__ x1) {
+  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int n3 = 3 * S.ncol, rows = off ? 3 * S.nb : n3;
+  const int rb = blockIdx.x, i = GV_R * rb + (int)threadIdx.x;
+  if (i >= rows) return;
+  const int slot = blockIdx.y * gridDim.x + rb;
+  double t = 0.0;
+  for (int q = 0; q < nsplit; ++q) t += part[((long)slot * nsplit + q) * GV_R + threadIdx.x];
+  if (off)
+    x1[S.x1_off + n3 + i] = fwd1_front(S, n3 + i, sup, child, invmap_off, invmap, perm, b, x1) - t;
+  else
+    y[3 * S.col0 + i] = t;
 }
 
 // y_s[j] -= sum_i L21(i, j) x[below row i]
@@ -794,14 +843,26 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
     const LevelInfo &L = F.levels[l];
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
-    k_fwd1_diag<<<dim3(cdiv(L.max_n3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
-                                                                       F.d_invmap, F.d_perm, b, F.d_linv, F.d_x1, y);
+    const int rd = cdiv(L.max_n3, GV_R), ro = cdiv(L.max_b3, GV_R);
+    k_fwd1_diag<<<dim3(rd * L.fwd_split_diag, L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
+                                                                        F.d_invmap, F.d_perm, b, F.d_linv, F.d_x1, y,
+                                                                        L.fwd_split_diag, F.d_fwd_part);
     ICR_LAUNCH_CHECK();
-    if (L.max_b3 > 0) {
-      k_fwd1_off<<<dim3(cdiv(L.max_b3, GV_R), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
-                                                                        F.d_invmap, F.d_perm, b, F.d_front, y,
-                                                                        F.d_x1);
+    if (L.fwd_split_diag > 1) {
+      k_fwd1_fin<<<dim3(rd, L.count), 64, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b, 0,
+                                                   L.fwd_split_diag, F.d_fwd_part, y, F.d_x1);
       ICR_LAUNCH_CHECK();
+    }
+    if (L.max_b3 > 0) {
+      k_fwd1_off<<<dim3(ro * L.fwd_split_off, L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
+                                                                       F.d_invmap, F.d_perm, b, F.d_front, y, F.d_x1,
+                                                                       L.fwd_split_off, F.d_fwd_part);
+      ICR_LAUNCH_CHECK();
+      if (L.fwd_split_off > 1) {
+        k_fwd1_fin<<<dim3(ro, L.count), 64, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b,
+                                                     1, L.fwd_split_off, F.d_fwd_part, y, F.d_x1);
+        ICR_LAUNCH_CHECK();
+      }
     }
   }
   backward_solve(s, x);

@@ -49,6 +49,7 @@ struct LevelInfo {
   int max_below_tiles = 0;    // max ceil(b3/64)
   int a_first = 0, a_count = 0;   // A-scatter entries of the level
   int child_rank_max = 0;
+  int fwd_split_diag = 1, fwd_split_off = 1;   // k-chunks of the split single-RHS forward products
 };
 
 struct Mesh {
@@ -107,6 +108,8 @@ struct Factor {
   double *d_R = nullptr;
   // single-RHS work vectors (permuted)
   double *d_y = nullptr;
+  // partial sums of the split forward products
+  double *d_fwd_part = nullptr;
 };
 
 // Work buffers of the PGS kernels: start gaps g [m], the compact coupling
