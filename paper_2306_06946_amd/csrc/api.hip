@@ -242,20 +242,31 @@ void prepare_factor(icr_scene *s) {
       L.max_below_tiles = std::max(L.max_below_tiles, cdiv(b3, TILE));
     }
   }
-  // k-chunks of the forward single-RHS products: a level with fewer than 256
-  // row blocks of 64 splits each block's k range (of at least 256 per chunk)
-  // over up to 16 blocks
+  // single-RHS task lists: every (supernode, block) of a level that exists;
+  // k-chunks of the forward products: a level with fewer than 256 row blocks
+  // of 64 splits each block's k range (of at least 256 per chunk) over up to
+  // 16 blocks
+  std::vector<int2> srhs;
   long long fwd_part = 0;
   for (LevelInfo &L : F.levels) {
-    auto split = [&](int rows, int k) {
-      const int blocks = cdiv(rows, 64) * L.count;
-      if (rows <= 0 || blocks >= 256) return 1;
+    const int rows_of[3] = {64, 64, 16};
+    for (int k = 0; k < 3; ++k) {
+      L.srhs_off[k] = (int)srhs.size();
+      for (int q = 0; q < L.count; ++q) {
+        const SupDev &S = F.sup[sym.level_sup[L.first + q]];
+        const int len = (k == SR_FWD_OFF) ? 3 * S.nb : 3 * S.ncol;
+        for (int bk = 0; bk < cdiv(len, rows_of[k]); ++bk) srhs.push_back(make_int2(q, bk));
+      }
+      L.srhs_cnt[k] = (int)srhs.size() - L.srhs_off[k];
+    }
+    auto split = [&](int blocks, int k) {
+      if (blocks <= 0 || blocks >= 256) return 1;
       return std::max(1, std::min({16, cdiv(512, blocks), k / 256}));
     };
-    L.fwd_split_diag = split(L.max_n3, L.max_n3);
-    L.fwd_split_off = split(L.max_b3, L.max_n3);
-    const long long rd = (long long)cdiv(L.max_n3, 64) * L.count, ro = (long long)cdiv(L.max_b3, 64) * L.count;
-    fwd_part = std::max({fwd_part, rd * L.fwd_split_diag, ro * L.fwd_split_off});
+    L.fwd_split_diag = split(L.srhs_cnt[SR_FWD_DIAG], L.max_n3);
+    L.fwd_split_off = split(L.srhs_cnt[SR_FWD_OFF], L.max_n3);
+    fwd_part = std::max({fwd_part, (long long)L.srhs_cnt[SR_FWD_DIAG] * L.fwd_split_diag,
+                         (long long)L.srhs_cnt[SR_FWD_OFF] * L.fwd_split_off});
   }
   std::vector<int> sup_of_node(m.N);
   for (int s_ = 0; s_ < ns; ++s_)
@@ -286,6 +297,7 @@ void prepare_factor(icr_scene *s) {
   F.d_y = A.alloc<double>(2L * m.n);
   F.d_err = A.alloc<int>(1);
   F.d_fwd_part = A.alloc<double>(std::max(1LL, fwd_part * 64));
+  F.d_srhs_tasks = A.upload(srhs, st);
   ICR_HIP(hipStreamSynchronize(st));
 }
 

@@ -599,17 +599,18 @@ __device__ inline double fwd1_front(const SupDev &S, int i, const SupDev *__rest
   return v;
 }
 
-// Split-K single-RHS products (top tree levels, where a level has too few
-// 64-row blocks to fill the GPU): block x = row block * nsplit + chunk; each
-// block writes the sums over its chunk of k to part[(slot * nsplit + chunk)
-// * 64 + row] (slot = supernode of the level * row blocks + row block) and
+// The single-RHS products take block x from a static task list of their
+// level: (supernode of the level, block of 64 rows or 16 columns), only the
+// blocks a supernode has.  Split-K (top tree levels, where a level has too
+// few row blocks to fill the GPU): block y = chunk of k; each block writes
+// the sums over its chunk to part[(task * nsplit + chunk) * 64 + row] and
 // k_fwd1_fin adds the nsplit partials in chunk order.  nsplit = 1: the row
 // block's sums are final.  Returns true when they are (wave 0: row sums).
-__device__ inline bool fwd1_split_store(double t, int rb, int nsplit, int nrb, double *__restrict__ part) {
+__device__ inline bool fwd1_split_store(double t, double *__restrict__ part) {
+  const int nsplit = gridDim.y;
   if (nsplit == 1) return true;
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6;
-  const int slot = blockIdx.y * nrb + rb, ks = blockIdx.x % nsplit;
-  if (ph == 0) part[((long)slot * nsplit + ks) * GV_R + r] = t;
+  if (ph == 0) part[((long)blockIdx.x * nsplit + blockIdx.y) * GV_R + r] = t;
   return false;
 }
 
@@ -623,21 +624,21 @@ __device__ inline void fwd1_chunk(int kend, int nsplit, int ks, int &ka, int &kb
 // y[3 col0 + i] = sum_{k <= i} Linv(i, k) x1_s[k]; the front entries it needs
 // are assembled on the fly into LDS (GV_X at a time)
 __global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                    const int *__restrict__ child,
+                                                    const int2 *__restrict__ tasks, const int *__restrict__ child,
                                                     const int *__restrict__ invmap_off, const int *__restrict__ invmap,
                                                     const int *__restrict__ perm, const double *__restrict__ b,
                                                     const double *__restrict__ linv, const double *__restrict__ x1,
-                                                    double *__restrict__ y, int nsplit, double *__restrict__ part) {
+                                                    double *__restrict__ y, double *__restrict__ part) {
   __shared__ double ps[GV_P][GV_R + 1];
   __shared__ double xs[GV_X];
-  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int2 tk = tasks[blockIdx.x];
+  const SupDev S = sup[level_sup[tk.x]];
   const int n3 = 3 * S.ncol;
-  const int rb = blockIdx.x / nsplit, i0 = GV_R * rb;
-  if (i0 >= n3) return;   // uniform over the block
+  const int i0 = GV_R * tk.y;
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
   const int kend = min(n3, i0 + GV_R);
   int ka, kb;
-  fwd1_chunk(kend, nsplit, blockIdx.x % nsplit, ka, kb);
+  fwd1_chunk(kend, gridDim.y, blockIdx.y, ka, kb);
   double v = 0.0;
   for (int kk = ka; kk < kb; kk += GV_X) {
     const int kn = min(kb, kk + GV_X);
@@ -648,28 +649,29 @@ __global__ __launch_bounds__(1024) void k_fwd1_diag(const SupDev *__restrict__ s
     v += gemv_part(linv + S.linv_off, n3, xs - kk, i, n3, kk, kn, ph);
   }
   const double t = phase_sum(v, ps);
-  if (!fwd1_split_store(t, rb, nsplit, gridDim.x / nsplit, part)) return;
+  if (!fwd1_split_store(t, part)) return;
   if (ph == 0 && i < n3) y[3 * S.col0 + i] = t;
 }
 
 // x1_s[n_s + i] = front(n_s + i) - sum_k L21(i, k) y_s[k]
 __global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                   const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                                   const int2 *__restrict__ tasks, const int *__restrict__ child,
+                                                   const int *__restrict__ invmap_off,
                                                    const int *__restrict__ invmap, const int *__restrict__ perm,
                                                    const double *__restrict__ b, const double *__restrict__ front,
-                                                   const double *__restrict__ y, double *__restrict__ x1, int nsplit,
+                                                   const double *__restrict__ y, double *__restrict__ x1,
                                                    double *__restrict__ part) {
   __shared__ double ps[GV_P][GV_R + 1];
-  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int2 tk = tasks[blockIdx.x];
+  const SupDev S = sup[level_sup[tk.x]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int rb = blockIdx.x / nsplit, i0 = GV_R * rb;
-  if (i0 >= b3) return;
+  const int i0 = GV_R * tk.y;
   const int r = threadIdx.x & 63, ph = threadIdx.x >> 6, i = i0 + r;
   int ka, kb;
-  fwd1_chunk(n3, nsplit, blockIdx.x % nsplit, ka, kb);
+  fwd1_chunk(n3, gridDim.y, blockIdx.y, ka, kb);
   const double v = gemv_part(front + S.front_off + n3, f, y + 3 * S.col0, i, b3, ka, kb, ph);
   const double t = phase_sum(v, ps);
-  if (!fwd1_split_store(t, rb, nsplit, gridDim.x / nsplit, part)) return;
+  if (!fwd1_split_store(t, part)) return;
   if (ph == 0 && i < b3)
     x1[S.x1_off + n3 + i] = fwd1_front(S, n3 + i, sup, child, invmap_off, invmap, perm, b, x1) - t;
 }
@@ -677,18 +679,19 @@ __global__ __launch_bounds__(1024) void k_fwd1_off(const SupDev *__restrict__ su
 // The sums of split products (one wave per row block): off = 0 writes y of
 // the diagonal product, off = 1 the below rows of x1.
 __global__ __launch_bounds__(64) void k_fwd1_fin(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                 const int *__restrict__ child, const int *__restrict__ invmap_off,
+                                                 const int2 *__restrict__ tasks, const int *__restrict__ child,
+                                                 const int *__restrict__ invmap_off,
                                                  const int *__restrict__ invmap, const int *__restrict__ perm,
                                                  const double *__restrict__ b, int off, int nsplit,
                                                  const double *__restrict__ part, double *__restrict__ y,
                                                  double *__restrict__ x1) {
-  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int2 tk = tasks[blockIdx.x];
+  const SupDev S = sup[level_sup[tk.x]];
   const int n3 = 3 * S.ncol, rows = off ? 3 * S.nb : n3;
-  const int rb = blockIdx.x, i = GV_R * rb + (int)threadIdx.x;
+  const int i = GV_R * tk.y + (int)threadIdx.x;
   if (i >= rows) return;
-  const int slot = blockIdx.y * gridDim.x + rb;
   double t = 0.0;
-  for (int q = 0; q < nsplit; ++q) t += part[((long)slot * nsplit + q) * GV_R + threadIdx.x];
+  for (int q = 0; q < nsplit; ++q) t += part[((long)blockIdx.x * nsplit + q) * GV_R + threadIdx.x];
   if (off)
     x1[S.x1_off + n3 + i] = fwd1_front(S, n3 + i, sup, child, invmap_off, invmap, perm, b, x1) - t;
   else
@@ -697,13 +700,14 @@ __global__ __launch_bounds__(64) void k_fwd1_fin(const SupDev *__restrict__ sup,
 
 // y_s[j] -= sum_i L21(i, j) x[below row i]
 __global__ __launch_bounds__(1024) void k_bwd1_off(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                   const int *__restrict__ rows, const double *__restrict__ front,
-                                                   const double *__restrict__ xp, double *__restrict__ y) {
+                                                   const int2 *__restrict__ tasks, const int *__restrict__ rows,
+                                                   const double *__restrict__ front, const double *__restrict__ xp,
+                                                   double *__restrict__ y) {
   __shared__ double xg[GV_X];
-  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int2 tk = tasks[blockIdx.x];
+  const SupDev S = sup[level_sup[tk.x]];
   const int n3 = 3 * S.ncol, b3 = 3 * S.nb, f = n3 + b3;
-  const int j0 = GV_P * blockIdx.x;
-  if (j0 >= n3) return;
+  const int j0 = GV_P * tk.y;
   const int *rw = rows + S.rows_off;
   const int bs = min(b3, GV_X);
   for (int i = threadIdx.x; i < bs; i += 1024) xg[i] = xp[3 * rw[i / 3] + i % 3];
@@ -728,13 +732,13 @@ __global__ __launch_bounds__(1024) void k_bwd1_off(const SupDev *__restrict__ su
 
 // xp[3 col0 + j] = sum_{i >= j} Linv(i, j) y_s[i]
 __global__ __launch_bounds__(1024) void k_bwd1_diag(const SupDev *__restrict__ sup, const int *__restrict__ level_sup,
-                                                    const double *__restrict__ linv, const double *__restrict__ y,
-                                                    double *__restrict__ xp) {
+                                                    const int2 *__restrict__ tasks, const double *__restrict__ linv,
+                                                    const double *__restrict__ y, double *__restrict__ xp) {
   __shared__ double yg[GV_X];
-  const SupDev S = sup[level_sup[blockIdx.y]];
+  const int2 tk = tasks[blockIdx.x];
+  const SupDev S = sup[level_sup[tk.x]];
   const int n3 = 3 * S.ncol;
-  const int j0 = GV_P * blockIdx.x;
-  if (j0 >= n3) return;
+  const int j0 = GV_P * tk.y;
   const double *ys = y + 3 * S.col0;
   const int ns = min(n3, GV_X);
   for (int i = j0 + threadIdx.x; i < ns; i += 1024) yg[i] = ys[i];
@@ -780,11 +784,13 @@ void backward_solve(icr_scene *s, double *x) {
     const LevelInfo &L = F.levels[l];
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
+    const int2 *tb = F.d_srhs_tasks + L.srhs_off[SR_BWD];
+    const unsigned nb = (unsigned)L.srhs_cnt[SR_BWD];
     if (L.max_b3 > 0) {
-      k_bwd1_off<<<dim3(cdiv(L.max_n3, GV_P), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_rows, F.d_front, xp, y);
+      k_bwd1_off<<<nb, 1024, 0, st>>>(F.d_sup, ls, tb, F.d_rows, F.d_front, xp, y);
       ICR_LAUNCH_CHECK();
     }
-    k_bwd1_diag<<<dim3(cdiv(L.max_n3, GV_P), L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_linv, y, xp);
+    k_bwd1_diag<<<nb, 1024, 0, st>>>(F.d_sup, ls, tb, F.d_linv, y, xp);
     ICR_LAUNCH_CHECK();
   }
   k_unpermute_vec<<<cdiv(s->mesh.N, 256), 256, 0, st>>>(s->mesh.N, F.d_perm, xp, x);
@@ -843,24 +849,23 @@ void single_rhs_solve(icr_scene *s, const double *b, double *x) {
     const LevelInfo &L = F.levels[l];
     if (!L.count) continue;
     const int *ls = F.d_level_sup + L.first;
-    const int rd = cdiv(L.max_n3, GV_R), ro = cdiv(L.max_b3, GV_R);
-    k_fwd1_diag<<<dim3(rd * L.fwd_split_diag, L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
-                                                                        F.d_invmap, F.d_perm, b, F.d_linv, F.d_x1, y,
-                                                                        L.fwd_split_diag, F.d_fwd_part);
+    const int2 *td = F.d_srhs_tasks + L.srhs_off[SR_FWD_DIAG], *to = F.d_srhs_tasks + L.srhs_off[SR_FWD_OFF];
+    const unsigned nd = (unsigned)L.srhs_cnt[SR_FWD_DIAG], no = (unsigned)L.srhs_cnt[SR_FWD_OFF];
+    k_fwd1_diag<<<dim3(nd, L.fwd_split_diag), 1024, 0, st>>>(F.d_sup, ls, td, F.d_child, F.d_invmap_off, F.d_invmap,
+                                                              F.d_perm, b, F.d_linv, F.d_x1, y, F.d_fwd_part);
     ICR_LAUNCH_CHECK();
     if (L.fwd_split_diag > 1) {
-      k_fwd1_fin<<<dim3(rd, L.count), 64, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b, 0,
-                                                   L.fwd_split_diag, F.d_fwd_part, y, F.d_x1);
+      k_fwd1_fin<<<nd, 64, 0, st>>>(F.d_sup, ls, td, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b, 0,
+                                    L.fwd_split_diag, F.d_fwd_part, y, F.d_x1);
       ICR_LAUNCH_CHECK();
     }
-    if (L.max_b3 > 0) {
-      k_fwd1_off<<<dim3(ro * L.fwd_split_off, L.count), 1024, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off,
-                                                                       F.d_invmap, F.d_perm, b, F.d_front, y, F.d_x1,
-                                                                       L.fwd_split_off, F.d_fwd_part);
+    if (no > 0) {
+      k_fwd1_off<<<dim3(no, L.fwd_split_off), 1024, 0, st>>>(F.d_sup, ls, to, F.d_child, F.d_invmap_off, F.d_invmap,
+                                                              F.d_perm, b, F.d_front, y, F.d_x1, F.d_fwd_part);
       ICR_LAUNCH_CHECK();
       if (L.fwd_split_off > 1) {
-        k_fwd1_fin<<<dim3(ro, L.count), 64, 0, st>>>(F.d_sup, ls, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b,
-                                                     1, L.fwd_split_off, F.d_fwd_part, y, F.d_x1);
+        k_fwd1_fin<<<no, 64, 0, st>>>(F.d_sup, ls, to, F.d_child, F.d_invmap_off, F.d_invmap, F.d_perm, b, 1,
+                                      L.fwd_split_off, F.d_fwd_part, y, F.d_x1);
         ICR_LAUNCH_CHECK();
       }
     }

@@ -50,7 +50,12 @@ struct LevelInfo {
   int a_first = 0, a_count = 0;   // A-scatter entries of the level
   int child_rank_max = 0;
   int fwd_split_diag = 1, fwd_split_off = 1;   // k-chunks of the split single-RHS forward products
+  int srhs_off[3] = {0, 0, 0}, srhs_cnt[3] = {0, 0, 0};   // single-RHS task lists (SR_*) of the level
 };
+// single-RHS task lists per level: (supernode of the level, block): forward
+// diagonal (64 rows of n_s), forward below rows (64 of b_s), backward (16
+// columns of n_s)
+enum { SR_FWD_DIAG = 0, SR_FWD_OFF = 1, SR_BWD = 2 };
 
 struct Mesh {
   int N = 0, T = 0, n = 0, nnzb = 0;
@@ -108,8 +113,9 @@ struct Factor {
   double *d_R = nullptr;
   // single-RHS work vectors (permuted)
   double *d_y = nullptr;
-  // partial sums of the split forward products
+  // partial sums of the split forward products, the single-RHS task lists
   double *d_fwd_part = nullptr;
+  int2 *d_srhs_tasks = nullptr;
 };
 
 // Work buffers of the PGS kernels: start gaps g [m], the compact coupling
