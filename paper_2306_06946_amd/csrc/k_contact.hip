@@ -1034,7 +1034,8 @@ struct PgsLds {
   unsigned char inS[PGS_MAX_NC];
   double Rmin;   // settle threshold of the set: B below it settles every skipped contact
   int nS, flag, stop, nu, zflag, settled;
-  int cprog, cflag;   // block Gauss-Seidel: contacts done by the chain, next block staged
+  int cprog, cflag;   // contacts done by the solving chain; block Gauss-Seidel: next block staged
+  int perr;           // a two-wave sweep's wait ran out
 };
 
 static_assert(sizeof(PgsLds) <= 160 * 1024, "active-set PGS state must fit one CU's LDS");
@@ -1167,6 +1168,107 @@ __device__ __forceinline__ void chain_wave(int nS, const double *__restrict__ Wb
 #pragma unroll
       for (int q = 0; q < 3; ++q) L.gS[3 * (c + o) + q] = g[k][q];
     }
+  }
+}
+
+// Sweep over a set of 65..128 contacts by two waves: wave w keeps the gaps of
+// contacts 64 w .. 64 w + 63 (the blocked W~_SS rows of both halves are
+// stored as for a two-slot chain).  Contacts 0..63 are solved by wave 0
+// while wave 1 applies each one's force change to its own gaps as soon as
+// it is published, then contacts 64.. by wave 1 while wave 0 applies
+// theirs; neither wave applies the other half's updates on the chain.  The
+// solving wave publishes how many contacts are done in L.cprog after the
+// force's stores (LDS operations of one wave complete in order); the
+// applying wave takes the change as the published force minus the force at
+// the sweep's start (each contact is solved once per sweep), so every gap
+// receives the same products in the same order as in the one-wave sweep.
+// A wait that runs out (a broken count, not an input) sets L.perr.
+constexpr int PAIR_SPIN = 1 << 24;
+__device__ inline void pair_load(double2 (&X)[1][PGS_BLK / 2], const double *__restrict__ Wb, int i, int ln,
+                                 int w) {
+  const double2 *base = reinterpret_cast<const double2 *>(Wb + (long)i * (128 * PGS_BLK));
+  const int lo = (64 * w + ln) * (PGS_BLK / 2);
+#pragma unroll
+  for (int j = 0; j < PGS_BLK / 2; ++j) X[0][j] = base[lo + j];
+}
+
+// The solving half: contacts b .. e-1 (one slot of this wave's gaps).
+template <int J>
+__device__ inline void pair_solve(int b, int e, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln,
+                                  int w, double (&g)[1][3]) {
+  if (b >= e) return;
+  const int last = e - 1;
+  double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
+  ChainRec rA, rB;
+  pair_load(A, Wb, b, ln, w);
+  pair_load(B, Wb, min(b + 1, last), ln, w);
+  chain_rec(rA, L, b);
+  for (int i = b; i < e; i += 2) {
+    chain_rec(rB, L, min(i + 1, last));
+    chain_step<0, 1, J>(i, A, rA, g, L, j_inner, ln, 0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (ln == 0) __hip_atomic_store(&L.cprog, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    pair_load(A, Wb, min(i + 2, last), ln, w);
+    if (i + 1 < e) {
+      chain_rec(rA, L, min(i + 2, last));
+      chain_step<0, 1, J>(i + 1, B, rB, g, L, j_inner, ln, 0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (ln == 0) __hip_atomic_store(&L.cprog, i + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    pair_load(B, Wb, min(i + 3, last), ln, w);
+  }
+}
+
+// The applying half: the changes of contacts b .. e-1, solved by the other
+// wave, added to this wave's gaps in contact order.
+__device__ inline void pair_apply_one(int i, const double2 (&X)[1][PGS_BLK / 2], PgsLds &L, double (&g)[1][3]) {
+  for (int spin = 0; __hip_atomic_load(&L.cprog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i; ++spin) {
+    if (spin == PAIR_SPIN) {
+      L.perr = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const double *rp = L.rec + PGS_RW * i + 19;
+  const double d0 = rp[0] - L.lamS0[3 * i], d1 = rp[1] - L.lamS0[3 * i + 1], d2 = rp[2] - L.lamS0[3 * i + 2];
+  const double bb[9] = {X[0][0].x, X[0][0].y, X[0][1].x, X[0][1].y, X[0][2].x,
+                        X[0][2].y, X[0][3].x, X[0][3].y, X[0][4].x};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g[0][a] = fma(bb[3 * a + 2], d2, fma(bb[3 * a + 1], d1, fma(bb[3 * a], d0, g[0][a])));
+}
+__device__ inline void pair_apply(int b, int e, const double *__restrict__ Wb, PgsLds &L, int ln, int w,
+                                  double (&g)[1][3]) {
+  if (b >= e) return;
+  const int last = e - 1;
+  double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
+  pair_load(A, Wb, b, ln, w);
+  pair_load(B, Wb, min(b + 1, last), ln, w);
+  for (int i = b; i < e; i += 2) {
+    pair_apply_one(i, A, L, g);
+    pair_load(A, Wb, min(i + 2, last), ln, w);
+    if (i + 1 < e) pair_apply_one(i + 1, B, L, g);
+    pair_load(B, Wb, min(i + 3, last), ln, w);
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void chain_pair(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int w) {
+  const int ln = threadIdx.x & 63, c = 64 * w + ln;
+  double g[1][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) g[0][q] = c < nS ? L.gS[3 * c + q] : 0.0;
+  const int h = min(64, nS);
+  if (w == 0) {
+    pair_solve<J>(0, h, Wb, L, j_inner, ln, w, g);
+    pair_apply(h, nS, Wb, L, ln, w, g);
+  } else {
+    pair_apply(0, h, Wb, L, ln, w, g);
+    pair_solve<J>(h, nS, Wb, L, j_inner, ln, w, g);
+  }
+  if (c < nS) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[0][q];
   }
 }
 
@@ -1374,6 +1476,7 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
   if (tid == 0) {
     L.stop = 0;
     L.zflag = 0;
+    L.perr = 0;
     ctl[0] = 0;
     ctl[1] = 0;
   }
@@ -1542,22 +1645,23 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
     if (tid == 0) {
       L.flag = 0;
       L.nu = 0;
+      L.cprog = 0;
     }
     __syncthreads();
     if (nS > 0) {
       if (nS <= 128) {
-        if (wv == 0) {
-          if (j_inner == 8) {
-            if (nsp == 64)
+        if (nsp == 64) {
+          if (wv == 0) {
+            if (j_inner == 8)
               chain_wave<1, 8>(nS, Wss, L, j_inner);
             else
-              chain_wave<2, 8>(nS, Wss, L, j_inner);
-          } else {
-            if (nsp == 64)
               chain_wave<1, 0>(nS, Wss, L, j_inner);
-            else
-              chain_wave<2, 0>(nS, Wss, L, j_inner);
           }
+        } else if (wv < 2) {
+          if (j_inner == 8)
+            chain_pair<8>(nS, Wss, L, j_inner, wv);
+          else
+            chain_pair<0>(nS, Wss, L, j_inner, wv);
         }
       } else {
         if (j_inner == 8)
@@ -1586,7 +1690,8 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
     if (tid == 0) {
       const double diff = sqrt(dpart), nl = sqrt(npart);
       eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
-      L.stop = (eps <= tol) ? 1 : 0;
+      if (L.perr) eps = NAN;   // a two-wave sweep lost its count: stop and report eps = NaN
+      L.stop = (eps <= tol || L.perr) ? 1 : 0;
       L.red[0] = bpart * (1.0 + 1e-12);
       L.settled = (L.zflag == 0 && L.red[0] < L.Rmin) ? 1 : 0;
     }
@@ -1616,7 +1721,7 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
       }
       __syncthreads();
     }
-    if (L.flag) {
+    if (L.flag && !L.perr) {
       // a skipped contact was not a no-op: restart the sweep with a larger S
       for (int r = tid; r < ldS; r += PGS_NT) lam[3 * L.Sidx[r / 3] + r % 3] = L.lamS0[r];
       need_build = true;
