@@ -99,8 +99,9 @@ def profiled_issue(kernel):
             valu, busy, cpi = float(f[2]), float(f[3]), float(f[4])
             return {"valu_insts_per_launch": valu, "busy_cycles_per_launch": busy, "cycles_per_valu": cpi,
                     "issue_bound_cycles": valu * cpi, "frac": valu * cpi / busy,
-                    "note": "one wave's dependent chain: FP64 VALU issue of the launch's instructions "
-                            "against its busy cycles (profiles/pgs_issue_precision.md)"}
+                    "note": "dependent chain of one solving wave at a time: FP64 VALU issue of the launch's "
+                            "instructions (all waves) against its busy cycles, an upper bound of the chain's "
+                            "share (profiles/pgs_issue_precision.md)"}
     return None
 
 
