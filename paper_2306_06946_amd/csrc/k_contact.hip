@@ -1024,8 +1024,6 @@ constexpr int PGS_BLK = kPgsBlk;            // doubles per 3x3 block of the bloc
 struct PgsLds {
   double gS[PGS_S3], lamS[PGS_S3], lamS0[PGS_S3], lamSet[PGS_S3];
   double rec[PGS_SMAX * PGS_RW];
-  double bc[3];
-  double ebuf[2][3];   // gap of the current contact, published by its owning wave
   double red[48];
   int Sidx[PGS_SMAX];
   unsigned char stS[PGS_SMAX];
@@ -1035,7 +1033,7 @@ struct PgsLds {
   double Rmin;   // settle threshold of the set: B below it settles every skipped contact
   int nS, flag, stop, nu, zflag, settled;
   int cprog, cflag;   // contacts done by the solving chain; block Gauss-Seidel: next block staged
-  int perr;           // a two-wave sweep's wait ran out
+  int perr;           // a wait of the ring sweep ran out
 };
 
 static_assert(sizeof(PgsLds) <= 160 * 1024, "active-set PGS state must fit one CU's LDS");
@@ -1171,62 +1169,69 @@ __device__ __forceinline__ void chain_wave(int nS, const double *__restrict__ Wb
   }
 }
 
-// Sweep over a set of 65..128 contacts by two waves: wave w keeps the gaps of
-// contacts 64 w .. 64 w + 63 (the blocked W~_SS rows of both halves are
-// stored as for a two-slot chain).  Contacts 0..63 are solved by wave 0
-// while wave 1 applies each one's force change to its own gaps as soon as
-// it is published, then contacts 64.. by wave 1 while wave 0 applies
-// theirs; neither wave applies the other half's updates on the chain.  The
-// solving wave publishes how many contacts are done in L.cprog after the
-// force's stores (LDS operations of one wave complete in order); the
-// applying wave takes the change as the published force minus the force at
-// the sweep's start (each contact is solved once per sweep), so every gap
-// receives the same products in the same order as in the one-wave sweep.
-// A wait that runs out (a broken count, not an input) sets L.perr.
-constexpr int PAIR_SPIN = 1 << 24;
-__device__ inline void pair_load(double2 (&X)[1][PGS_BLK / 2], const double *__restrict__ Wb, int i, int ln,
-                                 int w) {
-  const double2 *base = reinterpret_cast<const double2 *>(Wb + (long)i * (128 * PGS_BLK));
+// Sweep over a set of 65..512 contacts by R = ceil(nS / 64) waves: wave w
+// keeps the gaps of contacts 64 w .. 64 w + 63 (one register slot; blocked
+// W~_SS columns of nsp contacts).  The contacts are solved in order, each
+// 64-contact block by the wave that keeps its gaps, while every other wave
+// applies each solved contact's force change to its own gaps as soon as it
+// is published; no wave applies another block's updates on the solving
+// chain, and no barrier is taken.  The solving wave publishes how many
+// contacts are done in L.cprog after the force's stores (LDS operations of
+// one wave complete in order); an applying wave takes the change as the
+// published force minus the force at the sweep's start (each contact is
+// solved once per sweep), so every gap receives the same products in the
+// same order as in the one-wave sweep.  A wave solves its block only after
+// it has applied every earlier block, so each wait is on a wave that is
+// making progress.  A wait that runs out (a broken count, not an input)
+// sets L.perr.
+// NSP: the padded set size when fixed at compile time (128: two waves), else 0.
+constexpr int RING_SPIN = 1 << 24;
+template <int NSP>
+__device__ inline void ring_load(double2 (&X)[1][PGS_BLK / 2], const double *__restrict__ Wb, int i, int nsp,
+                                 int ln, int w) {
+  const double2 *base = reinterpret_cast<const double2 *>(Wb + (long)i * (NSP ? NSP : nsp) * PGS_BLK);
   const int lo = (64 * w + ln) * (PGS_BLK / 2);
 #pragma unroll
   for (int j = 0; j < PGS_BLK / 2; ++j) X[0][j] = base[lo + j];
 }
 
-// The solving half: contacts b .. e-1 (one slot of this wave's gaps).
-template <int J>
-__device__ inline void pair_solve(int b, int e, const double *__restrict__ Wb, PgsLds &L, int j_inner, int ln,
-                                  int w, double (&g)[1][3]) {
+// The solving part: contacts b .. e-1 (this wave's gaps).
+template <int J, int NSP>
+__device__ inline void ring_solve(int b, int e, int nsp, const double *__restrict__ Wb, PgsLds &L, int j_inner,
+                                  int ln, int w, double (&g)[1][3]) {
   if (b >= e) return;
   const int last = e - 1;
   double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
   ChainRec rA, rB;
-  pair_load(A, Wb, b, ln, w);
-  pair_load(B, Wb, min(b + 1, last), ln, w);
+  ring_load<NSP>(A, Wb, b, nsp, ln, w);
+  ring_load<NSP>(B, Wb, min(b + 1, last), nsp, ln, w);
   chain_rec(rA, L, b);
   for (int i = b; i < e; i += 2) {
     chain_rec(rB, L, min(i + 1, last));
     chain_step<0, 1, J>(i, A, rA, g, L, j_inner, ln, 0);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (ln == 0) __hip_atomic_store(&L.cprog, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    pair_load(A, Wb, min(i + 2, last), ln, w);
+    ring_load<NSP>(A, Wb, min(i + 2, last), nsp, ln, w);
     if (i + 1 < e) {
       chain_rec(rA, L, min(i + 2, last));
       chain_step<0, 1, J>(i + 1, B, rB, g, L, j_inner, ln, 0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (ln == 0) __hip_atomic_store(&L.cprog, i + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    pair_load(B, Wb, min(i + 3, last), ln, w);
+    ring_load<NSP>(B, Wb, min(i + 3, last), nsp, ln, w);
   }
 }
 
-// The applying half: the changes of contacts b .. e-1, solved by the other
+// The applying part: the changes of contacts b .. e-1, solved by another
 // wave, added to this wave's gaps in contact order.
-__device__ inline void pair_apply_one(int i, const double2 (&X)[1][PGS_BLK / 2], PgsLds &L, double (&g)[1][3]) {
+__device__ inline void ring_apply_one(int i, const double2 (&X)[1][PGS_BLK / 2], PgsLds &L, double (&g)[1][3]) {
   for (int spin = 0; __hip_atomic_load(&L.cprog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i; ++spin) {
-    if (spin == PAIR_SPIN) {
-      L.perr = 1;
+    if (spin == RING_SPIN) {
+      __hip_atomic_store(&L.perr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       break;
     }
+    if ((spin & 255) == 255 && __hip_atomic_load(&L.perr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+      break;   // another wave already gave up: no more waiting in this sweep
     __builtin_amdgcn_s_sleep(1);
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1237,131 +1242,50 @@ __device__ inline void pair_apply_one(int i, const double2 (&X)[1][PGS_BLK / 2],
 #pragma unroll
   for (int a = 0; a < 3; ++a) g[0][a] = fma(bb[3 * a + 2], d2, fma(bb[3 * a + 1], d1, fma(bb[3 * a], d0, g[0][a])));
 }
-__device__ inline void pair_apply(int b, int e, const double *__restrict__ Wb, PgsLds &L, int ln, int w,
+template <int NSP>
+__device__ inline void ring_apply(int b, int e, int nsp, const double *__restrict__ Wb, PgsLds &L, int ln, int w,
                                   double (&g)[1][3]) {
   if (b >= e) return;
   const int last = e - 1;
   double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
-  pair_load(A, Wb, b, ln, w);
-  pair_load(B, Wb, min(b + 1, last), ln, w);
+  ring_load<NSP>(A, Wb, b, nsp, ln, w);
+  ring_load<NSP>(B, Wb, min(b + 1, last), nsp, ln, w);
   for (int i = b; i < e; i += 2) {
-    pair_apply_one(i, A, L, g);
-    pair_load(A, Wb, min(i + 2, last), ln, w);
-    if (i + 1 < e) pair_apply_one(i + 1, B, L, g);
-    pair_load(B, Wb, min(i + 3, last), ln, w);
+    ring_apply_one(i, A, L, g);
+    ring_load<NSP>(A, Wb, min(i + 2, last), nsp, ln, w);
+    if (i + 1 < e) ring_apply_one(i + 1, B, L, g);
+    ring_load<NSP>(B, Wb, min(i + 3, last), nsp, ln, w);
   }
 }
 
-template <int J>
-__device__ __forceinline__ void chain_pair(int nS, const double *__restrict__ Wb, PgsLds &L, int j_inner, int w) {
-  const int ln = threadIdx.x & 63, c = 64 * w + ln;
+template <int J, int NSP>
+__device__ __forceinline__ void chain_ring(int nS, int nsp, const double *__restrict__ Wb, PgsLds &L, int j_inner,
+                                           int w) {
+  const int ln = threadIdx.x & 63, c = 64 * w + ln, R = (nS + 63) / 64;
   double g[1][3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) g[0][q] = c < nS ? L.gS[3 * c + q] : 0.0;
-  const int h = min(64, nS);
-  if (w == 0) {
-    pair_solve<J>(0, h, Wb, L, j_inner, ln, w, g);
-    pair_apply(h, nS, Wb, L, ln, w, g);
+  if constexpr (NSP == 128) {   // two waves: one block each
+    const int h = min(64, nS);
+    if (w == 0) {
+      ring_solve<J, NSP>(0, h, nsp, Wb, L, j_inner, ln, w, g);
+      ring_apply<NSP>(h, nS, nsp, Wb, L, ln, w, g);
+    } else {
+      ring_apply<NSP>(0, h, nsp, Wb, L, ln, w, g);
+      ring_solve<J, NSP>(h, nS, nsp, Wb, L, j_inner, ln, w, g);
+    }
   } else {
-    pair_apply(0, h, Wb, L, ln, w, g);
-    pair_solve<J>(h, nS, Wb, L, j_inner, ln, w, g);
+    for (int b = 0; b < R; ++b) {
+      const int lo = 64 * b, hi = min(lo + 64, nS);
+      if (b == w)
+        ring_solve<J, NSP>(lo, hi, nsp, Wb, L, j_inner, ln, w, g);
+      else
+        ring_apply<NSP>(lo, hi, nsp, Wb, L, ln, w, g);
+    }
   }
   if (c < nS) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[0][q];
-  }
-}
-
-// Sweep over a set of 129..512 contacts by Q = ceil(nS / 128) chain waves:
-// wave w keeps the gaps of contacts 128 w .. 128 w + 127 in two register
-// slots.  Per contact the owning wave publishes e_i through LDS, one block
-// barrier follows, then every chain wave runs the same local solve and
-// updates its own rows (the other waves only take the barriers).
-template <int J>
-__device__ __forceinline__ void chain_multi(int nS, int Q, const double *__restrict__ Wb, PgsLds &L, int j_inner) {
-  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const bool chain = w < Q;
-  const long colstride = (long)(128 * Q) * (PGS_BLK / 2);   // double2 per contact column (nsp = 128 Q)
-  double g[2][3];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int c = 128 * w + 64 * k + ln;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) g[k][q] = (chain && c < nS) ? L.gS[3 * c + q] : 0.0;
-  }
-  const int last = nS - 1;
-  // block (rows of contact c, columns of contact i) at double2 (i nsp + c) 5
-  const double2 *W2 = reinterpret_cast<const double2 *>(Wb) + (long)(128 * w + ln) * (PGS_BLK / 2);
-  auto load = [&](double2 (&X)[2][PGS_BLK / 2], int i) {
-    const double2 *base = W2 + (long)i * colstride;
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int j = 0; j < PGS_BLK / 2; ++j) X[k][j] = base[k * 64 * (PGS_BLK / 2) + j];
-  };
-  double2 A[2][PGS_BLK / 2], B[2][PGS_BLK / 2];
-  ChainRec rA, rB;
-  if (chain) {
-    load(A, 0);
-    load(B, min(1, last));
-    chain_rec(rA, L, 0);
-  }
-  auto step = [&](int i, const double2 (&X)[2][PGS_BLK / 2], const ChainRec &c) {
-    const int owner = i >> 7, k = (i >> 6) & 1, li = i & 63;
-    if (w == owner) {
-      const double e0 = readlane_f64(k ? g[1][0] : g[0][0], li);
-      const double e1 = readlane_f64(k ? g[1][1] : g[0][1], li);
-      const double e2 = readlane_f64(k ? g[1][2] : g[0][2], li);
-      if (ln == 0) {
-        L.ebuf[i & 1][0] = e0;
-        L.ebuf[i & 1][1] = e1;
-        L.ebuf[i & 1][2] = e2;
-      }
-    }
-    __syncthreads();
-    if (!chain) return;
-    double rc[19];
-#pragma unroll
-    for (int q = 0; q < 19; ++q) rc[q] = c[q];
-    const double lo0 = c[19], lo1 = c[20], lo2 = c[21];
-    double dd[3] = {L.ebuf[i & 1][0], L.ebuf[i & 1][1], L.ebuf[i & 1][2]};
-    const Local rs = local_solve_rec<J>(rc, dd, j_inner);
-    if (w == 0 && ln == 0) {
-      double *lp = L.rec + PGS_RW * i + 19;
-      lp[0] = rs.l[0];
-      lp[1] = rs.l[1];
-      lp[2] = rs.l[2];
-      L.stS[i] = (unsigned char)rs.st;
-    }
-    const double d0 = rs.l[0] - lo0, d1 = rs.l[1] - lo1, d2 = rs.l[2] - lo2;
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const double b[9] = {X[kk][0].x, X[kk][0].y, X[kk][1].x, X[kk][1].y, X[kk][2].x,
-                           X[kk][2].y, X[kk][3].x, X[kk][3].y, X[kk][4].x};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        g[kk][a] = fma(b[3 * a + 2], d2, fma(b[3 * a + 1], d1, fma(b[3 * a], d0, g[kk][a])));
-    }
-  };
-  for (int i = 0; i < nS; i += 2) {
-    if (chain) chain_rec(rB, L, min(i + 1, last));
-    step(i, A, rA);
-    if (chain) load(A, min(i + 2, last));
-    if (i + 1 < nS) {
-      if (chain) chain_rec(rA, L, min(i + 2, last));
-      step(i + 1, B, rB);
-    }
-    if (chain) load(B, min(i + 3, last));
-  }
-  if (chain) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int c = 128 * w + 64 * k + ln;
-      if (c < nS) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) L.gS[3 * c + q] = g[k][q];
-      }
-    }
   }
 }
 
@@ -1649,25 +1573,25 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
     }
     __syncthreads();
     if (nS > 0) {
-      if (nS <= 128) {
-        if (nsp == 64) {
-          if (wv == 0) {
-            if (j_inner == 8)
-              chain_wave<1, 8>(nS, Wss, L, j_inner);
-            else
-              chain_wave<1, 0>(nS, Wss, L, j_inner);
-          }
-        } else if (wv < 2) {
+      if (nS <= 64) {
+        if (wv == 0) {
           if (j_inner == 8)
-            chain_pair<8>(nS, Wss, L, j_inner, wv);
+            chain_wave<1, 8>(nS, Wss, L, j_inner);
           else
-            chain_pair<0>(nS, Wss, L, j_inner, wv);
+            chain_wave<1, 0>(nS, Wss, L, j_inner);
         }
-      } else {
+      } else if (nS <= 128) {
+        if (wv < 2) {
+          if (j_inner == 8)
+            chain_ring<8, 128>(nS, nsp, Wss, L, j_inner, wv);
+          else
+            chain_ring<0, 128>(nS, nsp, Wss, L, j_inner, wv);
+        }
+      } else if (wv < (nS + 63) / 64) {
         if (j_inner == 8)
-          chain_multi<8>(nS, (nS + 127) / 128, Wss, L, j_inner);
+          chain_ring<8, 0>(nS, nsp, Wss, L, j_inner, wv);
         else
-          chain_multi<0>(nS, (nS + 127) / 128, Wss, L, j_inner);
+          chain_ring<0, 0>(nS, nsp, Wss, L, j_inner, wv);
       }
     }
     __syncthreads();
@@ -1690,7 +1614,7 @@ __device__ __forceinline__ void pgs_active_body(PgsLds &L, int nc, const TW *__r
     if (tid == 0) {
       const double diff = sqrt(dpart), nl = sqrt(npart);
       eps = nl > 0.0 ? diff / nl : (diff == 0.0 ? 0.0 : INFINITY);
-      if (L.perr) eps = NAN;   // a two-wave sweep lost its count: stop and report eps = NaN
+      if (L.perr) eps = NAN;   // the ring sweep lost its count: stop and report eps = NaN
       L.stop = (eps <= tol || L.perr) ? 1 : 0;
       L.red[0] = bpart * (1.0 + 1e-12);
       L.settled = (L.zflag == 0 && L.red[0] < L.Rmin) ? 1 : 0;
