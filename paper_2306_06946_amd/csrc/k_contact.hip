@@ -1864,6 +1864,7 @@ struct PcaLds {
   int ulist[PGS_MAX_NC];
   unsigned char inS[PGS_MAX_NC];
   int nS, flag, stop, nu;
+  int cprog, perr;   // two-wave sweep: contacts done by the solving wave; a wait ran out
 };
 static_assert(sizeof(PcaLds) <= 160 * 1024, "per-constraint chain state must fit one CU's LDS");
 
@@ -2027,6 +2028,91 @@ __device__ __forceinline__ void pca_chain(int nS, const double *__restrict__ Wb,
   }
 }
 
+// A set of 65..128 contacts is swept by two waves as in chain_ring: wave w
+// keeps the proximities of contacts 64 w .. 64 w + 63, solves those
+// contacts while the other wave adds each published force change to its own
+// proximities, then applies the other half's changes.  The applying wave
+// takes the change as the published world force minus the force at the
+// sweep's start, so every proximity receives the same products in the same
+// order as in the one-wave sweep.
+template <int J>
+__device__ inline void pca_pair_solve(int b, int e, const double *__restrict__ Wb, PcaLds &L, int j_inner, int ln,
+                                      int w, double (&g)[1][3], const icr_obstacle &obs, double t0, double t1,
+                                      double h2) {
+  if (b >= e) return;
+  const int last = e - 1;
+  double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
+  PcaRec rA, rB;
+  ring_load<128>(A, Wb, b, 128, ln, w);
+  ring_load<128>(B, Wb, min(b + 1, last), 128, ln, w);
+  pca_rec(rA, L, b);
+  for (int i = b; i < e; i += 2) {
+    pca_rec(rB, L, min(i + 1, last));
+    pca_step<0, 1, J>(i, A, rA, g, L, j_inner, ln, obs, t0, t1, h2);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (ln == 0) __hip_atomic_store(&L.cprog, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    ring_load<128>(A, Wb, min(i + 2, last), 128, ln, w);
+    if (i + 1 < e) {
+      pca_rec(rA, L, min(i + 2, last));
+      pca_step<0, 1, J>(i + 1, B, rB, g, L, j_inner, ln, obs, t0, t1, h2);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (ln == 0) __hip_atomic_store(&L.cprog, i + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    ring_load<128>(B, Wb, min(i + 3, last), 128, ln, w);
+  }
+}
+__device__ inline void pca_pair_apply_one(int i, const double2 (&X)[1][PGS_BLK / 2], PcaLds &L, double (&g)[1][3]) {
+  for (int spin = 0; __hip_atomic_load(&L.cprog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i; ++spin) {
+    if (spin == RING_SPIN) {
+      __hip_atomic_store(&L.perr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      break;
+    }
+    if ((spin & 255) == 255 && __hip_atomic_load(&L.perr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+      break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const double *rp = L.rec + PCA_RW * i + 22;
+  const double d0 = rp[0] - L.f0[3 * i], d1 = rp[1] - L.f0[3 * i + 1], d2 = rp[2] - L.f0[3 * i + 2];
+  const double bb[9] = {X[0][0].x, X[0][0].y, X[0][1].x, X[0][1].y, X[0][2].x,
+                        X[0][2].y, X[0][3].x, X[0][3].y, X[0][4].x};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g[0][a] = fma(bb[3 * a + 2], d2, fma(bb[3 * a + 1], d1, fma(bb[3 * a], d0, g[0][a])));
+}
+__device__ inline void pca_pair_apply(int b, int e, const double *__restrict__ Wb, PcaLds &L, int ln, int w,
+                                      double (&g)[1][3]) {
+  if (b >= e) return;
+  const int last = e - 1;
+  double2 A[1][PGS_BLK / 2], B[1][PGS_BLK / 2];
+  ring_load<128>(A, Wb, b, 128, ln, w);
+  ring_load<128>(B, Wb, min(b + 1, last), 128, ln, w);
+  for (int i = b; i < e; i += 2) {
+    pca_pair_apply_one(i, A, L, g);
+    ring_load<128>(A, Wb, min(i + 2, last), 128, ln, w);
+    if (i + 1 < e) pca_pair_apply_one(i + 1, B, L, g);
+    ring_load<128>(B, Wb, min(i + 3, last), 128, ln, w);
+  }
+}
+template <int J>
+__device__ __forceinline__ void pca_pair(int nS, const double *__restrict__ Wb, PcaLds &L, int j_inner,
+                                         const icr_obstacle &obs, double t0, double t1, double h2, int w) {
+  const int ln = threadIdx.x & 63, c = 64 * w + ln, h = min(64, nS);
+  double g[1][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) g[0][q] = c < nS ? L.P[3 * c + q] : 0.0;
+  if (w == 0) {
+    pca_pair_solve<J>(0, h, Wb, L, j_inner, ln, w, g, obs, t0, t1, h2);
+    pca_pair_apply(h, nS, Wb, L, ln, w, g);
+  } else {
+    pca_pair_apply(0, h, Wb, L, ln, w, g);
+    pca_pair_solve<J>(h, nS, Wb, L, j_inner, ln, w, g, obs, t0, t1, h2);
+  }
+  if (c < nS) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) L.P[3 * c + q] = g[0][q];
+  }
+}
+
 // Exact proximity of a contact c outside S at its turn in the last sweep,
 // by one wave (all lanes return it): Pset_c + h^2 sum_{b in S} W_H,cb
 // (f_b^turn - f_b^set).
@@ -2074,6 +2160,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_pca(int nc, const StepCtx *__res
     ctl[0] = 0;
     ctl[1] = 0;
     L.stop = 0;
+    L.perr = 0;
   }
   __syncthreads();
   int sweep = 0, nS = 0, nsp = 64;
@@ -2168,19 +2255,22 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_pca(int nc, const StepCtx *__res
     if (tid == 0) {
       L.flag = 0;
       L.nu = 0;
+      L.cprog = 0;
     }
     __syncthreads();
-    if (nS > 0 && wv == 0) {
-      if (j_inner == 8) {
-        if (nsp == 64)
-          pca_chain<1, 8>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+    if (nS > 0) {
+      if (nsp == 64) {
+        if (wv == 0) {
+          if (j_inner == 8)
+            pca_chain<1, 8>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+          else
+            pca_chain<1, 0>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+        }
+      } else if (wv < 2) {
+        if (j_inner == 8)
+          pca_pair<8>(nS, Wss, L, j_inner, obs, t0, t1, h2, wv);
         else
-          pca_chain<2, 8>(nS, Wss, L, j_inner, obs, t0, t1, h2);
-      } else {
-        if (nsp == 64)
-          pca_chain<1, 0>(nS, Wss, L, j_inner, obs, t0, t1, h2);
-        else
-          pca_chain<2, 0>(nS, Wss, L, j_inner, obs, t0, t1, h2);
+          pca_pair<0>(nS, Wss, L, j_inner, obs, t0, t1, h2, wv);
       }
     }
     __syncthreads();
@@ -2202,7 +2292,8 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_pca(int nc, const StepCtx *__res
     if (tid == 0) {
       const double diff = sqrt(dpart), nf = sqrt(npart);
       eps = nf > 0.0 ? diff / nf : (diff == 0.0 ? 0.0 : INFINITY);
-      L.stop = (eps <= tol) ? 1 : 0;
+      if (L.perr) eps = NAN;   // the two-wave sweep lost its count: stop and report eps = NaN
+      L.stop = (eps <= tol || L.perr) ? 1 : 0;
       L.red[0] = bpart * (1.0 + 1e-12);
     }
     __syncthreads();
@@ -2230,7 +2321,7 @@ __global__ __launch_bounds__(PGS_NT) void k_pgs_pca(int nc, const StepCtx *__res
       }
     }
     __syncthreads();
-    if (L.flag) {
+    if (L.flag && !L.perr) {
       // a skipped contact was not a no-op: restart the sweep with a larger S
       for (int r = tid; r < 3 * nS; r += PGS_NT) f[3L * L.Sidx[r / 3] + r % 3] = L.f0[r];
       need_build = true;
